@@ -1,0 +1,668 @@
+/*
+ * CPU oracle: forward Monte Carlo with local estimation, and the surrogate
+ * gradient.  TEST INFRASTRUCTURE ONLY (see mcrt_oracle.h).  Plain C, FP64,
+ * single thread, no blocking and no reordering beyond the paper's steps.
+ *
+ * Paper: Holodovsky, Schechner, Levin, Levis, Aides, "In-situ
+ * multi-scattering tomography", arXiv 1512.02110.  Section, equation and
+ * step references below are to that paper.
+ *
+ * Readings where the paper is silent or garbled (each is listed in the
+ * design notes of the repository):
+ *  - Eq. (thetaHG) is used with the square on (1-g^2)/(1-g+2gu) restored.
+ *  - Uniforms: u = ((x >> 9) + 1/2) 2^-23 from one 32-bit Philox4x32-10 word,
+ *    an open interval, exact in FP32 and FP64.
+ *  - Photons enter through the top face only, uniformly (Sec. 2.1.2 step i);
+ *    all faces are open (step iii).
+ *  - Russian roulette (step v, "following Iwabuchi"): after w <- albedo*w,
+ *    if w < w_rr the photon survives with probability w/w_rr and then
+ *    carries w_rr.
+ *  - The local estimate (Eq. fle) is made at every collision with the
+ *    incoming direction and the weight before the albedo factor.
+ *  - The scattered direction is built on the orthonormal basis of Duff et al.
+ *    (JCGT 2017) around the incoming direction, then renormalised.
+ *  - Images are radiance per unit solar irradiance: the raw sum of local
+ *    estimates times mu0 * A_top / (N * Omega_p), Omega_p the pixel solid
+ *    angle.
+ *  - Gradient: the surrogate of Sec. 5.2 with the in-scatter field frozen.
+ *    For one local estimate C_e from a collision in voxel k_e,
+ *    dC_e/dbeta(m) = C_e (delta(m,k_e)/beta(k_e) - l_e(m)), the per-event
+ *    form of Eqs. (Jaco1, TcofJaco1, DivTc).
+ */
+#include "mcrt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): 10 rounds of two 32x32->64 multiplies with the */
+/* published multipliers, key bumped by the published Weyl constants.       */
+
+static void philox_round(uint32_t x[4], const uint32_t k[2])
+{
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x[1] ^ k[0];
+    uint32_t y2 = hi0 ^ x[3] ^ k[1];
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+}
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(x, k);
+    }
+    memcpy(out, x, sizeof(x));
+}
+
+double oracle_uniform(uint32_t x)
+{
+    return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+/* Draw leg `leg` of photon `pid`: counter (pid_lo, pid_hi, leg, 0), key = seed. */
+static void draw(uint64_t seed, uint64_t pid, uint32_t leg, double u[4])
+{
+    uint32_t ctr[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), leg, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    for (int i = 0; i < 4; ++i) u[i] = oracle_uniform(r[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Phase function, Eq. (Phg), and its inverse-transform sampling,           */
+/* Eq. (thetaHG) with the square restored.                                  */
+
+double oracle_hg_phase(double g, double c)
+{
+    double den = 1.0 + g * g - 2.0 * g * c;
+    return (1.0 - g * g) / (4.0 * ORC_PI * den * sqrt(den));
+}
+
+double oracle_hg_sample(double g, double u)
+{
+    double mu;
+    if (g == 0.0) {
+        mu = 2.0 * u - 1.0;
+    } else {
+        double s = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+        mu = (1.0 + g * g - s * s) / (2.0 * g);
+    }
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    return mu;
+}
+
+/* New direction at polar cosine mu and azimuth phi about w_in (step vi). */
+void oracle_scatter_direction(const double w[3], double mu, double phi, double out[3])
+{
+    double sign = copysign(1.0, w[2]);
+    double a = -1.0 / (sign + w[2]);
+    double b = w[0] * w[1] * a;
+    double b1[3] = {1.0 + sign * w[0] * w[0] * a, sign * b, -sign * w[0]};
+    double b2[3] = {b, sign + w[1] * w[1] * a, -w[1]};
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double cp = cos(phi), sp = sin(phi);
+    double n2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        out[i] = st * cp * b1[i] + st * sp * b2[i] + mu * w[i];
+        n2 += out[i] * out[i];
+    }
+    double inv = 1.0 / sqrt(n2);
+    for (int i = 0; i < 3; ++i) out[i] *= inv;
+}
+
+/* Solid angle of pixel (row, col): the rectangle [x1,x2] x [y1,y2] on the
+ * unit-focal plane subtends F(x2,y2)-F(x1,y2)-F(x2,y1)+F(x1,y1) with
+ * F(x,y) = atan(x y / sqrt(1 + x^2 + y^2)). */
+static double rect_F(double x, double y)
+{
+    return atan(x * y / sqrt(1.0 + x * x + y * y));
+}
+
+double oracle_pixel_solid_angle(const orc_camera* cam, int row, int col)
+{
+    double x1 = ((double)col - cam->cx) / cam->fx, x2 = ((double)col + 1.0 - cam->cx) / cam->fx;
+    double y1 = ((double)row - cam->cy) / cam->fy, y2 = ((double)row + 1.0 - cam->cy) / cam->fy;
+    return rect_F(x2, y2) - rect_F(x1, y2) - rect_F(x2, y1) + rect_F(x1, y1);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Voxel traversal (regular tracking): the voxel sequence of a ray and the  */
+/* length of the ray inside each voxel, so that tau = sum beta(m) l(m),     */
+/* Eq. (taoKtoc).                                                           */
+
+typedef struct {
+    int n[3];
+    double d[3];
+} geom;
+
+typedef struct {
+    double o[3], w[3];
+    int i[3], step[3];
+    double tmax[3];  /* ray parameter of the next face crossing on each axis */
+    double t;        /* ray parameter of the entry into the current voxel */
+} walker;
+
+static void walker_init(walker* wk, const geom* G, const double o[3], const double w[3], const int i[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        wk->o[a] = o[a];
+        wk->w[a] = w[a];
+        wk->i[a] = i[a];
+        if (w[a] > 0.0) {
+            wk->step[a] = 1;
+            wk->tmax[a] = ((double)(i[a] + 1) * G->d[a] - o[a]) / w[a];
+        } else if (w[a] < 0.0) {
+            wk->step[a] = -1;
+            wk->tmax[a] = ((double)i[a] * G->d[a] - o[a]) / w[a];
+        } else {
+            wk->step[a] = 0;
+            wk->tmax[a] = INFINITY;
+        }
+        if (wk->tmax[a] < 0.0) wk->tmax[a] = 0.0;
+    }
+    wk->t = 0.0;
+}
+
+/* Axis whose face is crossed next; ties go to the lowest axis. */
+static int walker_axis(const walker* wk)
+{
+    int a = 0;
+    if (wk->tmax[1] < wk->tmax[a]) a = 1;
+    if (wk->tmax[2] < wk->tmax[a]) a = 2;
+    return a;
+}
+
+enum { LEFT_NONE = -1 };
+
+/* Cross the face on axis a.  Returns LEFT_NONE while inside the domain,
+ * else the ORC_FATE_{TOP,BOTTOM,SIDE} of the face through which it left. */
+static int walker_cross(walker* wk, const geom* G, int a)
+{
+    wk->t = wk->tmax[a];
+    wk->i[a] += wk->step[a];
+    if (wk->i[a] < 0 || wk->i[a] >= G->n[a]) {
+        if (a == 2) return wk->step[a] > 0 ? ORC_FATE_TOP : ORC_FATE_BOTTOM;
+        return ORC_FATE_SIDE;
+    }
+    int face = wk->i[a] + (wk->step[a] > 0 ? 1 : 0);
+    wk->tmax[a] = ((double)face * G->d[a] - wk->o[a]) / wk->w[a];
+    return LEFT_NONE;
+}
+
+static int64_t vox_index(const geom* G, const int i[3])
+{
+    return (int64_t)i[0] + (int64_t)G->n[0] * ((int64_t)i[1] + (int64_t)G->n[1] * (int64_t)i[2]);
+}
+
+/* ------------------------------------------------------------------------ */
+
+enum { MODE_RENDER = 0, MODE_FROZEN = 1, MODE_GRAD = 2, MODE_TRACE = 3 };
+
+typedef struct {
+    geom G;
+    double L[3];
+    const double* beta_t;   /* extinction used to transport photons */
+    const double* beta_le;  /* extinction used by the local estimates */
+    int n_cams;
+    const orc_camera* cams;
+    int64_t* pix_off;       /* first pixel of each camera in the image vector */
+    int64_t n_pix;
+    const orc_params* prm;
+    double w_sun[3];
+    double* norm;           /* per-pixel mu0 A_top / (N Omega_p) */
+    int mode;
+    double* raw;            /* per-pixel sum of local estimates */
+    double* acc;            /* current photon's per-pixel sum (for images_m2) */
+    int64_t* touched;
+    int64_t n_touched, cap_touched;
+    double* m2;
+    const double* dl;
+    double* grad;
+    orc_stats st;
+    /* trace */
+    orc_path* path;
+    orc_event* ev;
+    int32_t* evpix;
+    uint32_t max_rec;
+    int32_t cur_events;
+    int64_t trace_slot;
+} ctx;
+
+/* Step (ii)-(iii): fly from X (in voxel vox) along w until the optical depth
+ * tau_star is reached, Eqs. (taurand, MCextinct), solved exactly voxel by
+ * voxel since beta is constant in a voxel.  Returns LEFT_NONE on a
+ * collision (X, vox updated) or the face through which the photon left
+ * (X set to the exit point). */
+static int free_flight(ctx* c, double X[3], int vox[3], const double w[3], double tau_star)
+{
+    walker wk;
+    walker_init(&wk, &c->G, X, w, vox);
+    double tau = 0.0;
+    for (;;) {
+        double b = c->beta_t[vox_index(&c->G, wk.i)];
+        c->st.vox_free++;
+        int a = walker_axis(&wk);
+        double seg = wk.tmax[a] - wk.t;
+        if (b > 0.0 && tau + b * seg >= tau_star) {
+            double tc = wk.t + (tau_star - tau) / b;
+            for (int q = 0; q < 3; ++q) {
+                X[q] = wk.o[q] + tc * wk.w[q];
+                vox[q] = wk.i[q];
+            }
+            return LEFT_NONE;
+        }
+        tau += b * seg;
+        int left = walker_cross(&wk, &c->G, a);
+        if (left != LEFT_NONE) {
+            for (int q = 0; q < 3; ++q) X[q] = wk.o[q] + wk.t * wk.w[q];
+            return left;
+        }
+    }
+}
+
+/* Optical depth from X (in voxel vox) along unit v over length r; the part
+ * of the segment outside the domain contributes nothing.  When grad_a is
+ * non-zero, also subtracts grad_a * l(m) from grad[m] for every voxel m. */
+static double connection_tau(ctx* c, const double* beta, const double X[3], const int vox[3],
+                             const double v[3], double r, double grad_a, int count)
+{
+    walker wk;
+    walker_init(&wk, &c->G, X, v, vox);
+    double tau = 0.0;
+    for (;;) {
+        int64_t k = vox_index(&c->G, wk.i);
+        if (count) c->st.vox_conn++;
+        int a = walker_axis(&wk);
+        int last = wk.tmax[a] >= r;
+        double tn = last ? r : wk.tmax[a];
+        double l = tn - wk.t;
+        tau += beta[k] * l;
+        if (grad_a != 0.0) c->grad[k] -= grad_a * l;
+        if (last) break;
+        if (walker_cross(&wk, &c->G, a) != LEFT_NONE) break;
+    }
+    return tau;
+}
+
+static void tally(ctx* c, int64_t p, double C)
+{
+    c->raw[p] += C;
+    if (c->m2) {
+        if (c->acc[p] == 0.0) {
+            if (c->n_touched == c->cap_touched) {
+                c->cap_touched = c->cap_touched ? 2 * c->cap_touched : 1024;
+                c->touched = (int64_t*)realloc(c->touched, (size_t)c->cap_touched * sizeof(int64_t));
+            }
+            c->touched[c->n_touched++] = p;
+        }
+        c->acc[p] += C;
+    }
+}
+
+/* Sec. 2.1.3, Eq. (fle): at a collision at X in voxel vox, with incoming
+ * direction w and packet intensity I_s = weight, add
+ * albedo I_s P(angle(w, X->X_c)) exp(-tau(X->X_c)) / |X_c - X|^2 to the pixel
+ * of every camera that sees X. */
+static void local_estimates(ctx* c, const double X[3], const int vox[3], const double w[3],
+                            double weight)
+{
+    const orc_params* P = c->prm;
+    int64_t ke = vox_index(&c->G, vox);
+    for (int ci = 0; ci < c->n_cams; ++ci) {
+        const orc_camera* cam = &c->cams[ci];
+        if (c->mode == MODE_TRACE && c->evpix && c->cur_events <= (int32_t)c->max_rec)
+            c->evpix[(c->trace_slot + c->cur_events - 1) * c->n_cams + ci] = -1;
+        double dX[3] = {X[0] - cam->pos[0], X[1] - cam->pos[1], X[2] - cam->pos[2]};
+        double q[3];
+        for (int i = 0; i < 3; ++i)
+            q[i] = cam->R[3 * i] * dX[0] + cam->R[3 * i + 1] * dX[1] + cam->R[3 * i + 2] * dX[2];
+        if (!(q[2] > 0.0)) continue;
+        double u = cam->fx * q[0] / q[2] + cam->cx;
+        double v = cam->fy * q[1] / q[2] + cam->cy;
+        if (!(u >= 0.0 && u < (double)cam->width && v >= 0.0 && v < (double)cam->height)) continue;
+        int col = (int)floor(u), row = (int)floor(v);
+        double V[3] = {-dX[0], -dX[1], -dX[2]};
+        double r2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+        if (r2 < 1e-12) continue;
+        double r = sqrt(r2);
+        double vh[3] = {V[0] / r, V[1] / r, V[2] / r};
+        double cosang = w[0] * vh[0] + w[1] * vh[1] + w[2] * vh[2];
+        int64_t p = c->pix_off[ci] + (int64_t)row * cam->width + col;
+        c->st.le_jobs++;
+        if (c->mode == MODE_TRACE) {
+            if (c->evpix && c->cur_events <= (int32_t)c->max_rec)
+                c->evpix[(c->trace_slot + c->cur_events - 1) * c->n_cams + ci] = row * cam->width + col;
+            continue;
+        }
+        double tau = connection_tau(c, c->beta_le, X, vox, vh, r, 0.0, 1);
+        double C = P->albedo * weight * oracle_hg_phase(P->g, cosang) * exp(-tau) / r2;
+        if (c->mode == MODE_FROZEN) C *= c->beta_le[ke] / c->beta_t[ke];
+        if (c->mode == MODE_GRAD) {
+            double a = c->dl[p] * c->norm[p] * C;
+            if (a != 0.0) {
+                c->grad[ke] += a / c->beta_t[ke];
+                connection_tau(c, c->beta_le, X, vox, vh, r, a, 0);
+            }
+        } else {
+            tally(c, p, C);
+        }
+    }
+}
+
+/* The photon life cycle of Sec. 2.1.2, steps (i)-(vi). */
+static int trace_photon(ctx* c, uint64_t pid)
+{
+    const orc_params* P = c->prm;
+    double u[4];
+    /* (i) launch at a uniform point of the top of the domain, along w_sun */
+    draw(P->seed, pid, 0u, u);
+    double X[3] = {u[0] * c->L[0], u[1] * c->L[1], c->L[2]};
+    int vox[3];
+    for (int a = 0; a < 2; ++a) {
+        int i = (int)floor(X[a] / c->G.d[a]);
+        vox[a] = i < c->G.n[a] - 1 ? i : c->G.n[a] - 1;
+    }
+    vox[2] = c->G.n[2] - 1;
+    double w[3] = {c->w_sun[0], c->w_sun[1], c->w_sun[2]};
+    double weight = 1.0;
+    double tau_star = -log(1.0 - u[2]); /* Eq. (taurand) */
+    uint32_t s = 0;
+    for (;;) {
+        /* (ii)-(iii) */
+        int left = free_flight(c, X, vox, w, tau_star);
+        if (left != LEFT_NONE) {
+            if (left == ORC_FATE_TOP) c->st.esc_top++;
+            else if (left == ORC_FATE_BOTTOM) c->st.esc_bottom++;
+            else c->st.esc_side++;
+            if (c->path) {
+                for (int q = 0; q < 3; ++q) {
+                    c->path->exit_pos[q] = X[q];
+                    c->path->exit_dir[q] = w[q];
+                }
+                c->path->exit_w = weight;
+            }
+            return left;
+        }
+        ++s;
+        c->st.events++;
+        c->cur_events = (int32_t)s;
+        if (c->mode == MODE_TRACE && s <= c->max_rec) {
+            orc_event* e = &c->ev[c->trace_slot + s - 1];
+            e->x = X[0];
+            e->y = X[1];
+            e->z = X[2];
+            e->w = weight;
+            e->voxel = (int32_t)vox_index(&c->G, vox);
+            e->pad_ = 0;
+        }
+        /* Sec. 2.1.3: local estimate with the incoming ray and I_s */
+        local_estimates(c, X, vox, w, weight);
+        if (s >= P->max_events) {
+            c->st.capped++;
+            return ORC_FATE_CAP;
+        }
+        draw(P->seed, pid, s, u);
+        /* (v) albedo and Russian roulette */
+        weight *= P->albedo;
+        if (weight < P->rr_weight) {
+            if (u[2] < weight / P->rr_weight) {
+                weight = P->rr_weight;
+            } else {
+                c->st.rr_killed++;
+                return ORC_FATE_RR;
+            }
+        }
+        /* (vi) scattering angle, Eq. (thetaHG), and uniform azimuth */
+        double mu = oracle_hg_sample(P->g, u[0]);
+        double phi = 2.0 * ORC_PI * u[1];
+        double wn[3];
+        oracle_scatter_direction(w, mu, phi, wn);
+        w[0] = wn[0];
+        w[1] = wn[1];
+        w[2] = wn[2];
+        tau_star = -log(1.0 - u[3]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+
+static int finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+static int validate(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                    const orc_params* P)
+{
+    if (!grid || !beta || !cams || !P) return ORC_ERR_INVALID_ARG;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return ORC_ERR_INVALID_ARG;
+    if (!finite_pos(grid->dx) || !finite_pos(grid->dy) || !finite_pos(grid->dz)) return ORC_ERR_INVALID_ARG;
+    if ((int64_t)grid->nx * grid->ny * grid->nz > 2147483647LL) return ORC_ERR_INVALID_ARG;
+    if (n_cams < 1) return ORC_ERR_INVALID_ARG;
+    for (int i = 0; i < n_cams; ++i) {
+        const orc_camera* c = &cams[i];
+        if (c->width < 1 || c->height < 1) return ORC_ERR_INVALID_ARG;
+        if (!finite_pos(c->fx) || !finite_pos(c->fy) || !isfinite(c->cx) || !isfinite(c->cy))
+            return ORC_ERR_INVALID_ARG;
+        for (int j = 0; j < 3; ++j) if (!isfinite(c->pos[j])) return ORC_ERR_INVALID_ARG;
+        for (int j = 0; j < 9; ++j) if (!isfinite(c->R[j])) return ORC_ERR_INVALID_ARG;
+    }
+    if (!(P->albedo >= 0.0 && P->albedo <= 1.0)) return ORC_ERR_INVALID_ARG;
+    if (!(P->g > -1.0 && P->g < 1.0)) return ORC_ERR_INVALID_ARG;
+    if (!(P->sun_zenith >= 0.0 && P->sun_zenith < 0.5 * ORC_PI)) return ORC_ERR_INVALID_ARG;
+    if (!isfinite(P->sun_azimuth)) return ORC_ERR_INVALID_ARG;
+    if (!(P->rr_weight > 0.0 && P->rr_weight <= 1.0)) return ORC_ERR_INVALID_ARG;
+    if (P->max_events < 1) return ORC_ERR_INVALID_ARG;
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    for (int64_t k = 0; k < nv; ++k)
+        if (!(beta[k] >= 0.0) || !isfinite(beta[k])) return ORC_ERR_INVALID_ARG;
+    return ORC_OK;
+}
+
+static void ctx_setup(ctx* c, const orc_grid* grid, const double* beta_t, const double* beta_le,
+                      int n_cams, const orc_camera* cams, const orc_params* P, int mode)
+{
+    memset(c, 0, sizeof(*c));
+    c->G.n[0] = grid->nx;
+    c->G.n[1] = grid->ny;
+    c->G.n[2] = grid->nz;
+    c->G.d[0] = grid->dx;
+    c->G.d[1] = grid->dy;
+    c->G.d[2] = grid->dz;
+    for (int a = 0; a < 3; ++a) c->L[a] = c->G.n[a] * c->G.d[a];
+    c->beta_t = beta_t;
+    c->beta_le = beta_le;
+    c->n_cams = n_cams;
+    c->cams = cams;
+    c->prm = P;
+    c->mode = mode;
+    /* direction towards the sun s = (sin z cos a, sin z sin a, cos z); photons travel -s */
+    c->w_sun[0] = -sin(P->sun_zenith) * cos(P->sun_azimuth);
+    c->w_sun[1] = -sin(P->sun_zenith) * sin(P->sun_azimuth);
+    c->w_sun[2] = -cos(P->sun_zenith);
+    c->pix_off = (int64_t*)malloc((size_t)(n_cams + 1) * sizeof(int64_t));
+    c->pix_off[0] = 0;
+    for (int i = 0; i < n_cams; ++i)
+        c->pix_off[i + 1] = c->pix_off[i] + (int64_t)cams[i].width * cams[i].height;
+    c->n_pix = c->pix_off[n_cams];
+    /* radiance normalisation mu0 * A_top / (N * Omega_p) with unit irradiance */
+    uint64_t N = P->n_photons_norm ? P->n_photons_norm : P->n_photons;
+    double base = N ? cos(P->sun_zenith) * c->L[0] * c->L[1] / (double)N : 0.0;
+    c->norm = (double*)malloc((size_t)c->n_pix * sizeof(double));
+    for (int i = 0; i < n_cams; ++i)
+        for (int row = 0; row < cams[i].height; ++row)
+            for (int col = 0; col < cams[i].width; ++col)
+                c->norm[c->pix_off[i] + (int64_t)row * cams[i].width + col] =
+                    base / oracle_pixel_solid_angle(&cams[i], row, col);
+}
+
+static void ctx_free(ctx* c)
+{
+    free(c->pix_off);
+    free(c->norm);
+    free(c->acc);
+    free(c->touched);
+}
+
+static void run_photons(ctx* c)
+{
+    const orc_params* P = c->prm;
+    for (uint64_t n = 0; n < P->n_photons; ++n) {
+        trace_photon(c, P->photon_offset + n);
+        c->st.photons++;
+        if (c->m2) {
+            for (int64_t t = 0; t < c->n_touched; ++t) {
+                int64_t p = c->touched[t];
+                double y = c->acc[p] * c->norm[p];
+                c->m2[p] += y * y;
+                c->acc[p] = 0.0;
+            }
+            c->n_touched = 0;
+        }
+    }
+}
+
+static int render_common(const orc_grid* grid, const double* beta_t, const double* beta_le,
+                         int n_cams, const orc_camera* cams, const orc_params* P,
+                         double* images, double* images_m2, orc_stats* stats, int mode)
+{
+    int err = validate(grid, beta_t, n_cams, cams, P);
+    if (err) return err;
+    if (beta_le != beta_t && (err = validate(grid, beta_le, n_cams, cams, P))) return err;
+    if (!images) return ORC_ERR_INVALID_ARG;
+    ctx c;
+    ctx_setup(&c, grid, beta_t, beta_le, n_cams, cams, P, mode);
+    c.raw = images;
+    memset(images, 0, (size_t)c.n_pix * sizeof(double));
+    if (images_m2) {
+        c.m2 = images_m2;
+        memset(images_m2, 0, (size_t)c.n_pix * sizeof(double));
+        c.acc = (double*)calloc((size_t)c.n_pix, sizeof(double));
+    }
+    run_photons(&c);
+    for (int64_t p = 0; p < c.n_pix; ++p) images[p] *= c.norm[p];
+    if (stats) *stats = c.st;
+    ctx_free(&c);
+    return ORC_OK;
+}
+
+int oracle_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                  const orc_params* P, double* images, double* images_m2, orc_stats* stats)
+{
+    return render_common(grid, beta, beta, n_cams, cams, P, images, images_m2, stats, MODE_RENDER);
+}
+
+int oracle_render_frozen(const orc_grid* grid, const double* beta_sample, const double* beta_eval,
+                         int n_cams, const orc_camera* cams, const orc_params* P,
+                         double* images, orc_stats* stats)
+{
+    return render_common(grid, beta_sample, beta_eval, n_cams, cams, P, images, NULL, stats,
+                         MODE_FROZEN);
+}
+
+int oracle_grad_beta(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                     const orc_params* P, const double* dl, double* grad, orc_stats* stats)
+{
+    int err = validate(grid, beta, n_cams, cams, P);
+    if (err) return err;
+    if (!dl || !grad) return ORC_ERR_INVALID_ARG;
+    ctx c;
+    ctx_setup(&c, grid, beta, beta, n_cams, cams, P, MODE_GRAD);
+    c.dl = dl;
+    c.grad = grad;
+    memset(grad, 0, (size_t)grid->nx * grid->ny * grid->nz * sizeof(double));
+    run_photons(&c);
+    if (stats) *stats = c.st;
+    ctx_free(&c);
+    return ORC_OK;
+}
+
+int oracle_trace_paths(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                       const orc_params* P, uint64_t first_pid, uint32_t count, uint32_t max_rec,
+                       orc_event* events, int32_t* pix, orc_path* paths)
+{
+    int err = validate(grid, beta, n_cams, cams, P);
+    if (err) return err;
+    if ((count > 0 && max_rec > 0 && !events) || (count > 0 && !paths)) return ORC_ERR_INVALID_ARG;
+    ctx c;
+    ctx_setup(&c, grid, beta, beta, n_cams, cams, P, MODE_TRACE);
+    c.ev = events;
+    c.evpix = pix;
+    c.max_rec = max_rec;
+    for (uint32_t n = 0; n < count; ++n) {
+        c.trace_slot = (int64_t)n * max_rec;
+        c.cur_events = 0;
+        memset(&paths[n], 0, sizeof(paths[n]));
+        c.path = &paths[n];
+        uint64_t before = c.st.events;
+        int fate = trace_photon(&c, first_pid + n);
+        paths[n].n_events = (int32_t)(c.st.events - before);
+        paths[n].fate = fate;
+    }
+    ctx_free(&c);
+    return ORC_OK;
+}
+
+double oracle_optical_depth(const orc_grid* grid, const double* beta, const double p0[3],
+                            const double p1[3], int64_t* nvox)
+{
+    ctx c;
+    orc_params P;
+    memset(&P, 0, sizeof(P));
+    memset(&c, 0, sizeof(c));
+    c.G.n[0] = grid->nx;
+    c.G.n[1] = grid->ny;
+    c.G.n[2] = grid->nz;
+    c.G.d[0] = grid->dx;
+    c.G.d[1] = grid->dy;
+    c.G.d[2] = grid->dz;
+    for (int a = 0; a < 3; ++a) c.L[a] = c.G.n[a] * c.G.d[a];
+    double D[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    double len = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    if (nvox) *nvox = 0;
+    if (!(len > 0.0)) return 0.0;
+    double v[3] = {D[0] / len, D[1] / len, D[2] / len};
+    /* clip the segment to the domain (slab method) */
+    double t0 = 0.0, t1 = len;
+    for (int a = 0; a < 3; ++a) {
+        if (v[a] == 0.0) {
+            if (p0[a] < 0.0 || p0[a] > c.L[a]) return 0.0;
+            continue;
+        }
+        double ta = (0.0 - p0[a]) / v[a], tb = (c.L[a] - p0[a]) / v[a];
+        if (ta > tb) { double tmp = ta; ta = tb; tb = tmp; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    if (!(t1 > t0)) return 0.0;
+    double X[3];
+    int vox[3];
+    for (int a = 0; a < 3; ++a) {
+        X[a] = p0[a] + t0 * v[a];
+        /* the voxel entered in the direction of travel */
+        double f = X[a] / c.G.d[a];
+        int i = (int)floor(f);
+        if (v[a] < 0.0 && f == floor(f)) i -= 1;
+        if (i < 0) i = 0;
+        if (i > c.G.n[a] - 1) i = c.G.n[a] - 1;
+        vox[a] = i;
+    }
+    double tau = connection_tau(&c, beta, X, vox, v, t1 - t0, 0.0, 1);
+    if (nvox) *nvox = (int64_t)c.st.vox_conn;
+    return tau;
+}
