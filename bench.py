@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+Workload (default): 64^3 voxels of 0.02 km with a thresholded fractal cloud
+field (max beta 50 km^-1), 9 in-situ cameras of 128x128 px (70 deg FOV) on a
+3x3 ground lattice, albedo 0.99, g 0.85, sun zenith 45 deg, 1e8 photons per
+render; FP32 transport with FP64 tallies.
+
+One step = the whole hot path on one photon batch: the forward render
+(launch, free flights, local estimates to all cameras, albedo/roulette,
+scattering, normalisation) followed by the adjoint replay that scatters
+dL/dbeta for an L2 image loss.  Each step uses its own seed.
+
+Printed: one JSON line with the forward scattering-event rate (value), the
+adjoint cost ratio, the FP32-vs-FP64 transport comparison, the roofline of
+the transport kernel and the CPU oracle baseline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32, dense
+PEAK_HBM_GBPS = 8000.0
+
+
+def _cpu_worker(args):
+    cfg, n, offset = args
+    from oracle import oracle as O
+    from paper_1512_02110_amd import scenes
+    s = scenes.CONFIGS[cfg](n_photons=n)
+    t0 = time.perf_counter()
+    _, st = O.render(s, n_photons=n, photon_offset=offset)
+    return st["events"], time.perf_counter() - t0
+
+
+def cpu_baseline(cfg, per_proc, procs):
+    """The oracle as it stands, P independent processes over disjoint photon
+    ranges (one thread each)."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    from oracle import oracle as O
+    O.lib()  # build if needed, before the workers start
+    jobs = [(cfg, per_proc, i * per_proc) for i in range(procs)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_cpu_worker, jobs))
+    wall = time.perf_counter() - t0
+    events = sum(r[0] for r in res)
+    cpu_s = sum(r[1] for r in res)
+    return {"value": events / wall, "unit": "scattering events/s", "cores": procs, "kind": "oracle",
+            "sample": f"{cfg} workload, photon ids 0..{procs * per_proc - 1} split over {procs} "
+                      f"single-threaded processes ({per_proc} photons each), FP64",
+            "events": events, "wall_s": round(wall, 3), "cpu_s": round(cpu_s, 3),
+            "per_core": events / cpu_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--photons", type=int, default=None)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-photons", type=int, default=60000, help="photons per CPU process")
+    ap.add_argument("--cpu-procs", type=int, default=None)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(photon ranges would shard with one FP64 all-reduce of the images; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1512_02110_amd import scenes
+    make = scenes.CONFIGS[args.config]
+    s = make() if args.photons is None else make(n_photons=args.photons)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(args.config, args.cpu_photons, procs)
+        print(f"[bench] cpu baseline: {cpu['value']:.3e} events/s on {procs} processes", flush=True)
+
+    import numpy as np
+    import torch
+    from paper_1512_02110_amd import mcrt as M
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    M.load_library()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    beta32 = M.beta_tensor(s, "fp32")
+    # a 'measured' image for the L2 loss: a different seed on a perturbed field
+    meas, _ = M.mc_render(s, M.beta_tensor(s, "fp32", beta=s.beta * 0.9), seed=99,
+                          n_photons=min(s.n_photons, 10_000_000))
+
+    def step(seed):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        img, st = M.mc_render(s, beta32, seed=seed, stats=True)
+        e1.record(stream)
+        ast = None
+        if not args.no_adjoint:
+            dl = 2.0 * (img - meas)
+            _, ast = M.mc_grad_beta(s, beta32, dl, seed=seed, stats=True)
+        e2.record(stream)
+        return img, st, ast, (e0, e1, e2)
+
+    for w in range(args.warmup):
+        step(500 + w)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    recs = [step(1000 + k) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    fwd_ms = [r[3][0].elapsed_time(r[3][1]) for r in recs]
+    adj_ms = [r[3][1].elapsed_time(r[3][2]) for r in recs]
+    events = sum(r[1]["events"] for r in recs)
+    st = {k: sum(r[1][k] for r in recs) for k in recs[0][1]}
+    fwd_s = sum(fwd_ms) / 1e3
+    value = events / fwd_s
+
+    # roofline of the transport kernel (one launch per render): algorithmic
+    # work per scattering event, counted from the launch's own statistics
+    flops = (10.0 * (st["vox_free"] + st["vox_conn"]) + 60.0 * st["le_jobs"] + 150.0 * st["events"])
+    gbytes = 4.0 * (st["vox_free"] + st["vox_conn"]) + 16.0 * st["le_jobs"]
+    achieved_tflops = flops / fwd_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": None,
+                "kernel": "k_transport<float, render, f64 tally>",
+                "kernel_ms_avg": round(sum(fwd_ms) / len(fwd_ms), 3),
+                "gather_GBps": round(gbytes / fwd_s / 1e9, 1),
+                "voxel_steps_per_s": (st["vox_free"] + st["vox_conn"]) / fwd_s}
+
+    out = {
+        "metric": "scattering events/s fwd; fwd+adjoint time vs fwd, FP32 vs FP64 at <=1e-4 error",
+        "value": value,
+        "unit": "scattering events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {s.nx}x{s.ny}x{s.nz} voxels of {s.dx} km, "
+                               f"{s.n_cams} cameras {s.cameras[0].width}x{s.cameras[0].height}, "
+                               f"{s.n_photons:.0e} photons/render, FP32 transport + FP64 tallies",
+                   "photons": s.n_photons, "n_cams": s.n_cams},
+        "fwd_ms": round(sum(fwd_ms) / len(fwd_ms), 3),
+        "events_per_render": events // args.steps,
+        "stats_per_render": {k: v // args.steps for k, v in st.items()},
+        "roofline": roofline,
+    }
+    if not args.no_adjoint:
+        out["adj_ms"] = round(sum(adj_ms) / len(adj_ms), 3)
+        out["fwd_plus_adj_over_fwd"] = round((sum(fwd_ms) + sum(adj_ms)) / sum(fwd_ms), 4)
+
+    if not args.no_fp64:
+        beta64 = M.beta_tensor(s, "fp64")
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        img64, st64 = M.mc_render(s, beta64, transport="fp64", seed=1000, stats=True)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        t64 = a0.elapsed_time(a1)
+        # error bars of the same FP64 render (second moments, untimed)
+        _, m2_64, _ = M.mc_render_moments(s, beta64, transport="fp64", seed=1000, stats=False)
+        i32 = recs[0][0].cpu().numpy()
+        i64 = img64.cpu().numpy()
+        sig = np.sqrt(np.maximum(m2_64.cpu().numpy() - i64 ** 2 / s.n_photons, 0.0))
+        diff = np.abs(i32 - i64)
+        nz = np.abs(i64) > 0
+        rel = diff[nz] / np.abs(i64)[nz]
+        ok = diff <= np.maximum(1e-4 * np.abs(i64), 3 * sig)
+        out["fp64"] = {"fwd_ms": round(t64, 3), "events_per_s": st64["events"] / (t64 / 1e3),
+                       "speedup_fp32_over_fp64": round(t64 / fwd_ms[0], 3),
+                       "frac_pixels_within_max_1e-4_rel_3sigma": float(ok.mean()),
+                       "frac_pixels_within_1e-4_rel": float((rel <= 1e-4).mean()) if rel.size else 1.0,
+                       "pixel_rel_err_median": float(np.median(rel)) if rel.size else 0.0,
+                       "pixel_rel_err_max": float(rel.max()) if rel.size else 0.0,
+                       "image_rel_l1": float(diff.sum() / np.abs(i64).sum()),
+                       "events_fp32_minus_fp64": int(recs[0][1]["events"] - st64["events"])}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * mcrt.h - C ABI of the MI355X (gfx950) Monte Carlo renderer for in-situ
+ * multi-scattering tomography.
+ *
+ * Method: Holodovsky, Schechner, Levin, Levis, Aides, "In-situ
+ * multi-scattering tomography", arXiv 1512.02110.
+ *   - Forward Monte Carlo (FMC), Sec. 2.1.2 steps (i)-(vi): photons enter at
+ *     the top of the domain along the sun direction, fly free paths drawn by
+ *     inverse transform (Eqs. Ftau, taurand, MCextinct) through a voxel grid
+ *     of piecewise-constant extinction (Sec. 3), lose albedo at every
+ *     collision with Russian roulette below a weight threshold, and scatter
+ *     with the Henyey-Greenstein phase function (Eqs. Phg, thetaHG).
+ *   - Local estimation (Sec. 2.1.3, Eq. fle): at every collision, every
+ *     camera that sees the collision point receives
+ *     albedo * I_s * P(angle) * exp(-tau(X_s -> X_c)) / |X_c - X_s|^2 in the
+ *     pixel hit by the connecting ray; tau is the optical depth of that ray
+ *     (Eqs. tau, beer-lambert, tc).
+ *   - Surrogate gradient (Sec. 5.2, Eqs. Jaco1, TcofJaco1, DivTc): with the
+ *     in-scatter field frozen at the events of the render, a local estimate
+ *     C_e from a collision in voxel k_e has
+ *     dC_e/dbeta(m) = C_e (delta(m, k_e) / beta(k_e) - l_e(m)),
+ *     l_e(m) the length of the connecting ray inside voxel m.
+ *
+ * Conventions for every entry point:
+ *   - Structs (grid, cameras, params, stats) are HOST memory and are read (or
+ *     written, for stats) before the call returns.
+ *   - Array arguments (beta, images, dl_dimages, grad_beta, trace buffers)
+ *     are DEVICE pointers on the current HIP device, owned by the caller.
+ *     The library never frees or keeps them.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the legacy
+ *     default stream).  The call returns without waiting unless `stats` is
+ *     non-NULL, in which case it waits for the stream and fills *stats.
+ *   - The library allocates its own small scratch (counters, the camera
+ *     table, per-pixel weights) stream-ordered on `hip_stream` and releases
+ *     it stream-ordered before returning.
+ *   - Return value: MC_OK (0) or a negative MC_ERR_* code; the library never
+ *     prints or aborts.  On an argument error nothing is enqueued.  On
+ *     MC_ERR_HIP the contents of output arrays are unspecified.
+ *   - beta must be finite and >= 0 (a negative or NaN value yields
+ *     meaningless images but every kernel still terminates).
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed
+ *     and counter (photon id lo, photon id hi, leg, 0); leg 0 launches the
+ *     photon (uniforms: x, y, free path), leg s >= 1 follows collision s
+ *     (uniforms: polar, azimuth, roulette, free path).  A uniform is
+ *     ((word >> 9) + 1/2) * 2^-23.  The same (seed, photon id) gives the same
+ *     photon on every run, device and precision, up to rounding.
+ */
+#ifndef MCRT_H
+#define MCRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MC_OK = 0,
+    MC_ERR_INVALID_ARG = -1,   /* an argument is out of range or a pointer is missing */
+    MC_ERR_NO_DEVICE = -2,     /* no HIP device is visible */
+    MC_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+    MC_ERR_OUT_OF_MEMORY = -4  /* scratch allocation failed */
+};
+
+/* Transport precision: positions, directions, traversal and free-path
+ * optical depth.  Connection-ray optical depths and all tallies are FP64 in
+ * both. */
+enum { MC_FP32 = 0, MC_FP64 = 1 };
+
+/* Tally accumulation: FP64 atomics, or FP32 sum + FP32 compensation term
+ * (error-free transformation of every atomic add), reduced to FP64 at the
+ * end. */
+enum { MC_TALLY_F64 = 0, MC_TALLY_KAHAN32 = 1 };
+
+/* Voxel grid (Sec. 3): domain [0, nx*dx] x [0, ny*dy] x [0, nz*dz] in km, z up.
+ * Voxel k = ix + nx*(iy + ny*iz) (x fastest), beta(k) in km^-1, constant
+ * inside the voxel.  1 <= nx, ny <= 2048, 1 <= nz <= 1024, nx*ny*nz < 2^31,
+ * d* > 0. */
+typedef struct mc_grid {
+    int32_t nx, ny, nz, pad_;
+    double dx, dy, dz;
+} mc_grid;
+
+/* Pinhole camera c (Sec. 2.1, "center of projection X_c"; the cone of pixel
+ * p is the set of directions that project into it).  A point X maps to
+ * q = R (X - pos) (R row-major, rows = camera x-right, y-down, z-forward),
+ * column u = fx qx/qz + cx and row v = fy qy/qz + cy; it is seen when qz > 0
+ * and 0 <= u < width, 0 <= v < height, in pixel (floor v, floor u).
+ * fx, fy > 0; width, height >= 1. */
+typedef struct mc_camera {
+    double pos[3];
+    double R[9];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+} mc_camera;
+
+typedef struct mc_params {
+    double albedo;            /* single-scattering albedo, 0 <= albedo <= 1 */
+    double g;                 /* HG asymmetry, -1 < g < 1 */
+    double sun_zenith;        /* rad, 0 <= . < pi/2: zenith of the direction TO the sun */
+    double sun_azimuth;       /* rad, from +x towards +y; photons travel along -s */
+    double rr_weight;         /* Russian-roulette threshold weight, 0 < . <= 1 (0.1 typical) */
+    uint64_t n_photons;       /* photons traced: ids photon_offset .. photon_offset + n_photons - 1 */
+    uint64_t seed;            /* Philox key */
+    uint64_t photon_offset;   /* first photon id */
+    uint64_t n_photons_norm;  /* N in the image normalisation; 0 means n_photons.  Set it to
+                                 the total of all shards when photon ranges are split. */
+    uint32_t max_events;      /* collisions after which a photon is stopped and counted as
+                                 capped, >= 1 */
+    int32_t transport;        /* MC_FP32 or MC_FP64 */
+    int32_t tally;            /* MC_TALLY_F64 or MC_TALLY_KAHAN32 */
+    int32_t pad_;
+} mc_params;
+
+/* Counters of one call (all photons of the call). */
+typedef struct mc_stats {
+    uint64_t photons;     /* photons traced */
+    uint64_t events;      /* collisions (scattering events), including a capped one */
+    uint64_t le_jobs;     /* local estimates made (camera sees the collision) */
+    uint64_t vox_free;    /* voxels visited by free flights */
+    uint64_t vox_conn;    /* voxels visited by connection rays (one walk per local estimate) */
+    uint64_t esc_top, esc_bottom, esc_side;  /* photons that left through each face */
+    uint64_t rr_killed;   /* photons ended by Russian roulette */
+    uint64_t capped;      /* photons stopped at max_events */
+} mc_stats;
+
+/* Forward render (FMC + local estimation).
+ * beta: device array of nx*ny*nz values, float for MC_FP32 transport and
+ *   double for MC_FP64.
+ * images: device array of sum_c width_c*height_c doubles, [camera][row][col],
+ *   overwritten with radiance per unit solar irradiance: the sum of local
+ *   estimates of a pixel times mu0 * A_top / (N * Omega_p), with
+ *   mu0 = cos(sun_zenith), A_top = nx dx ny dy, N = n_photons_norm (or
+ *   n_photons) and Omega_p the solid angle of the pixel.  n_photons = 0
+ *   yields zero images.
+ * tally must be MC_TALLY_F64 or MC_TALLY_KAHAN32.
+ * stats: nullable; non-NULL makes the call wait for the stream. */
+int mc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+              const mc_params* params, double* images, mc_stats* stats, void* hip_stream);
+
+/* mc_render plus Monte Carlo error bars.  images_m2 (device, same layout as
+ * images, nullable) is overwritten with the sum over local estimates of the
+ * square of each normalised estimate; Var(image) ~= images_m2 - images^2 / N
+ * (exact when no photon adds more than one estimate to a pixel, otherwise a
+ * lower bound).  Costs one more FP64 atomic per local estimate. */
+int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                      const mc_params* params, double* images, double* images_m2, mc_stats* stats,
+                      void* hip_stream);
+
+/* Surrogate gradient dL/dbeta for a loss L(images) whose image gradient is
+ * dl_dimages (device, same layout as mc_render's images; for an L2 loss,
+ * 2 (i - i_measured) times any pixel mask).  The events are those of
+ * mc_render with the same grid, beta, cameras and params (same seed and
+ * photon range).
+ * grad_beta: device array of nx*ny*nz doubles, overwritten. */
+int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                 const mc_params* params, const double* dl_dimages, double* grad_beta,
+                 mc_stats* stats, void* hip_stream);
+
+/* Test and diagnostics export: the first max_rec collisions of each of the
+ * photons first_pid .. first_pid+count-1, for path-by-path comparison.
+ * events: device array of count*max_rec mc_event (nullable if max_rec == 0);
+ * pix: device array of count*max_rec*n_cams int32, the pixel row*width+col
+ *   that each camera assigns to each recorded collision, or -1 (nullable);
+ * paths: device array of count mc_path.  Slots past a photon's events are
+ *   left untouched.  Always waits for the stream. */
+typedef struct mc_event {
+    double x, y, z;       /* collision point (km) */
+    double w;             /* packet weight I_s at the collision, before the albedo factor */
+    int32_t voxel;        /* voxel of the collision */
+    int32_t pad_;
+} mc_event;
+
+enum { MC_FATE_TOP = 0, MC_FATE_BOTTOM = 1, MC_FATE_SIDE = 2, MC_FATE_RR = 3, MC_FATE_CAP = 4 };
+
+typedef struct mc_path {
+    int32_t n_events;     /* collisions of the photon */
+    int32_t fate;         /* MC_FATE_* */
+    double exit_pos[3];   /* exit point (fates TOP, BOTTOM, SIDE), else unspecified */
+    double exit_dir[3];
+    double exit_w;
+} mc_path;
+
+int mc_trace_paths(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                   const mc_params* params, uint64_t first_pid, uint32_t count, uint32_t max_rec,
+                   mc_event* events, int32_t* pix, mc_path* paths, void* hip_stream);
+
+/* Static description of a status code. */
+const char* mc_error_string(int code);
+
+/* Number of visible HIP devices (0 when none); never fails. */
+int mc_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCRT_H */

@@ -1,0 +1,136 @@
+// Micro-benchmarks that measure the ceilings the renderer is compared with:
+// random 4-byte gathers from a working set of a given size (global memory and
+// LDS), FP64 atomic adds (device scope and workgroup scope, spread and
+// hot-spot), and a plain streaming copy (for calibrating HBM byte counters).
+// Exported through a separate C ABI (libmcrt_micro.so); none of this is on
+// the rendering path.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // integer hash (Wang-style avalanche) for addresses independent of data
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void k_gather(const float* __restrict__ data, uint32_t n, uint32_t loads, float* sink) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.f;
+    uint32_t h = mix32(tid * 0x9E3779B9u + 1u);
+#pragma unroll 8
+    for (uint32_t j = 0; j < loads; ++j) {
+        h = mix32(h + j);
+        acc += data[h % n];
+    }
+    if (acc == 1234.5f) sink[tid] = acc;  // keeps the loads alive
+}
+
+__global__ void k_gather_lds(const float* __restrict__ data, uint32_t n, uint32_t loads, float* sink) {
+    extern __shared__ float tile[];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) tile[i] = data[i];
+    __syncthreads();
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    float acc = 0.f;
+    uint32_t h = mix32(tid * 0x9E3779B9u + 1u);
+#pragma unroll 8
+    for (uint32_t j = 0; j < loads; ++j) {
+        h = mix32(h + j);
+        acc += tile[h % n];
+    }
+    if (acc == 1234.5f) sink[tid] = acc;
+}
+
+// KIND: 0 f64 device scope, 1 f64 workgroup scope, 2 f32 device scope (no
+// return), 3 f32 device scope with the old value used, 4 u64 device scope,
+// 5 f64 LDS (n <= 8192), 6 f32 LDS (n <= 16384)
+template <int KIND>
+__global__ void k_atomic(void* data, uint32_t n, uint32_t ops) {
+    __shared__ double lds[8192];
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (KIND >= 5) {
+        for (uint32_t i = threadIdx.x; i < 8192; i += blockDim.x) lds[i] = 0.0;
+        __syncthreads();
+    }
+    uint32_t h = mix32(tid * 0x9E3779B9u + 7u);
+    float keep = 0.f;
+    for (uint32_t j = 0; j < ops; ++j) {
+        h = mix32(h + j);
+        const uint32_t i = h % n;
+        if (KIND == 0) {
+            unsafeAtomicAdd((double*)data + i, 1.0);
+        } else if (KIND == 1) {
+            __hip_atomic_fetch_add((double*)data + i, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (KIND == 2) {
+            unsafeAtomicAdd((float*)data + i, 1.0f);
+        } else if (KIND == 3) {
+            keep += atomicAdd((float*)data + i, 1.0f);
+        } else if (KIND == 4) {
+            atomicAdd((unsigned long long*)data + i, 1ull);
+        } else if (KIND == 5) {
+            atomicAdd(&lds[i & 8191u], 1.0);
+        } else {
+            atomicAdd(((float*)lds) + (i & 16383u), 1.0f);
+        }
+    }
+    if (KIND >= 5) {
+        __syncthreads();
+        if (threadIdx.x == 0 && lds[0] == -1.0) ((double*)data)[0] = lds[1];
+    }
+    if (KIND == 3 && keep == -1.f) ((float*)data)[0] = keep;
+}
+
+__global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+// loads per thread; grid = blocks x 256.  Returns a hipError_t value.
+int mc_micro_gather(const float* data, uint32_t n, uint32_t blocks, uint32_t loads, int use_lds, float* sink,
+                    void* stream) {
+    if (!data || n == 0 || !sink) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    if (use_lds) {
+        if ((size_t)n * sizeof(float) > 64 * 1024) return (int)hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_gather_lds, dim3(blocks), dim3(256), n * sizeof(float), s, data, n, loads, sink);
+    } else {
+        hipLaunchKernelGGL(k_gather, dim3(blocks), dim3(256), 0, s, data, n, loads, sink);
+    }
+    return (int)hipGetLastError();
+}
+
+// Atomic adds at hashed addresses in [0, n) of `data` (n elements of the
+// kind's type; LDS kinds use min(n, LDS size) and data only as a sink).
+int mc_micro_atomic(void* data, uint32_t n, uint32_t blocks, uint32_t ops, int kind, void* stream) {
+    if (!data || n == 0 || kind < 0 || kind > 6) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(k_atomic<0>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 1: hipLaunchKernelGGL(k_atomic<1>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 2: hipLaunchKernelGGL(k_atomic<2>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 3: hipLaunchKernelGGL(k_atomic<3>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 4: hipLaunchKernelGGL(k_atomic<4>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 5: hipLaunchKernelGGL(k_atomic<5>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        default: hipLaunchKernelGGL(k_atomic<6>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+    }
+    return (int)hipGetLastError();
+}
+
+// Streaming copy of n16 16-byte elements.
+int mc_micro_copy(const void* src, void* dst, int64_t n16, uint32_t blocks, void* stream) {
+    if (!src || !dst || n16 <= 0) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)src, (float4*)dst,
+                       n16);
+    return (int)hipGetLastError();
+}
+
+}  // extern "C"

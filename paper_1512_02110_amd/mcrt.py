@@ -1,0 +1,286 @@
+"""Python binding of libmcrt.so (the gfx950 HIP renderer).
+
+Argument marshalling only: every step of the renderer runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the library
+is missing or no GPU is visible the calls raise; there is no CPU fallback.
+
+Entry points (same names as the C ABI in include/mcrt.h):
+    mc_render(scene, beta, ...)      -> images (float64 tensor on the GPU), stats
+    mc_grad_beta(scene, beta, dl, ...) -> dL/dbeta (float64 tensor), stats
+    mc_trace_paths(scene, beta, first_pid, count, max_rec, ...)
+    MCRender: torch.autograd.Function (forward = render, backward = surrogate gradient)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmcrt.so")
+
+MC_OK, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE, MC_ERR_HIP, MC_ERR_OUT_OF_MEMORY = 0, -1, -2, -3, -4
+MC_FP32, MC_FP64 = 0, 1
+MC_TALLY_F64, MC_TALLY_KAHAN32 = 0, 1
+TRANSPORTS = {"fp32": MC_FP32, "fp64": MC_FP64}
+TALLIES = {"f64": MC_TALLY_F64, "kahan32": MC_TALLY_KAHAN32}
+
+
+class McGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class McCamera(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("R", C.c_double * 9), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class McParams(C.Structure):
+    _fields_ = [("albedo", C.c_double), ("g", C.c_double), ("sun_zenith", C.c_double),
+                ("sun_azimuth", C.c_double), ("rr_weight", C.c_double),
+                ("n_photons", C.c_uint64), ("seed", C.c_uint64), ("photon_offset", C.c_uint64),
+                ("n_photons_norm", C.c_uint64), ("max_events", C.c_uint32),
+                ("transport", C.c_int32), ("tally", C.c_int32), ("pad_", C.c_int32)]
+
+
+STAT_FIELDS = ["photons", "events", "le_jobs", "vox_free", "vox_conn", "esc_top", "esc_bottom",
+               "esc_side", "rr_killed", "capped"]
+
+
+class McStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in STAT_FIELDS]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n in STAT_FIELDS}
+
+
+EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("w", "<f8"),
+                        ("voxel", "<i4"), ("pad_", "<i4")])
+PATH_DTYPE = np.dtype([("n_events", "<i4"), ("fate", "<i4"), ("exit_pos", "<f8", (3,)),
+                       ("exit_dir", "<f8", (3,)), ("exit_w", "<f8")])
+
+EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_error_string",
+           "mc_device_count"]
+
+
+class McError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {code} ({error_string(code)})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmcrt.so (raises OSError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise OSError(f"{path} is missing: build it with `python -m paper_1512_02110_amd.build`")
+        L = C.CDLL(path)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.mc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                C.POINTER(McParams), vp, C.POINTER(McStats), vp]
+        L.mc_render_moments.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                        C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
+        L.mc_grad_beta.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                   C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
+        L.mc_trace_paths.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                     C.POINTER(McParams), C.c_uint64, C.c_uint32, C.c_uint32,
+                                     vp, vp, vp, vp]
+        for f in ("mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_device_count"):
+            getattr(L, f).restype = C.c_int
+        L.mc_device_count.argtypes = []
+        L.mc_error_string.argtypes = [C.c_int]
+        L.mc_error_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return load_library().mc_error_string(int(code)).decode()
+
+
+def _check(fn, rc):
+    if rc != MC_OK:
+        raise McError(fn, rc)
+
+
+def make_grid(s) -> McGrid:
+    return McGrid(int(s.nx), int(s.ny), int(s.nz), 0, float(s.dx), float(s.dy), float(s.dz))
+
+
+def make_cameras(cameras):
+    arr = (McCamera * max(1, len(cameras)))()
+    for i, c in enumerate(cameras):
+        arr[i].pos[:] = [float(v) for v in c.pos]
+        arr[i].R[:] = [float(v) for v in c.R]
+        arr[i].fx, arr[i].fy = float(c.fx), float(c.fy)
+        arr[i].cx, arr[i].cy = float(c.cx), float(c.cy)
+        arr[i].width, arr[i].height = int(c.width), int(c.height)
+    return arr
+
+
+def make_params(s, n_photons=None, seed=None, photon_offset=0, n_photons_norm=0,
+                max_events=100000, rr_weight=0.1, transport="fp32", tally="f64") -> McParams:
+    return McParams(float(s.albedo), float(s.g), float(s.sun_zenith), float(s.sun_azimuth),
+                    float(rr_weight), int(s.n_photons if n_photons is None else n_photons),
+                    int(s.seed if seed is None else seed), int(photon_offset), int(n_photons_norm),
+                    int(max_events), TRANSPORTS[transport], TALLIES[tally], 0)
+
+
+def n_pixels(s) -> int:
+    return sum(int(c.width) * int(c.height) for c in s.cameras)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the renderer runs only on the HIP device")
+    return torch
+
+
+def _stream(torch, stream):
+    return (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+
+
+def beta_tensor(s, transport="fp32", beta=None, device="cuda"):
+    """Device copy of the scene's extinction in the dtype the transport reads."""
+    torch = _torch()
+    b = s.beta if beta is None else beta
+    dt = torch.float32 if transport == "fp32" else torch.float64
+    if isinstance(b, torch.Tensor):
+        return b.detach().to(device=device, dtype=dt).contiguous().reshape(-1)
+    return torch.as_tensor(np.ascontiguousarray(b).reshape(-1), dtype=dt, device=device)
+
+
+def _check_beta(torch, s, beta, transport):
+    want = torch.float32 if transport == "fp32" else torch.float64
+    if not (beta.is_cuda and beta.dtype == want and beta.is_contiguous() and beta.numel() == s.n_vox):
+        raise ValueError(f"beta must be a contiguous {want} CUDA tensor of {s.n_vox} voxels")
+
+
+def mc_render(s, beta, transport="fp32", tally="f64", stats=True, out=None, stream=None, **kw):
+    """Forward render.  Returns (images [n_pix] float64 on the GPU, stats dict or None)."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    n = n_pixels(s)
+    img = out if out is not None else torch.empty(n, dtype=torch.float64, device=beta.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_render(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                  make_cameras(s.cameras),
+                                  C.byref(make_params(s, transport=transport, tally=tally, **kw)),
+                                  C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
+                                  C.c_void_p(_stream(torch, stream)))
+    _check("mc_render", rc)
+    return img, (st.as_dict() if stats else None)
+
+
+def mc_render_moments(s, beta, transport="fp32", tally="f64", stats=True, stream=None, **kw):
+    """Forward render with per-pixel second moments.  Returns (images, images_m2, stats);
+    the Monte Carlo variance of a pixel is about images_m2 - images**2 / N."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    n = n_pixels(s)
+    img = torch.empty(n, dtype=torch.float64, device=beta.device)
+    m2 = torch.empty(n, dtype=torch.float64, device=beta.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_render_moments(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()),
+                                          len(s.cameras), make_cameras(s.cameras),
+                                          C.byref(make_params(s, transport=transport, tally=tally, **kw)),
+                                          C.c_void_p(img.data_ptr()), C.c_void_p(m2.data_ptr()),
+                                          C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
+    _check("mc_render_moments", rc)
+    return img, m2, (st.as_dict() if stats else None)
+
+
+def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True, out=None,
+                 stream=None, **kw):
+    """Surrogate gradient dL/dbeta for image gradient dl_dimages (float64 [n_pix])."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    dl = dl_dimages.detach().to(device=beta.device, dtype=torch.float64).contiguous().reshape(-1)
+    if dl.numel() != n_pixels(s):
+        raise ValueError("dl_dimages has the wrong number of pixels")
+    g = out if out is not None else torch.empty(s.n_vox, dtype=torch.float64, device=beta.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_grad_beta(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()),
+                                     len(s.cameras), make_cameras(s.cameras),
+                                     C.byref(make_params(s, transport=transport, tally=tally, **kw)),
+                                     C.c_void_p(dl.data_ptr()), C.c_void_p(g.data_ptr()),
+                                     C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
+    _check("mc_grad_beta", rc)
+    return g, (st.as_dict() if stats else None)
+
+
+def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pix=True,
+                   stream=None, **kw):
+    """Per-photon event records.  Returns numpy (events[count, max_rec], paths[count],
+    pix[count, max_rec, n_cams] or None); unrecorded slots hold zeros / -2."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    dev = beta.device
+    ev = torch.zeros(max(1, count * max_rec * EVENT_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    paths = torch.zeros(max(1, count * PATH_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    pix = (torch.full((max(1, count * max_rec * len(s.cameras)),), -2, dtype=torch.int32, device=dev)
+           if with_pix else None)
+    rc = load_library().mc_trace_paths(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()),
+                                       len(s.cameras), make_cameras(s.cameras),
+                                       C.byref(make_params(s, transport=transport, **kw)),
+                                       int(first_pid), int(count), int(max_rec),
+                                       C.c_void_p(ev.data_ptr() if max_rec > 0 else 0),
+                                       C.c_void_p(pix.data_ptr() if with_pix else 0),
+                                       C.c_void_p(paths.data_ptr()), C.c_void_p(_stream(torch, stream)))
+    _check("mc_trace_paths", rc)
+    ev_np = ev.cpu().numpy()[:count * max_rec * EVENT_DTYPE.itemsize].view(EVENT_DTYPE)
+    p_np = paths.cpu().numpy()[:count * PATH_DTYPE.itemsize].view(PATH_DTYPE)
+    pix_np = (pix.cpu().numpy()[:count * max_rec * len(s.cameras)].reshape(count, max_rec, len(s.cameras))
+              if with_pix else None)
+    return ev_np.reshape(count, max_rec), p_np, pix_np
+
+
+class MCRender:
+    """torch.autograd.Function wrapper: images = render(beta); the backward
+    pass returns the surrogate gradient (frozen in-scatter, Sec. 5.2) on the
+    events of the same photon stream (or of `grad_seed` when given)."""
+
+    @staticmethod
+    def apply(beta, scene, transport="fp32", tally="f64", grad_seed=None, **kw):
+        return _autograd_fn().apply(beta, scene, transport, tally, grad_seed, kw)
+
+
+_fn = None
+
+
+def _autograd_fn():
+    global _fn
+    if _fn is None:
+        torch = _torch()
+
+        class _MCRender(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, beta, scene, transport, tally, grad_seed, kw):
+                b = beta_tensor(scene, transport, beta=beta, device=beta.device)
+                img, _ = mc_render(scene, b, transport=transport, tally=tally, stats=False, **kw)
+                ctx.save_for_backward(b)
+                ctx.scene, ctx.transport, ctx.tally, ctx.grad_seed, ctx.kw = scene, transport, tally, grad_seed, kw
+                ctx.beta_dtype = beta.dtype
+                return img
+
+            @staticmethod
+            def backward(ctx, g_img):
+                (b,) = ctx.saved_tensors
+                kw = dict(ctx.kw)
+                if ctx.grad_seed is not None:
+                    kw["seed"] = ctx.grad_seed
+                g, _ = mc_grad_beta(ctx.scene, b, g_img, transport=ctx.transport, tally=ctx.tally,
+                                    stats=False, **kw)
+                return g.to(ctx.beta_dtype), None, None, None, None, None
+
+        _fn = _MCRender
+    return _fn
+

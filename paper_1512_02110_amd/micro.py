@@ -1,0 +1,105 @@
+"""Runs the micro-benchmarks of libmcrt_micro.so and prints one JSON object:
+random-gather rates per working-set size (global memory and LDS), FP64
+atomic-add rates (device and workgroup scope; spread and hot-spot) and a
+streaming-copy bandwidth.
+
+    python -m paper_1512_02110_amd.micro [--quick]
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(PKG, "libmcrt_micro.so")
+
+
+def _lib():
+    L = C.CDLL(LIB)
+    L.mc_micro_gather.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p,
+                                  C.c_void_p]
+    L.mc_micro_atomic.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
+    L.mc_micro_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]
+    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy):
+        f.restype = C.c_int
+    return L
+
+
+def _time(torch, fn, reps=3):
+    fn()  # warm-up
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def main(quick=False):
+    import torch
+    L = _lib()
+    dev = torch.device("cuda:0")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    blocks = n_cu * 8
+    out = {"n_cu": n_cu, "blocks": blocks, "gather": [], "atomic": []}
+    sink = torch.zeros(blocks * 256, dtype=torch.float32, device=dev)
+    loads = 128 if quick else 512
+    for nbytes, lds in [(16 << 10, 1), (16 << 10, 0), (1 << 20, 0), (8 << 20, 0), (32 << 20, 0),
+                        (256 << 20, 0)]:
+        n = nbytes // 4
+        data = torch.rand(n, dtype=torch.float32, device=dev)
+
+        def run():
+            rc = L.mc_micro_gather(C.c_void_p(data.data_ptr()), n, blocks, loads, lds,
+                                   C.c_void_p(sink.data_ptr()), st)
+            assert rc == 0, rc
+        ms = _time(torch, run)
+        total = blocks * 256 * loads
+        out["gather"].append({"working_set_bytes": nbytes, "lds": bool(lds), "ms": ms,
+                              "gloads_per_s": total / (ms / 1e3) / 1e9,
+                              "useful_GBps": total * 4 / (ms / 1e3) / 1e9})
+        print(f"[micro] gather {nbytes >> 10} KiB lds={lds}: {out['gather'][-1]['gloads_per_s']:.1f} G/s",
+              flush=True)
+    ops = 32 if quick else 128
+    kinds = {0: "f64 device", 1: "f64 workgroup", 2: "f32 device", 3: "f32 device returning",
+             4: "u64 device", 5: "f64 LDS", 6: "f32 LDS"}
+    for nbytes in (64, 1 << 20, 16 << 20, 64 << 20):
+        n = nbytes // 8
+        data = torch.zeros(n, dtype=torch.float64, device=dev)
+        for kind, name in kinds.items():
+            if kind >= 5 and nbytes != 64 and nbytes != (1 << 20):
+                continue
+            nn = n if kind in (0, 1, 4) else (2 * n if kind in (2, 3) else min(n, 8192 if kind == 5 else 16384))
+
+            def run():
+                rc = L.mc_micro_atomic(C.c_void_p(data.data_ptr()), nn, blocks, ops, kind, st)
+                assert rc == 0, rc
+            ms = _time(torch, run)
+            total = blocks * 256 * ops
+            out["atomic"].append({"addresses": nn, "kind": name, "ms": ms,
+                                  "gatomics_per_s": total / (ms / 1e3) / 1e9})
+            print(f"[micro] atomic {name} n={nn}: {out['atomic'][-1]['gatomics_per_s']:.2f} G/s", flush=True)
+    nb = 1 << 30
+    src = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+
+    def run_copy():
+        rc = L.mc_micro_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb // 16, n_cu * 16, st)
+        assert rc == 0, rc
+    ms = _time(torch, run_copy)
+    out["copy"] = {"bytes_each_way": nb, "ms": ms, "GBps": 2 * nb / (ms / 1e3) / 1e9}
+    print(f"[micro] copy: {out['copy']['GBps']:.0f} GB/s", flush=True)
+    print(json.dumps(out), flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    main(quick="--quick" in sys.argv)
