@@ -64,6 +64,38 @@ def cpu_baseline(cfg, per_proc, procs):
             "per_core": events / cpu_s}
 
 
+def adjoint_c3(M, torch, np, stream, n_photons):
+    """Forward + adjoint on the 16^3 Gaussian-blob workload: beta0 = 0.7 x
+    smoothed truth, L2 loss against images of the truth (another seed);
+    FP32 transport, FP64 and compensated-FP32 gradient tallies."""
+    from paper_1512_02110_amd import scenes
+    truth = scenes.config3_truth(n_photons=n_photons, seed=1)
+    s = scenes.config3_initial(n_photons=n_photons, seed=0)
+    meas, _ = M.mc_render(truth, M.beta_tensor(truth, "fp32"), stats=False)
+    beta = M.beta_tensor(s, "fp32")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    timed(lambda: M.mc_render(s, beta, stats=False))  # warm-up
+    (img, _), t_fwd = timed(lambda: M.mc_render(s, beta, stats=False))
+    dl = 2.0 * (img - meas)
+    timed(lambda: M.mc_grad_beta(s, beta, dl, stats=False))  # warm-up
+    (g64, _), t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl, stats=False))
+    (g32, _), t_adj32 = timed(lambda: M.mc_grad_beta(s, beta, dl, tally="kahan32", stats=False))
+    a, b = g64.cpu().numpy(), g32.cpu().numpy()
+    return {"workload": f"c3: 16^3 blob, 4 cameras 32x32, {n_photons:.0e} photons, FP32 transport",
+            "fwd_ms": round(t_fwd, 3), "adj_ms_f64": round(t_adj, 3), "adj_ms_kahan32": round(t_adj32, 3),
+            "fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 4),
+            "kahan32_vs_f64_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
+            "kahan32_vs_f64_max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(a)))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +108,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-photons", type=int, default=60000, help="photons per CPU process")
     ap.add_argument("--cpu-procs", type=int, default=None)
+    ap.add_argument("--c3-photons", type=int, default=100_000_000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -200,6 +233,8 @@ def main():
                        "pixel_rel_err_max": float(rel.max()) if rel.size else 0.0,
                        "image_rel_l1": float(diff.sum() / np.abs(i64).sum()),
                        "events_fp32_minus_fp64": int(recs[0][1]["events"] - st64["events"])}
+    if not args.no_adjoint and args.config == "c2":
+        out["fwd_adjoint_c3"] = adjoint_c3(M, torch, np, stream, args.c3_photons)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

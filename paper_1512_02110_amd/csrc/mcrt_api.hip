@@ -139,7 +139,6 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
 
     CHECK_HIP(hipGetDevice(&dev));
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    CHECK_HIP(transport_occupancy<Real>(mode, tally, &per_cu));
     CHECK_HIP(hipMallocAsync((void**)&S.base, bytes, stream));
     counters = S.take<unsigned long long>(1 + ST_N);
     dcams = S.take<DevCam<Real>>(n_cams);
@@ -209,6 +208,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.mncy = (int)ncell(1);
     A.mask_words = (int)mask_words;
     A.mask_fine = (sh[0] | sh[1] | sh[2]) == 0;
+    A.grad_lds = mode == MODE_GRAD &&
+                 ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
+    CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;

@@ -27,6 +27,17 @@ struct HostCam {
     int64_t pix_off;
 };
 
+// One connection ray of the gradient, written by the replay for every tile
+// of the grid the ray crosses (32 bytes).
+struct TapeRec {
+    uint32_t vox;          // start voxel: ix | iy << 11 | iz << 22
+    uint16_t fx, fy, fz;   // start fraction in the voxel, * 65535
+    uint16_t pad_;
+    float vx, vy, vz;      // unit direction to the camera
+    float r;               // length to the camera (km)
+    float a;               // gradient weight dL/di_p * norm_p * C
+};
+
 // Per-pixel normalisation table entry (double).
 struct NormCam {
     double fx, fy, cx, cy;
@@ -63,6 +74,12 @@ struct KArgs {
     // occupancy bitmask of beta > 0 over cells of 2^msh voxels per axis
     const uint32_t* mask;
     int mshx, mshy, mshz, mncx, mncy, mask_words, mask_fine;
+    int grad_lds;               // gradient privatised in LDS (small grids)
+    // gradient tape (large grids): one bin of bin_cap records per tile
+    TapeRec* tape;
+    unsigned long long* bin_count;
+    int64_t bin_cap;
+    int tx, ty, tz, ntx, nty, ntz;  // tile edge (voxels) and tiles per axis
     // trace
     uint64_t first_pid;
     uint32_t trace_count, max_rec;
@@ -71,13 +88,27 @@ struct KArgs {
     mc_path* paths;
 };
 
+constexpr int MASK_WORDS = 8192;  // 32 KB of LDS: up to 262144 cells
+constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)
+constexpr int DEPOSIT_BLOCK = 1024;
+
+// Work item of the deposit kernel: a record range of one tile's bin.
+struct DepositItem {
+    int tile;
+    int pad_;
+    int64_t lo, hi;
+};
+constexpr int64_t GRAD_LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a privatised gradient
+
+constexpr int BLOCK = 256;
+
 // Launchers (mcrt_kernels.hip).
 template <typename Real>
 hipError_t launch_write_cams(const CamChunk& chunk, DevCam<Real>* dev, NormCam* norm, hipStream_t s);
 template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s);
 template <typename Real>
-hipError_t transport_occupancy(int mode, int tally, int* blocks_per_cu);
+hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* blocks_per_cu);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s);
@@ -88,9 +119,8 @@ hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams
 hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipStream_t s);
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipStream_t s);
+template <typename Real>
+hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s);
 
-constexpr int MASK_WORDS = 8192;  // 32 KB of LDS: up to 262144 cells
-
-constexpr int BLOCK = 256;
 
 }  // namespace mcrt

@@ -93,6 +93,18 @@ __device__ __forceinline__ void tally_f64(double* base, float* base32, int64_t i
     }
 }
 
+// Gradient deposit: into the block's LDS copy of the whole gradient when the
+// grid is small enough to be privatised (flushed once at the end of the
+// kernel), else straight to the device array.
+template <typename Real, int TALLY>
+__device__ __forceinline__ void grad_add(const KArgs<Real>& A, double* lds_grad, int64_t k, double x) {
+    if (lds_grad) {
+        atomicAdd(lds_grad + k, x);
+    } else {
+        tally_f64<TALLY>(A.grad, A.grad32, k, x);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Voxel walk in registers.  Along the unit direction w from the voxel-local
 // point (i, f), the next crossing on axis a is t_a = r_a g_a with
@@ -395,7 +407,7 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
 
 // One voxel of the connection ray; returns true when the ray is done.
 template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J) {
+__device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J) {
     bool cx, cy, cz;
     const Real tn = walk_next(J.W, cx, cy, cz);
     const bool last = tn >= J.r;
@@ -403,7 +415,7 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     const Real l = tend - J.W.t;
     const bool scatter = MODE == MODE_GRAD && J.phase == 2;
     if (scatter) {
-        tally_f64<TALLY>(A.grad, A.grad32, J.W.k, -J.a * (double)l);
+        grad_add<Real, TALLY>(A, lds_grad, J.W.k, -J.a * (double)l);
     } else {
         J.tau += (double)J.bp * (double)J.lp;
         J.bp = J.bn;
@@ -423,7 +435,7 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
 // Tally of a finished ray.  For the gradient, a finished first walk with a
 // non-zero weight starts the second walk (returns true: the lane stays busy).
 template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J,
+__device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J,
                                            uint64_t& vconn) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     vconn += J.steps;
@@ -436,7 +448,7 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
         const double a = A.gw[J.pix] * C;
         if (a == 0.0) return false;
         const int ke = J.i0x + A.G.nx * J.i0y + A.G.nxy * J.i0z;
-        tally_f64<TALLY>(A.grad, A.grad32, ke, a / (double)A.beta[ke]);
+        grad_add<Real, TALLY>(A, lds_grad, ke, a / (double)A.beta[ke]);
         J.a = a;
         J.phase = 2;
         job_begin(A, mask, J);
@@ -447,13 +459,13 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
 template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, JobQueue<Real>& Q,
-                                      uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy, bool& fin,
-                                      bool final_pass, uint64_t& vconn) {
+__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
+                                      JobQueue<Real>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
+                                      bool& fin, bool final_pass, uint64_t& vconn) {
     for (;;) {
         if (fin) {
             fin = false;
-            busy = job_finish<Real, MODE, TALLY>(A, mask, J, vconn);
+            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn);
         }
         const uint32_t count = qtail - qhead;
         const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
@@ -488,7 +500,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
         // walk until a quarter of the lanes are idle (all, if nothing is queued)
         const uint32_t keep = (qtail - qhead) > 0 ? (uint32_t)WAVE - REFILL_IDLE : 0u;
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-            if (busy && job_step<Real, MODE, TALLY>(A, mask, J)) {
+            if (busy && job_step<Real, MODE, TALLY>(A, mask, lds_grad, J)) {
                 busy = false;
                 fin = true;
             }
@@ -496,11 +508,19 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
     }
 }
 
+// Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
+// the gradient is privatised, one double per voxel.
 template <typename Real, int MODE, int TALLY>
 __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
     __shared__ JobQueue<Real> s_q[WAVES];
-    __shared__ uint32_t s_mask[MASK_WORDS];
     __shared__ unsigned long long s_st[ST_N];
+    extern __shared__ uint32_t s_dyn[];
+    uint32_t* s_mask = s_dyn;
+    double* lds_grad = nullptr;
+    if (MODE == MODE_GRAD && A.grad_lds) {
+        lds_grad = reinterpret_cast<double*>(s_dyn + ((A.mask_words + 1) & ~1));
+        for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) lds_grad[i] = 0.0;
+    }
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
     for (int i = threadIdx.x; i < A.mask_words; i += BLOCK) s_mask[i] = A.mask[i];
     __syncthreads();
@@ -562,7 +582,7 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY>(A, mask, Q, qhead, qtail, J, busy, fin, false, vconn);
+                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn);
             }
         }
         if (collided) {
@@ -572,9 +592,9 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY>(A, mask, Q, qhead, qtail, J, busy, fin, false, vconn);
+        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn);
     }
-    drain<Real, MODE, TALLY>(A, mask, Q, qhead, qtail, J, busy, fin, true, vconn);
+    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn);
 
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
     if (n_le) atomicAdd(&s_st[ST_LE], (unsigned long long)n_le);
@@ -582,6 +602,12 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
     if (vconn) atomicAdd(&s_st[ST_VCONN], (unsigned long long)vconn);
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
+    if (lds_grad) {
+        for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) {
+            const double v = lds_grad[i];
+            if (v != 0.0) tally_f64<TALLY>(A.grad, A.grad32, i, v);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -777,9 +803,19 @@ hipError_t launch_write_cams(const CamChunk& chunk, DevCam<Real>* dev, NormCam* 
     return hipGetLastError();
 }
 
+// Dynamic LDS bytes of k_render for these arguments.
+template <typename Real>
+size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
+    size_t words = (size_t)((a.mask_words + 1) & ~1);
+    size_t bytes = words * sizeof(uint32_t);
+    if (mode == MODE_GRAD && a.grad_lds) bytes += (size_t)a.n_vox * sizeof(double);
+    return bytes;
+}
+
 template <typename Real, int MODE, int TALLY>
 static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_render<Real, MODE, TALLY>), dim3(grid), dim3(BLOCK), 0, s, a);
+    const size_t dyn = render_dyn_lds(a, MODE);
+    hipLaunchKernelGGL((k_render<Real, MODE, TALLY>), dim3(grid), dim3(BLOCK), dyn, s, a);
     return hipGetLastError();
 }
 
@@ -798,16 +834,17 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
 }
 
 template <typename Real, int MODE, int TALLY>
-static hipError_t occ_r(int* b) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY>, BLOCK, 0);
+static hipError_t occ_r(const KArgs<Real>& a, int* b) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY>, BLOCK,
+                                                        render_dyn_lds(a, MODE));
 }
 
 template <typename Real>
-hipError_t transport_occupancy(int mode, int tally, int* b) {
-    if (mode == MODE_RENDER) return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64>(b)
-                                                       : occ_r<Real, MODE_RENDER, TALLY_K32>(b);
-    if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(b)
-                                                     : occ_r<Real, MODE_GRAD, TALLY_K32>(b);
+hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b) {
+    if (mode == MODE_RENDER) return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64>(a, b)
+                                                       : occ_r<Real, MODE_RENDER, TALLY_K32>(a, b);
+    if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
+                                                     : occ_r<Real, MODE_GRAD, TALLY_K32>(a, b);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
 
@@ -823,8 +860,8 @@ template hipError_t launch_write_cams<float>(const CamChunk&, DevCam<float>*, No
 template hipError_t launch_write_cams<double>(const CamChunk&, DevCam<double>*, NormCam*, hipStream_t);
 template hipError_t launch_transport<float>(const KArgs<float>&, int, int, int, hipStream_t);
 template hipError_t launch_transport<double>(const KArgs<double>&, int, int, int, hipStream_t);
-template hipError_t transport_occupancy<float>(int, int, int*);
-template hipError_t transport_occupancy<double>(int, int, int*);
+template hipError_t transport_occupancy<float>(const KArgs<float>&, int, int, int*);
+template hipError_t transport_occupancy<double>(const KArgs<double>&, int, int, int*);
 
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
