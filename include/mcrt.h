@@ -109,7 +109,11 @@ typedef struct mc_params {
                                  capped, >= 1 */
     int32_t transport;        /* MC_FP32 or MC_FP64 */
     int32_t tally;            /* MC_TALLY_F64 or MC_TALLY_KAHAN32 */
-    int32_t pad_;
+    int32_t tape_limit;       /* mc_grad_beta on grids too large for an LDS copy of the
+                                 gradient: most records of its ray tape (stream-ordered
+                                 scratch of 4 + 8 sizeof(real) bytes each); 0 = automatic
+                                 (up to a quarter of free device memory, at most 16 GiB).
+                                 A smaller tape means more, smaller replay chunks.  >= 0. */
 } mc_params;
 
 /* Counters of one call (all photons of the call). */

@@ -1,6 +1,7 @@
 // C ABI of the gfx950 renderer: argument validation, stream-ordered scratch,
 // camera-table upload and kernel launches.  See include/mcrt.h for the
 // contract of every entry point.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -58,6 +59,7 @@ int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* ca
     if (p->max_events < 1) return MC_ERR_INVALID_ARG;
     if (p->transport != MC_FP32 && p->transport != MC_FP64) return MC_ERR_INVALID_ARG;
     if (p->tally != MC_TALLY_F64 && p->tally != MC_TALLY_KAHAN32) return MC_ERR_INVALID_ARG;
+    if (p->tape_limit < 0) return MC_ERR_INVALID_ARG;
     return MC_OK;
 }
 
@@ -92,6 +94,189 @@ struct Scratch {
 };
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Tile edges of the gradient tape: columns of at most 64 voxels in z and
+// TILE_VOX voxels in all (connection rays to cameras below or above the
+// cloud are closer to vertical than to horizontal, so tall tiles are crossed
+// by fewer rays more than once).
+void tape_tiles(const mc_grid* g, int& tx, int& ty, int& tz) {
+    tz = g->nz < 64 ? g->nz : 64;
+    const int txy = (int)std::floor(std::sqrt((double)TILE_VOX / tz));
+    tx = g->nx < txy ? g->nx : txy;
+    ty = TILE_VOX / (tz * tx);
+    if (ty > g->ny) ty = g->ny;
+}
+
+constexpr int TAPE_FALLBACK = 1;
+
+// Gradient of a large grid through the tape, in chunks of photons whose
+// records fit the tape: replay a chunk (k_render writes the records of its
+// connection rays), read back the tiles' slot counts, then deposit every
+// tile's records (k_deposit).  A chunk whose records overflowed a tile is
+// replayed smaller before anything of it reaches the gradient.  The slot
+// capacity of every tile follows the slot demand per photon measured on the
+// chunks so far.  Stats of the successful chunks are summed into host_sum.
+template <typename Real>
+int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
+             int n_cu, unsigned long long* counters, unsigned long long* host_sum, hipStream_t stream) {
+    int rc = MC_OK;
+    const int nt = A.tp.n_tiles;
+    const size_t rec = sizeof(uint32_t) + 8 * sizeof(Real);
+    uint64_t waves = (uint64_t)max_blocks * (BLOCK / 64);
+    size_t free_b = 0, total_b = 0;
+    char* pool = nullptr;
+    uint32_t* meta = nullptr;  // count[nt], overflow, off[nt], cap[nt]
+    DepositItem* ditems = nullptr;
+    const int max_items = nt + 2 * n_cu + 1;
+    std::vector<uint32_t> h_offcap(2 * (size_t)nt), h_count(nt + 1);
+    std::vector<DepositItem> h_items;
+    std::vector<double> demand(nt, 0.0);
+    double seen = 0.0;
+    unsigned long long h_ctr[1 + ST_N];
+    uint64_t P = 0, done = 0, chunk = 0, slack = 0;
+    size_t off = 0;
+
+    CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+    {
+        const uint64_t lim = std::min<uint64_t>(free_b / 4, (uint64_t)16 << 30) / rec;
+        P = std::max<uint64_t>(n_photons * 64, std::max<uint64_t>(32 * waves * (uint64_t)nt, (uint64_t)1 << 20));
+        P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
+        if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
+    }
+    // every resident wavefront may hold a partly used block of slots in
+    // every tile: keep that slack within half of the tape, with fewer
+    // resident blocks if the tape is small
+    A.tp.block = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, P / (16 * waves * (uint64_t)nt)));
+    if (2 * waves * A.tp.block * (uint64_t)nt > P) {
+        max_blocks = (int)std::max<uint64_t>(1, P / (2 * (uint64_t)nt * (BLOCK / 64)));
+        if (max_blocks > n_cu * 64) max_blocks = n_cu * 64;
+        waves = (uint64_t)max_blocks * (BLOCK / 64);
+    }
+    if (2 * waves * A.tp.block * (uint64_t)nt > P) return TAPE_FALLBACK;
+    slack = waves * A.tp.block;
+
+    CHECK_HIP(hipMallocAsync((void**)&pool, P * rec + 16 * 256, stream));
+    CHECK_HIP(hipMallocAsync((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + 1), stream));
+    CHECK_HIP(hipMallocAsync((void**)&ditems, sizeof(DepositItem) * max_items, stream));
+    {
+        auto take = [&](size_t bytes) {
+            char* p = pool + off;
+            off += (bytes + 255) & ~(size_t)255;
+            return p;
+        };
+        A.tp.vox = reinterpret_cast<uint32_t*>(take(P * sizeof(uint32_t)));
+        Real** fields[8] = {&A.tp.fx, &A.tp.fy, &A.tp.fz, &A.tp.vx, &A.tp.vy, &A.tp.vz, &A.tp.r, &A.tp.a};
+        for (Real** f : fields) *f = reinterpret_cast<Real*>(take(P * sizeof(Real)));
+    }
+    A.tp.count = meta;
+    A.tp.overflow = meta + nt;
+    A.tp.off = meta + nt + 1;
+    A.tp.cap = meta + 2 * nt + 1;
+
+    // first chunk: equal capacities and a guess of 64 slots per photon
+    chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, P / (64 * (uint64_t)nt) / 4));
+    while (done < n_photons) {
+        uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
+        double rate_sum = 0.0;
+        for (int i = 0; i < nt; ++i) rate_sum += seen > 0.0 ? demand[i] / seen : 0.0;
+        if (rate_sum > 0.0) {
+            const double room = (double)P - (double)nt * (double)slack;
+            const double fit = std::floor(room / (1.25 * rate_sum));
+            if (fit < 1.0) {
+                rc = MC_ERR_OUT_OF_MEMORY;
+                goto done;
+            }
+            if ((double)n > fit) n = (uint64_t)fit;
+            double used = 0.0;
+            std::vector<double> c(nt);
+            for (int i = 0; i < nt; ++i) {
+                c[i] = 1.25 * demand[i] / seen * (double)n + (double)slack;
+                used += c[i];
+            }
+            uint64_t o = 0;
+            for (int i = 0; i < nt; ++i) {
+                // spread what is left of the tape in proportion to the demand
+                const double extra = ((double)P - used) * (demand[i] / seen) / rate_sum;
+                uint64_t cap = (uint64_t)std::floor(c[i] + (extra > 0.0 ? extra : 0.0));
+                if (o + cap > P) cap = P - o;
+                h_offcap[i] = (uint32_t)o;
+                h_offcap[nt + i] = (uint32_t)cap;
+                o += cap;
+            }
+        } else {
+            for (int i = 0; i < nt; ++i) {
+                h_offcap[i] = (uint32_t)(P / nt * i);
+                h_offcap[nt + i] = (uint32_t)(P / nt);
+            }
+        }
+        CHECK_HIP(hipMemcpyAsync(meta + nt + 1, h_offcap.data(), sizeof(uint32_t) * 2 * nt, hipMemcpyHostToDevice,
+                                 stream));
+        CHECK_HIP(launch_fill_u32(meta, nt + 1, stream));
+        CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
+        if (sizeof(Real) == 4)
+            CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(A.tp.a), (int64_t)P, stream));
+        else
+            CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(A.tp.a), (int64_t)P, stream));
+        A.pid0 = pid0 + done;
+        A.n_photons = n;
+        {
+            const uint64_t need = (n + BLOCK - 1) / BLOCK;
+            const int grid = (int)std::min<uint64_t>(need, (uint64_t)max_blocks);
+            CHECK_HIP(launch_transport<Real>(A, MODE_GRAD, tally, grid, stream));
+        }
+        CHECK_HIP(hipMemcpyAsync(h_count.data(), meta, sizeof(uint32_t) * (nt + 1), hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipMemcpyAsync(h_ctr, counters, sizeof(h_ctr), hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        for (int i = 0; i < nt; ++i) demand[i] += (double)h_count[i];
+        seen += (double)n;
+        if (h_count[nt]) {
+            if (n == 1) {
+                rc = MC_ERR_OUT_OF_MEMORY;
+                goto done;
+            }
+            chunk = n / 2;
+            continue;
+        }
+        for (int i = 1; i < 1 + ST_N; ++i) host_sum[i] += h_ctr[i];
+        {
+            uint64_t total = 0;
+            for (int i = 0; i < nt; ++i) total += h_count[i];
+            const uint64_t R = std::max<uint64_t>(8192, (total + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
+            h_items.clear();
+            for (int i = 0; i < nt; ++i)
+                for (uint64_t lo = 0; lo < h_count[i]; lo += R) {
+                    DepositItem d;
+                    d.tile = i;
+                    d.lo = (uint32_t)lo;
+                    d.hi = (uint32_t)std::min<uint64_t>(h_count[i], lo + R);
+                    d.pad_ = 0;
+                    h_items.push_back(d);
+                }
+            if ((int)h_items.size() > max_items) {
+                rc = MC_ERR_HIP;
+                goto done;
+            }
+            if (!h_items.empty()) {
+                CHECK_HIP(hipMemcpyAsync(ditems, h_items.data(), sizeof(DepositItem) * h_items.size(),
+                                         hipMemcpyHostToDevice, stream));
+                CHECK_HIP(launch_deposit<Real>(A, tally, ditems, (int)h_items.size(), stream));
+            }
+        }
+        done += n;
+        chunk = n_photons - done;  // the next chunk is sized from the demand
+    }
+    CHECK_HIP(hipStreamSynchronize(stream));
+
+done:
+    for (void* p : {(void*)ditems, (void*)meta, (void*)pool}) {
+        if (!p) continue;
+        hipError_t e = hipFreeAsync(p, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    // the host arrays above were sources of asynchronous copies
+    (void)hipStreamSynchronize(stream);
+    return rc;
+}
 
 // One call of the transport kernel with all its preparation.
 template <typename Real>
@@ -136,6 +321,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     double base_norm = 0.0;
     int dev = 0, n_cu = 0, per_cu = 0, grid_blocks = 1;
     const uint64_t n_norm = prm->n_photons_norm ? prm->n_photons_norm : prm->n_photons;
+    const int64_t need_blocks = (int64_t)((prm->n_photons + BLOCK - 1) / BLOCK);
+    bool tape_counts = false;
 
     CHECK_HIP(hipGetDevice(&dev));
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -210,6 +397,31 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.mask_fine = (sh[0] | sh[1] | sh[2]) == 0;
     A.grad_lds = mode == MODE_GRAD &&
                  ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
+    if (mode == MODE_GRAD && !A.grad_lds) {
+        int tx, ty, tz;
+        tape_tiles(grid, tx, ty, tz);
+        const int ntx = (grid->nx + tx - 1) / tx, nty = (grid->ny + ty - 1) / ty, ntz = (grid->nz + tz - 1) / tz;
+        if ((int64_t)ntx * nty * ntz <= MAX_TAPE_TILES) {
+            A.tape = 1;
+            A.tp.tx = tx;
+            A.tp.ty = ty;
+            A.tp.tz = tz;
+            A.tp.n_tiles = ntx * nty * ntz;
+            A.tp.itx = (Real)(1.0 / tx);
+            A.tp.ity = (Real)(1.0 / ty);
+            A.tp.itz = (Real)(1.0 / tz);
+            A.tp.T.nx = ntx;
+            A.tp.T.ny = nty;
+            A.tp.T.nz = ntz;
+            A.tp.T.nxy = ntx * nty;
+            A.tp.T.dx = (Real)(grid->dx * tx);
+            A.tp.T.dy = (Real)(grid->dy * ty);
+            A.tp.T.dz = (Real)(grid->dz * tz);
+            A.tp.T.idx = (Real)(1.0 / (grid->dx * tx));
+            A.tp.T.idy = (Real)(1.0 / (grid->dy * ty));
+            A.tp.T.idz = (Real)(1.0 / (grid->dz * tz));
+        }
+    }
     CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
@@ -253,11 +465,29 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         grid_blocks = (int)((trace_count + BLOCK - 1) / BLOCK);
     } else {
         const int64_t full = (int64_t)n_cu * (per_cu > 0 ? per_cu : 1);
-        const int64_t need = (int64_t)((prm->n_photons + BLOCK - 1) / BLOCK);
-        grid_blocks = (int)(need < full ? need : full);
+        grid_blocks = (int)(need_blocks < full ? need_blocks : full);
     }
-    if (grid_blocks > 0 && (mode == MODE_TRACE || prm->n_photons > 0))
+    if (A.tape && prm->n_photons > 0) {
+        std::memset(host_counters, 0, sizeof(host_counters));
+        rc = run_tape<Real>(A, tally, prm->n_photons, prm->photon_offset, prm->tape_limit,
+                            (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
+                            stream);
+        if (rc == TAPE_FALLBACK) {
+            // tape too small for the resident wavefronts: device atomics
+            rc = MC_OK;
+            A.tape = 0;
+            CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));
+            const int64_t full = (int64_t)n_cu * (per_cu > 0 ? per_cu : 1);
+            grid_blocks = (int)(need_blocks < full ? need_blocks : full);
+            CHECK_HIP(launch_transport<Real>(A, mode, tally, grid_blocks, stream));
+        } else if (rc != MC_OK) {
+            goto done;
+        } else {
+            tape_counts = true;
+        }
+    } else if (grid_blocks > 0 && (mode == MODE_TRACE || prm->n_photons > 0)) {
         CHECK_HIP(launch_transport<Real>(A, mode, tally, grid_blocks, stream));
+    }
 
     if (mode == MODE_RENDER) {
         if (k32) CHECK_HIP(launch_kahan_reduce(images, A.img32, n_pix, stream));
@@ -268,7 +498,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     }
 
     if (stats || mode == MODE_TRACE) {
-        CHECK_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, stream));
+        if (!tape_counts) {
+            CHECK_HIP(hipMemcpyAsync(host_counters, counters, sizeof(host_counters), hipMemcpyDeviceToHost, stream));
+        }
         CHECK_HIP(hipStreamSynchronize(stream));
         if (stats) {
             stats->photons = mode == MODE_TRACE ? trace_count : prm->n_photons;

@@ -27,17 +27,6 @@ struct HostCam {
     int64_t pix_off;
 };
 
-// One connection ray of the gradient, written by the replay for every tile
-// of the grid the ray crosses (32 bytes).
-struct TapeRec {
-    uint32_t vox;          // start voxel: ix | iy << 11 | iz << 22
-    uint16_t fx, fy, fz;   // start fraction in the voxel, * 65535
-    uint16_t pad_;
-    float vx, vy, vz;      // unit direction to the camera
-    float r;               // length to the camera (km)
-    float a;               // gradient weight dL/di_p * norm_p * C
-};
-
 // Per-pixel normalisation table entry (double).
 struct NormCam {
     double fx, fy, cx, cy;
@@ -50,6 +39,28 @@ struct CamChunk {
     int first, n;
     double dx, dy, dz;  // voxel edges, to express camera centres in voxel units
     HostCam c[CAM_CHUNK];
+};
+
+// Gradient tape of large grids.  The grid is cut into tiles of at most
+// TILE_VOX voxels; the replay writes one record per connection ray and tile
+// the ray crosses, into that tile's slot range [off, off + cap) of the
+// structure-of-arrays below, and the deposit kernel then accumulates each
+// tile's records in LDS.  A slot whose weight a is 0 is empty.
+template <typename Real>
+struct Tape {
+    uint32_t* vox;            // start voxel: ix | iy << 11 | iz << 22
+    Real *fx, *fy, *fz;       // start fraction in the voxel
+    Real *vx, *vy, *vz;       // unit direction to the camera
+    Real* r;                  // length to the camera (km)
+    Real* a;                  // gradient weight dL/di_p * norm_p * C
+    uint32_t* count;          // [n_tiles] slots handed out (may exceed cap)
+    const uint32_t* off;      // [n_tiles]
+    const uint32_t* cap;      // [n_tiles]
+    uint32_t* overflow;       // set when a tile ran out of slots
+    uint32_t block;           // slots a wavefront reserves at a time
+    int tx, ty, tz, n_tiles;  // tile edges in voxels
+    Real itx, ity, itz;       // 1 / tile edges
+    DevGrid<Real> T;          // grid of tiles (edges in km)
 };
 
 template <typename Real>
@@ -75,11 +86,8 @@ struct KArgs {
     const uint32_t* mask;
     int mshx, mshy, mshz, mncx, mncy, mask_words, mask_fine;
     int grad_lds;               // gradient privatised in LDS (small grids)
-    // gradient tape (large grids): one bin of bin_cap records per tile
-    TapeRec* tape;
-    unsigned long long* bin_count;
-    int64_t bin_cap;
-    int tx, ty, tz, ntx, nty, ntz;  // tile edge (voxels) and tiles per axis
+    int tape;                   // gradient through the tape (large grids)
+    Tape<Real> tp;
     // trace
     uint64_t first_pid;
     uint32_t trace_count, max_rec;
@@ -90,13 +98,14 @@ struct KArgs {
 
 constexpr int MASK_WORDS = 8192;  // 32 KB of LDS: up to 262144 cells
 constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)
+constexpr int MAX_TAPE_TILES = 640;
 constexpr int DEPOSIT_BLOCK = 1024;
 
-// Work item of the deposit kernel: a record range of one tile's bin.
+// Work item of the deposit kernel: slots [lo, hi) of one tile's range.
 struct DepositItem {
-    int tile;
-    int pad_;
-    int64_t lo, hi;
+    int32_t tile;
+    uint32_t lo, hi;
+    uint32_t pad_;
 };
 constexpr int64_t GRAD_LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a privatised gradient
 
@@ -112,6 +121,7 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_normalize(double* img, const NormCam* cams, int n_cams, int64_t n_pix, double base, int power,
                             hipStream_t s);
 hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams, int n_cams, int64_t n_pix,

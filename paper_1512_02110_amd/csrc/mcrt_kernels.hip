@@ -24,6 +24,11 @@
 // contribution C to pixel p scatters the surrogate gradient (Sec. 5.2,
 // Eqs. Jaco1, TcofJaco1, DivTc for one event): grad[k_e] += a / beta(k_e)
 // and, walking the ray again, grad[m] -= a l(m), with a = dL/di_p norm_p C.
+// Small grids accumulate this in a per-workgroup LDS copy of the gradient.
+// Large grids write the ray to a tape instead, once per gradient tile it
+// crosses, and k_deposit accumulates every tile's rays in LDS: a device-scope
+// atomic add per voxel crossing would run at the memory-side atomic rate,
+// far below the walk.
 //
 // k_trace: one photon per lane, the same transport, recording events.
 #include "mcrt_internal.hpp"
@@ -434,9 +439,12 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
 
 // Tally of a finished ray.  For the gradient, a finished first walk with a
 // non-zero weight starts the second walk (returns true: the lane stays busy).
+//
+// With the tape, a ray with a non-zero weight instead starts a walk over the
+// grid of tiles (emit: its records are written by emit_records).
 template <typename Real, int MODE, int TALLY>
 __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J,
-                                           uint64_t& vconn) {
+                                           uint64_t& vconn, bool& emit) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     vconn += J.steps;
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
@@ -447,6 +455,20 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
     } else {
         const double a = A.gw[J.pix] * C;
         if (a == 0.0) return false;
+        if (A.tape) {
+            const Tape<Real>& P = A.tp;
+            const int tix = J.i0x / P.tx, tiy = J.i0y / P.ty, tiz = J.i0z / P.tz;
+            const Real ftx = ((Real)(J.i0x - tix * P.tx) + J.f0x) * P.itx;
+            const Real fty = ((Real)(J.i0y - tiy * P.ty) + J.f0y) * P.ity;
+            const Real ftz = ((Real)(J.i0z - tiz * P.tz) + J.f0z) * P.itz;
+            if (!walk_begin(J.W, P.T, tix, tiy, tiz, ftx, fty, ftz, J.vx, J.vy, J.vz)) {
+                // only the start tile
+                J.W.tx = J.W.ty = J.W.tz = (Real)INFINITY;
+            }
+            J.a = a;
+            emit = true;
+            return false;
+        }
         const int ke = J.i0x + A.G.nx * J.i0y + A.G.nxy * J.i0z;
         grad_add<Real, TALLY>(A, lds_grad, ke, a / (double)A.beta[ke]);
         J.a = a;
@@ -456,17 +478,83 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
     }
 }
 
+// Tape records of the rays whose lanes have `emit` set: one record per lane
+// and step, for the tile the lane's tile walk is in, then the walk moves to
+// the next tile.  Slots are handed out per wavefront: `tab` (LDS, private to
+// the wavefront) holds for every tile the base, the used count and the size
+// of the block of slots the wavefront reserved last.  Appends take positions
+// with LDS atomics; the first lane past the end of a block reserves the next
+// one from the tile's device counter (one device atomic per block, not per
+// record).  A reservation beyond the tile's capacity sets the overflow flag
+// and its records are dropped (the host then replays the chunk smaller).
+template <typename Real>
+__device__ __forceinline__ void emit_records(const KArgs<Real>& A, uint32_t* tab, Job<Real>& J, bool& emit) {
+    const Tape<Real>& P = A.tp;
+    uint32_t* t_base = tab;
+    uint32_t* t_used = tab + P.n_tiles;
+    uint32_t* t_size = tab + 2 * P.n_tiles;
+    while (__ballot(emit)) {
+        const int t = emit ? J.W.k : 0;
+        uint32_t pos = 0, base = 0, size = 0;
+        if (emit) {
+            pos = atomicAdd(&t_used[t], 1u);
+            base = t_base[t];
+            size = t_size[t];
+        }
+        const bool spill = emit && pos >= size;
+        if (__ballot(spill)) {
+            if (spill && pos == size) {
+                // positions of one tile are consecutive from the used count,
+                // which never exceeds the size: exactly one lane per tile
+                // lands on the end of the block
+                const uint32_t n_sp = t_used[t] - size;
+                const uint32_t need = n_sp > P.block ? n_sp : P.block;
+                const uint32_t nb = atomicAdd(&P.count[t], need);
+                if ((uint64_t)nb + need > (uint64_t)P.cap[t]) P.overflow[0] = 1u;
+                t_base[t] = nb;
+                t_used[t] = n_sp;
+                t_size[t] = need;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (spill) {
+                base = t_base[t];
+                pos -= size;
+            }
+        }
+        if (emit) {
+            const uint32_t slot = base + pos;
+            if (slot < P.cap[t]) {
+                const uint32_t i = P.off[t] + slot;
+                P.vox[i] = (uint32_t)J.i0x | ((uint32_t)J.i0y << 11) | ((uint32_t)J.i0z << 22);
+                P.fx[i] = J.f0x;
+                P.fy[i] = J.f0y;
+                P.fz[i] = J.f0z;
+                P.vx[i] = J.vx;
+                P.vy[i] = J.vy;
+                P.vz[i] = J.vz;
+                P.r[i] = J.r;
+                P.a[i] = (Real)J.a;
+            }
+            bool cx, cy, cz;
+            const Real tn = walk_next(J.W, cx, cy, cz);
+            if (tn >= J.r || walk_cross(J.W, P.T, tn, cx, cy, cz)) emit = false;
+        }
+    }
+}
+
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
 template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
+__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, uint32_t* tab,
                                       JobQueue<Real>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
                                       bool& fin, bool final_pass, uint64_t& vconn) {
     for (;;) {
+        bool emit = false;
         if (fin) {
             fin = false;
-            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn);
+            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn, emit);
         }
+        if (MODE == MODE_GRAD && A.tape) emit_records(A, tab, J, emit);
         const uint32_t count = qtail - qhead;
         const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
         if (final_pass ? (count + nbusy == 0) : (count + nbusy < (uint32_t)WAVE)) break;
@@ -509,7 +597,8 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 }
 
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
-// the gradient is privatised, one double per voxel.
+// the gradient is privatised, one double per voxel, or with the tape, every
+// wavefront's slot table (3 words per tile).
 template <typename Real, int MODE, int TALLY>
 __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
     __shared__ JobQueue<Real> s_q[WAVES];
@@ -517,9 +606,16 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
     extern __shared__ uint32_t s_dyn[];
     uint32_t* s_mask = s_dyn;
     double* lds_grad = nullptr;
+    uint32_t* tab = nullptr;
     if (MODE == MODE_GRAD && A.grad_lds) {
         lds_grad = reinterpret_cast<double*>(s_dyn + ((A.mask_words + 1) & ~1));
         for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) lds_grad[i] = 0.0;
+    }
+    if (MODE == MODE_GRAD && A.tape) {
+        uint32_t* all = s_dyn + ((A.mask_words + 1) & ~1);
+        // used = size = 0: the first append to a tile reserves a block
+        for (int i = threadIdx.x; i < WAVES * 3 * A.tp.n_tiles; i += BLOCK) all[i] = 0u;
+        tab = all + (threadIdx.x / WAVE) * 3 * A.tp.n_tiles;
     }
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
     for (int i = threadIdx.x; i < A.mask_words; i += BLOCK) s_mask[i] = A.mask[i];
@@ -582,7 +678,7 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn);
+                    drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, false, vconn);
             }
         }
         if (collided) {
@@ -592,9 +688,9 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn);
+        drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, false, vconn);
     }
-    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn);
+    drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, true, vconn);
 
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
     if (n_le) atomicAdd(&s_st[ST_LE], (unsigned long long)n_le);
@@ -606,6 +702,126 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
         for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) {
             const double v = lds_grad[i];
             if (v != 0.0) tally_f64<TALLY>(A.grad, A.grad32, i, v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gradient deposit of one tile: the block accumulates in LDS, for the tape
+// slots [lo, hi) of its tile, -a l(m) along every recorded ray inside the
+// tile and a / beta(k_e) for the rays that start in it, then adds the tile
+// to the gradient (one device atomic per touched voxel).
+
+// Start the walk of the tape record in slot i (tile-local coordinates; the
+// walk's linear index is the LDS index).  False when the record is empty or
+// the ray has no length inside the tile.
+template <typename Real>
+__device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
+                                              uint32_t i, double* s_g, WalkRegs<Real>& W, Real& len, double& a) {
+    const Tape<Real>& P = A.tp;
+    const Real ar = P.a[i];
+    if (ar == (Real)0) return false;
+    a = (double)ar;
+    const uint32_t v = P.vox[i];
+    const int i0x = (int)(v & 2047u), i0y = (int)((v >> 11) & 2047u), i0z = (int)(v >> 22);
+    const Real f0x = P.fx[i], f0y = P.fy[i], f0z = P.fz[i];
+    const Real vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const Real r = P.r[i];
+    const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
+    if ((unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz) {
+        const int ke = i0x + A.G.nx * i0y + A.G.nxy * i0z;
+        atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), a / (double)A.beta[ke]);
+    }
+    // clip [0, r] to the tile box, in tile-local voxel units (double)
+    const double o[3] = {(double)jx + (double)f0x, (double)jy + (double)f0y, (double)jz + (double)f0z};
+    const double u[3] = {(double)vx / (double)L.dx, (double)vy / (double)L.dy, (double)vz / (double)L.dz};
+    const int e[3] = {L.nx, L.ny, L.nz};
+    double t0 = 0.0, t1 = (double)r;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (u[ax] > 1e-300 || u[ax] < -1e-300) {
+            const double ta = (0.0 - o[ax]) / u[ax], tb = ((double)e[ax] - o[ax]) / u[ax];
+            t0 = fmax(t0, fmin(ta, tb));
+            t1 = fmin(t1, fmax(ta, tb));
+        } else if (!(o[ax] >= 0.0 && o[ax] <= (double)e[ax])) {
+            return false;
+        }
+    }
+    if (!(t1 > t0)) return false;
+    int j[3];
+    Real f[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        const double p = o[ax] + t0 * u[ax];
+        double fl = floor(p);
+        fl = fl < 0.0 ? 0.0 : (fl > (double)(e[ax] - 1) ? (double)(e[ax] - 1) : fl);
+        double fr = p - fl;
+        fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
+        j[ax] = (int)fl;
+        f[ax] = (Real)fr;
+    }
+    if (!walk_begin(W, L, j[0], j[1], j[2], f[0], f[1], f[2], vx, vy, vz)) return false;
+    len = (Real)(t1 - t0);
+    return true;
+}
+
+template <typename Real, int TALLY>
+__global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const DepositItem* items) {
+    __shared__ double s_g[TILE_VOX];
+    __shared__ uint32_t s_next;
+    const Tape<Real>& P = A.tp;
+    const DepositItem it = items[blockIdx.x];
+    const int tix = it.tile % P.T.nx, tiy = (it.tile / P.T.nx) % P.T.ny, tiz = it.tile / P.T.nxy;
+    const int b0x = tix * P.tx, b0y = tiy * P.ty, b0z = tiz * P.tz;
+    DevGrid<Real> L = A.G;
+    L.nx = min(P.tx, A.G.nx - b0x);
+    L.ny = min(P.ty, A.G.ny - b0y);
+    L.nz = min(P.tz, A.G.nz - b0z);
+    L.nxy = L.nx * L.ny;
+    const int nloc = L.nxy * L.nz;
+    for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
+    if (threadIdx.x == 0) s_next = it.lo;
+    __syncthreads();
+
+    const uint32_t base = P.off[it.tile];
+    WalkRegs<Real> W;
+    Real len = (Real)0;
+    double a = 0.0;
+    bool busy = false, more = true;
+    for (;;) {
+        if (more) {
+            // idle lanes take the next slots of the block's range
+            const unsigned long long idle = __ballot(!busy);
+            if (idle) {
+                const int leader = __ffsll((long long)idle) - 1;
+                uint32_t first = 0;
+                if (__lane_id() == leader) first = atomicAdd(&s_next, (uint32_t)__popcll(idle));
+                first = __shfl(first, leader);
+                if (first >= it.hi) more = false;
+                if (!busy) {
+                    const uint32_t s = first + lanes_below(idle);
+                    if (s < it.hi) busy = deposit_begin(A, L, b0x, b0y, b0z, base + s, s_g, W, len, a);
+                }
+            }
+        }
+        if (!more && __ballot(busy) == 0ull) break;
+        const uint32_t keep = more ? (uint32_t)WAVE - REFILL_IDLE : 0u;
+        while ((uint32_t)__popcll(__ballot(busy)) > keep) {
+            if (busy) {
+                bool cx, cy, cz;
+                const Real tn = walk_next(W, cx, cy, cz);
+                const bool last = tn >= len;
+                const Real l = (last ? len : tn) - W.t;
+                atomicAdd(s_g + W.k, -a * (double)l);
+                if (walk_cross(W, L, tn, cx, cy, cz) || last) busy = false;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) {
+        const double v = s_g[i];
+        if (v != 0.0) {
+            const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / L.nxy;
+            tally_f64<TALLY>(A.grad, A.grad32, (int64_t)(b0x + x) + (int64_t)A.G.nx * (b0y + y) +
+                                                   (int64_t)A.G.nxy * (b0z + z), v);
         }
     }
 }
@@ -724,6 +940,10 @@ __global__ void k_fill_f32(float* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0f;
 }
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
 
 // Solid angle of a pixel: the rectangle [x1,x2] x [y1,y2] on the unit-focal
 // plane subtends F(x2,y2) - F(x1,y2) - F(x2,y1) + F(x1,y1) with
@@ -809,6 +1029,7 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
     size_t words = (size_t)((a.mask_words + 1) & ~1);
     size_t bytes = words * sizeof(uint32_t);
     if (mode == MODE_GRAD && a.grad_lds) bytes += (size_t)a.n_vox * sizeof(double);
+    if (mode == MODE_GRAD && a.tape) bytes += (size_t)WAVES * 3 * a.tp.n_tiles * sizeof(uint32_t);
     return bytes;
 }
 
@@ -854,6 +1075,18 @@ hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipS
     return hipGetLastError();
 }
 
+template <typename Real>
+hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (tally == TALLY_F64)
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_F64>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+    else
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_K32>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+    return hipGetLastError();
+}
+
+template hipError_t launch_deposit<float>(const KArgs<float>&, int, const DepositItem*, int, hipStream_t);
+template hipError_t launch_deposit<double>(const KArgs<double>&, int, const DepositItem*, int, hipStream_t);
 template hipError_t launch_build_mask<float>(const KArgs<float>&, uint32_t*, int, hipStream_t);
 template hipError_t launch_build_mask<double>(const KArgs<double>&, uint32_t*, int, hipStream_t);
 template hipError_t launch_write_cams<float>(const CamChunk&, DevCam<float>*, NormCam*, hipStream_t);
@@ -876,6 +1109,11 @@ hipError_t launch_fill_f64(double* p, int64_t n, hipStream_t s) {
 hipError_t launch_fill_f32(float* p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n)), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
 hipError_t launch_normalize(double* img, const NormCam* cams, int n_cams, int64_t n_pix, double base, int power,

@@ -43,7 +43,7 @@ class McParams(C.Structure):
                 ("sun_azimuth", C.c_double), ("rr_weight", C.c_double),
                 ("n_photons", C.c_uint64), ("seed", C.c_uint64), ("photon_offset", C.c_uint64),
                 ("n_photons_norm", C.c_uint64), ("max_events", C.c_uint32),
-                ("transport", C.c_int32), ("tally", C.c_int32), ("pad_", C.c_int32)]
+                ("transport", C.c_int32), ("tally", C.c_int32), ("tape_limit", C.c_int32)]
 
 
 STAT_FIELDS = ["photons", "events", "le_jobs", "vox_free", "vox_conn", "esc_top", "esc_bottom",
@@ -126,11 +126,11 @@ def make_cameras(cameras):
 
 
 def make_params(s, n_photons=None, seed=None, photon_offset=0, n_photons_norm=0,
-                max_events=100000, rr_weight=0.1, transport="fp32", tally="f64") -> McParams:
+                max_events=100000, rr_weight=0.1, transport="fp32", tally="f64", tape_limit=0) -> McParams:
     return McParams(float(s.albedo), float(s.g), float(s.sun_zenith), float(s.sun_azimuth),
                     float(rr_weight), int(s.n_photons if n_photons is None else n_photons),
                     int(s.seed if seed is None else seed), int(photon_offset), int(n_photons_norm),
-                    int(max_events), TRANSPORTS[transport], TALLIES[tally], 0)
+                    int(max_events), TRANSPORTS[transport], TALLIES[tally], int(tape_limit))
 
 
 def n_pixels(s) -> int:
