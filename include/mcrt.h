@@ -30,9 +30,11 @@
  *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the legacy
  *     default stream).  The call returns without waiting unless `stats` is
  *     non-NULL, in which case it waits for the stream and fills *stats.
- *   - The library allocates its own small scratch (counters, the camera
- *     table, per-pixel weights) stream-ordered on `hip_stream` and releases
- *     it stream-ordered before returning.
+ *   - The library allocates its own scratch (counters, the camera table,
+ *     per-pixel weights and, for mc_grad_beta on large grids, the ray tape
+ *     bounded by params->tape_limit) stream-ordered on `hip_stream` and
+ *     releases it stream-ordered before returning.
+ *   - 1 <= n_cams <= 65535; the pixels of all cameras number < 2^31.
  *   - Return value: MC_OK (0) or a negative MC_ERR_* code; the library never
  *     prints or aborts.  On an argument error nothing is enqueued.  On
  *     MC_ERR_HIP the contents of output arrays are unspecified.
@@ -156,7 +158,13 @@ int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const m
  * 2 (i - i_measured) times any pixel mask).  The events are those of
  * mc_render with the same grid, beta, cameras and params (same seed and
  * photon range).
- * grad_beta: device array of nx*ny*nz doubles, overwritten. */
+ * grad_beta: device array of nx*ny*nz doubles, overwritten.
+ * Grids of more than about 7000 voxels (an FP64 gradient too large for a
+ * per-workgroup LDS copy) are cut into tiles of at most 16384 voxels: the
+ * photons are replayed in chunks whose connection rays are written to a
+ * tape, once per tile crossed, then accumulated tile by tile in LDS.  Such
+ * a call waits for the stream after every chunk (it reads back the tape's
+ * fill to size the next chunk), whether or not stats is NULL. */
 int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
                  const mc_params* params, const double* dl_dimages, double* grad_beta,
                  mc_stats* stats, void* hip_stream);

@@ -39,7 +39,8 @@ int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* ca
     // the local-estimate queue packs a voxel as 11 + 11 + 10 bits
     if (g->nx > 2048 || g->ny > 2048 || g->nz > 1024) return MC_ERR_INVALID_ARG;
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dz)) return MC_ERR_INVALID_ARG;
-    if (n_cams < 1) return MC_ERR_INVALID_ARG;
+    // camera indices travel as 16-bit values through the job queue
+    if (n_cams < 1 || n_cams > 65535) return MC_ERR_INVALID_ARG;
     int64_t npix = 0;
     for (int i = 0; i < n_cams; ++i) {
         const mc_camera& c = cams[i];
@@ -95,141 +96,111 @@ struct Scratch {
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Tile edges of the gradient tape: columns of at most 64 voxels in z and
-// TILE_VOX voxels in all (connection rays to cameras below or above the
-// cloud are closer to vertical than to horizontal, so tall tiles are crossed
-// by fewer rays more than once).
-void tape_tiles(const mc_grid* g, int& tx, int& ty, int& tz) {
-    tz = g->nz < 64 ? g->nz : 64;
-    const int txy = (int)std::floor(std::sqrt((double)TILE_VOX / tz));
-    tx = g->nx < txy ? g->nx : txy;
-    ty = TILE_VOX / (tz * tx);
-    if (ty > g->ny) ty = g->ny;
+// Tile edges of the gradient tape, as powers of two (so that the tile of a
+// voxel is a shift away): columns of at most 64 voxels in z and TILE_VOX
+// voxels in all.  Connection rays to cameras below or above the cloud are
+// closer to vertical than to horizontal, so tall tiles are crossed by fewer
+// rays more than once.
+int ceil_log2(int n) {
+    int s = 0;
+    while ((1 << s) < n) ++s;
+    return s;
+}
+
+void tape_tiles(const mc_grid* g, int& shx, int& shy, int& shz) {
+    const int total = ceil_log2(TILE_VOX);
+    shz = std::min(6, ceil_log2(g->nz));
+    const int rest = total - shz;
+    shx = std::min(ceil_log2(g->nx), (rest + 1) / 2);
+    shy = std::min(ceil_log2(g->ny), rest - shx);
+    if (shy < rest - shx) shx = std::min(ceil_log2(g->nx), rest - shy);
 }
 
 constexpr int TAPE_FALLBACK = 1;
 
-// Gradient of a large grid through the tape, in chunks of photons whose
-// records fit the tape: replay a chunk (k_render writes the records of its
-// connection rays), read back the tiles' slot counts, then deposit every
-// tile's records (k_deposit).  A chunk whose records overflowed a tile is
-// replayed smaller before anything of it reaches the gradient.  The slot
-// capacity of every tile follows the slot demand per photon measured on the
-// chunks so far.  Stats of the successful chunks are summed into host_sum.
+// Gradient of a large grid through the tape, in chunks of photons:
+//   1. replay the chunk (k_render, MODE_TAPE): every wavefront writes the
+//      connection rays with a non-zero weight to its slice of the ray tape;
+//   2. count the rays crossing each tile (k_bin, count pass) and read the
+//      counts back;
+//   3. for groups of tiles whose bins fit the bin space: copy the rays into
+//      the bins (k_bin, scatter pass) and deposit every tile (k_deposit).
+// A chunk whose rays overflowed a wavefront slice, or with a tile bin larger
+// than the bin space, is replayed smaller before anything of it reaches the
+// gradient.  Chunks are sized from the rays per photon of the busiest
+// wavefront of the chunks so far.  Stats of the completed chunks are summed
+// into host_sum.
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, hipStream_t stream) {
     int rc = MC_OK;
     const int nt = A.tp.n_tiles;
-    const size_t rec = sizeof(uint32_t) + 8 * sizeof(Real);
-    uint64_t waves = (uint64_t)max_blocks * (BLOCK / 64);
+    const size_t rec = sizeof(TapeRec<Real>);
+    const int wpb = BLOCK / 64;  // wavefronts per block
     size_t free_b = 0, total_b = 0;
     char* pool = nullptr;
-    uint32_t* meta = nullptr;  // count[nt], overflow, off[nt], cap[nt]
+    uint32_t* meta = nullptr;  // tile_count[nt], cursor[nt], tile_end[nt], overflow, wave_count[]
     DepositItem* ditems = nullptr;
-    const int max_items = nt + 2 * n_cu + 1;
-    std::vector<uint32_t> h_offcap(2 * (size_t)nt), h_count(nt + 1);
+    const int max_items = nt + 4 * n_cu + 1;
+    std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt), h_wave((size_t)max_blocks * wpb);
     std::vector<DepositItem> h_items;
-    std::vector<double> demand(nt, 0.0);
-    double seen = 0.0;
     unsigned long long h_ctr[1 + ST_N];
-    uint64_t P = 0, done = 0, chunk = 0, slack = 0;
-    size_t off = 0;
+    uint32_t h_over = 0;
+    uint64_t P = 0, r_cap = 0, b_cap = 0, done = 0, chunk = 0;
 
     CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
     {
-        const uint64_t lim = std::min<uint64_t>(free_b / 4, (uint64_t)16 << 30) / rec;
-        P = std::max<uint64_t>(n_photons * 64, std::max<uint64_t>(32 * waves * (uint64_t)nt, (uint64_t)1 << 20));
+        const uint64_t lim = std::min<uint64_t>(free_b / 4, (uint64_t)32 << 30) / rec;
+        P = std::max<uint64_t>(n_photons * 48, (uint64_t)1 << 20);
         P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
         if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
     }
-    // every resident wavefront may hold a partly used block of slots in
-    // every tile: keep that slack within half of the tape, with fewer
-    // resident blocks if the tape is small
-    A.tp.block = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, P / (16 * waves * (uint64_t)nt)));
-    if (2 * waves * A.tp.block * (uint64_t)nt > P) {
-        max_blocks = (int)std::max<uint64_t>(1, P / (2 * (uint64_t)nt * (BLOCK / 64)));
-        if (max_blocks > n_cu * 64) max_blocks = n_cu * 64;
-        waves = (uint64_t)max_blocks * (BLOCK / 64);
-    }
-    if (2 * waves * A.tp.block * (uint64_t)nt > P) return TAPE_FALLBACK;
-    slack = waves * A.tp.block;
+    // half for the rays, half for the bins; at least 64 ray slots per
+    // wavefront (fewer resident blocks if the tape is small)
+    r_cap = P / 2;
+    b_cap = P - r_cap;
+    if (r_cap < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_cap / (64 * (uint64_t)wpb));
+    if (max_blocks < 1 || b_cap < 64) return TAPE_FALLBACK;
 
-    CHECK_HIP(hipMallocAsync((void**)&pool, P * rec + 16 * 256, stream));
-    CHECK_HIP(hipMallocAsync((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + 1), stream));
+    CHECK_HIP(hipMallocAsync((void**)&pool, P * rec, stream));
+    CHECK_HIP(hipMallocAsync((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_blocks * wpb),
+                             stream));
     CHECK_HIP(hipMallocAsync((void**)&ditems, sizeof(DepositItem) * max_items, stream));
-    {
-        auto take = [&](size_t bytes) {
-            char* p = pool + off;
-            off += (bytes + 255) & ~(size_t)255;
-            return p;
-        };
-        A.tp.vox = reinterpret_cast<uint32_t*>(take(P * sizeof(uint32_t)));
-        Real** fields[8] = {&A.tp.fx, &A.tp.fy, &A.tp.fz, &A.tp.vx, &A.tp.vy, &A.tp.vz, &A.tp.r, &A.tp.a};
-        for (Real** f : fields) *f = reinterpret_cast<Real*>(take(P * sizeof(Real)));
-    }
-    A.tp.count = meta;
-    A.tp.overflow = meta + nt;
-    A.tp.off = meta + nt + 1;
-    A.tp.cap = meta + 2 * nt + 1;
+    A.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool);
+    A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + r_cap;
+    A.tp.tile_count = meta;
+    A.tp.cursor = meta + nt;
+    A.tp.tile_end = meta + 2 * nt;
+    A.tp.overflow = meta + 3 * nt;
+    A.tp.wave_count = meta + 3 * nt + 1;
 
-    // first chunk: equal capacities and a guess of 64 slots per photon
-    chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, P / (64 * (uint64_t)nt) / 4));
+    // first chunk: a guess of 64 rays per photon
+    chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, r_cap / 64));
     while (done < n_photons) {
-        uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
-        double rate_sum = 0.0;
-        for (int i = 0; i < nt; ++i) rate_sum += seen > 0.0 ? demand[i] / seen : 0.0;
-        if (rate_sum > 0.0) {
-            const double room = (double)P - (double)nt * (double)slack;
-            const double fit = std::floor(room / (1.25 * rate_sum));
-            if (fit < 1.0) {
-                rc = MC_ERR_OUT_OF_MEMORY;
-                goto done;
-            }
-            if ((double)n > fit) n = (uint64_t)fit;
-            double used = 0.0;
-            std::vector<double> c(nt);
-            for (int i = 0; i < nt; ++i) {
-                c[i] = 1.25 * demand[i] / seen * (double)n + (double)slack;
-                used += c[i];
-            }
-            uint64_t o = 0;
-            for (int i = 0; i < nt; ++i) {
-                // spread what is left of the tape in proportion to the demand
-                const double extra = ((double)P - used) * (demand[i] / seen) / rate_sum;
-                uint64_t cap = (uint64_t)std::floor(c[i] + (extra > 0.0 ? extra : 0.0));
-                if (o + cap > P) cap = P - o;
-                h_offcap[i] = (uint32_t)o;
-                h_offcap[nt + i] = (uint32_t)cap;
-                o += cap;
-            }
-        } else {
-            for (int i = 0; i < nt; ++i) {
-                h_offcap[i] = (uint32_t)(P / nt * i);
-                h_offcap[nt + i] = (uint32_t)(P / nt);
-            }
-        }
-        CHECK_HIP(hipMemcpyAsync(meta + nt + 1, h_offcap.data(), sizeof(uint32_t) * 2 * nt, hipMemcpyHostToDevice,
-                                 stream));
-        CHECK_HIP(launch_fill_u32(meta, nt + 1, stream));
-        CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
-        if (sizeof(Real) == 4)
-            CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(A.tp.a), (int64_t)P, stream));
-        else
-            CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(A.tp.a), (int64_t)P, stream));
+        const uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
+        const int grid = (int)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, (uint64_t)max_blocks);
+        const int nw = grid * wpb;
+        A.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / nw, 0xffffffffu);
         A.pid0 = pid0 + done;
         A.n_photons = n;
-        {
-            const uint64_t need = (n + BLOCK - 1) / BLOCK;
-            const int grid = (int)std::min<uint64_t>(need, (uint64_t)max_blocks);
-            CHECK_HIP(launch_transport<Real>(A, MODE_GRAD, tally, grid, stream));
-        }
-        CHECK_HIP(hipMemcpyAsync(h_count.data(), meta, sizeof(uint32_t) * (nt + 1), hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
+        CHECK_HIP(launch_fill_u32(A.tp.overflow, 1, stream));
+        CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
+        CHECK_HIP(launch_transport<Real>(A, MODE_TAPE, TALLY_F64, grid, stream));
+        CHECK_HIP(launch_bin<Real>(A, false, nw, stream));
+        CHECK_HIP(hipMemcpyAsync(h_count.data(), A.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost,
+                                 stream));
+        CHECK_HIP(hipMemcpyAsync(&h_over, A.tp.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipMemcpyAsync(h_wave.data(), A.tp.wave_count, sizeof(uint32_t) * nw, hipMemcpyDeviceToHost,
+                                 stream));
         CHECK_HIP(hipMemcpyAsync(h_ctr, counters, sizeof(h_ctr), hipMemcpyDeviceToHost, stream));
         CHECK_HIP(hipStreamSynchronize(stream));
-        for (int i = 0; i < nt; ++i) demand[i] += (double)h_count[i];
-        seen += (double)n;
-        if (h_count[nt]) {
+        uint32_t busiest = 0;
+        for (int w = 0; w < nw; ++w) busiest = std::max(busiest, h_wave[w]);
+        const double rate = (double)busiest * nw / (double)n;  // rays per photon, busiest wavefront
+        bool too_big = h_over != 0;
+        for (int i = 0; i < nt; ++i) too_big = too_big || h_count[i] > b_cap;
+        if (too_big) {
             if (n == 1) {
                 rc = MC_ERR_OUT_OF_MEMORY;
                 goto done;
@@ -238,17 +209,25 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
             continue;
         }
         for (int i = 1; i < 1 + ST_N; ++i) host_sum[i] += h_ctr[i];
-        {
-            uint64_t total = 0;
-            for (int i = 0; i < nt; ++i) total += h_count[i];
-            const uint64_t R = std::max<uint64_t>(8192, (total + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
+        for (int g0 = 0; g0 < nt;) {
+            // the next group of tiles whose bins fit together
+            uint64_t sum = 0;
+            int g1 = g0;
+            while (g1 < nt && g1 - g0 < BIN_GROUP_TILES && sum + h_count[g1] <= b_cap) sum += h_count[g1++];
+            uint32_t o = 0;
+            for (int i = g0; i < g1; ++i) {
+                h_bins[i] = o;
+                h_bins[nt + i] = o + h_count[i];
+                o += h_count[i];
+            }
+            const uint64_t R = std::max<uint64_t>(8192, (sum + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
             h_items.clear();
-            for (int i = 0; i < nt; ++i)
+            for (int i = g0; i < g1; ++i)
                 for (uint64_t lo = 0; lo < h_count[i]; lo += R) {
                     DepositItem d;
                     d.tile = i;
-                    d.lo = (uint32_t)lo;
-                    d.hi = (uint32_t)std::min<uint64_t>(h_count[i], lo + R);
+                    d.lo = h_bins[i] + (uint32_t)lo;
+                    d.hi = h_bins[i] + (uint32_t)std::min<uint64_t>(h_count[i], lo + R);
                     d.pad_ = 0;
                     h_items.push_back(d);
                 }
@@ -256,14 +235,24 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
                 rc = MC_ERR_HIP;
                 goto done;
             }
+            A.tp.t_lo = g0;
+            A.tp.t_hi = g1;
+            CHECK_HIP(hipMemcpyAsync(A.tp.cursor + g0, h_bins.data() + g0, sizeof(uint32_t) * (g1 - g0),
+                                     hipMemcpyHostToDevice, stream));
+            CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.tile_end) + g0, h_bins.data() + nt + g0,
+                                     sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
+            CHECK_HIP(launch_bin<Real>(A, true, nw, stream));
             if (!h_items.empty()) {
                 CHECK_HIP(hipMemcpyAsync(ditems, h_items.data(), sizeof(DepositItem) * h_items.size(),
                                          hipMemcpyHostToDevice, stream));
                 CHECK_HIP(launch_deposit<Real>(A, tally, ditems, (int)h_items.size(), stream));
             }
+            g0 = g1;
+            if (g0 < nt) CHECK_HIP(hipStreamSynchronize(stream));  // host arrays are reused
         }
         done += n;
-        chunk = n_photons - done;  // the next chunk is sized from the demand
+        // next chunk: the busiest wavefront's slice about 80% full
+        chunk = rate > 0.0 ? (uint64_t)std::max(1.0, std::floor(0.8 * (double)r_cap / rate)) : n_photons - done;
     }
     CHECK_HIP(hipStreamSynchronize(stream));
 
@@ -398,14 +387,15 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.grad_lds = mode == MODE_GRAD &&
                  ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
     if (mode == MODE_GRAD && !A.grad_lds) {
-        int tx, ty, tz;
-        tape_tiles(grid, tx, ty, tz);
+        int shx, shy, shz;
+        tape_tiles(grid, shx, shy, shz);
+        const int tx = 1 << shx, ty = 1 << shy, tz = 1 << shz;
         const int ntx = (grid->nx + tx - 1) / tx, nty = (grid->ny + ty - 1) / ty, ntz = (grid->nz + tz - 1) / tz;
         if ((int64_t)ntx * nty * ntz <= MAX_TAPE_TILES) {
             A.tape = 1;
-            A.tp.tx = tx;
-            A.tp.ty = ty;
-            A.tp.tz = tz;
+            A.tp.shx = shx;
+            A.tp.shy = shy;
+            A.tp.shz = shz;
             A.tp.n_tiles = ntx * nty * ntz;
             A.tp.itx = (Real)(1.0 / tx);
             A.tp.ity = (Real)(1.0 / ty);
@@ -422,7 +412,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             A.tp.T.idz = (Real)(1.0 / (grid->dz * tz));
         }
     }
-    CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));
+    CHECK_HIP(transport_occupancy<Real>(A, A.tape ? MODE_TAPE : mode, tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
@@ -473,7 +463,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                             (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
                             stream);
         if (rc == TAPE_FALLBACK) {
-            // tape too small for the resident wavefronts: device atomics
+            // tape too small even for one block: device atomics
             rc = MC_OK;
             A.tape = 0;
             CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));

@@ -9,7 +9,7 @@
 
 namespace mcrt {
 
-enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2 };
+enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3 };
 enum { TALLY_F64 = 0, TALLY_K32 = 1 };
 enum {
     ST_PHOTONS = 0, ST_EVENTS, ST_LE, ST_VFREE, ST_VCONN,
@@ -41,25 +41,35 @@ struct CamChunk {
     HostCam c[CAM_CHUNK];
 };
 
-// Gradient tape of large grids.  The grid is cut into tiles of at most
-// TILE_VOX voxels; the replay writes one record per connection ray and tile
-// the ray crosses, into that tile's slot range [off, off + cap) of the
-// structure-of-arrays below, and the deposit kernel then accumulates each
-// tile's records in LDS.  A slot whose weight a is 0 is empty.
+// Gradient tape of large grids.  The replay (MODE_TAPE) writes every
+// connection ray with a non-zero gradient weight to its wavefront's slice of
+// the ray tape; a binning pass copies each ray into the bin of every
+// gradient tile (at most TILE_VOX voxels) it crosses, and the deposit kernel
+// accumulates each tile's bin in LDS.  A record holds the start of the ray
+// and its pixel (ray tape) or camera (bins); direction and length are
+// recomputed from the camera, so that a record fills whole 16-byte words.
+template <typename Real>
+struct alignas(16) TapeRec {
+    uint32_t vox;       // start voxel: ix | iy << 11 | iz << 22
+    uint32_t id;        // pixel (ray tape) or camera index (bins)
+    Real fx, fy, fz;    // start fraction in the voxel
+    Real a;             // gradient weight dL/di_p * norm_p * C
+};
+
 template <typename Real>
 struct Tape {
-    uint32_t* vox;            // start voxel: ix | iy << 11 | iz << 22
-    Real *fx, *fy, *fz;       // start fraction in the voxel
-    Real *vx, *vy, *vz;       // unit direction to the camera
-    Real* r;                  // length to the camera (km)
-    Real* a;                  // gradient weight dL/di_p * norm_p * C
-    uint32_t* count;          // [n_tiles] slots handed out (may exceed cap)
-    const uint32_t* off;      // [n_tiles]
-    const uint32_t* cap;      // [n_tiles]
-    uint32_t* overflow;       // set when a tile ran out of slots
-    uint32_t block;           // slots a wavefront reserves at a time
-    int tx, ty, tz, n_tiles;  // tile edges in voxels
-    Real itx, ity, itz;       // 1 / tile edges
+    TapeRec<Real>* rec;       // rays: wavefront w owns slots [w rw, (w + 1) rw)
+    uint32_t rw;              // ray slots per wavefront
+    uint32_t* wave_count;     // [wavefronts] rays written (more than rw: overflow)
+    uint32_t* overflow;       // set when a wavefront ran out of slots
+    TapeRec<Real>* brec;      // rays binned by tile
+    uint32_t* tile_count;     // [n_tiles] records per tile
+    uint32_t* cursor;         // [n_tiles] next binned slot of each tile
+    const uint32_t* tile_end; // [n_tiles] end of each tile's bin
+    int t_lo, t_hi;           // tiles binned by this pass
+    int shx, shy, shz;        // tile edges are 2^sh voxels
+    int n_tiles;
+    Real itx, ity, itz;       // 1 / tile edges (exact)
     DevGrid<Real> T;          // grid of tiles (edges in km)
 };
 
@@ -98,7 +108,9 @@ struct KArgs {
 
 constexpr int MASK_WORDS = 8192;  // 32 KB of LDS: up to 262144 cells
 constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)
-constexpr int MAX_TAPE_TILES = 640;
+constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: up to 104 KB of LDS
+constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS
+constexpr int BIN_GROUP_TILES = 4096; // tiles per scatter pass (3 LDS words each)
 constexpr int DEPOSIT_BLOCK = 1024;
 
 // Work item of the deposit kernel: slots [lo, hi) of one tile's range.
@@ -129,6 +141,8 @@ hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams
 hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipStream_t s);
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipStream_t s);
+template <typename Real>
+hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s);
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s);
 

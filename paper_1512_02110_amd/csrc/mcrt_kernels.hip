@@ -25,12 +25,15 @@
 // Eqs. Jaco1, TcofJaco1, DivTc for one event): grad[k_e] += a / beta(k_e)
 // and, walking the ray again, grad[m] -= a l(m), with a = dL/di_p norm_p C.
 // Small grids accumulate this in a per-workgroup LDS copy of the gradient.
-// Large grids write the ray to a tape instead, once per gradient tile it
-// crosses, and k_deposit accumulates every tile's rays in LDS: a device-scope
-// atomic add per voxel crossing would run at the memory-side atomic rate,
-// far below the walk.
+// Large grids replay in MODE_TAPE instead: the finished ray goes to a tape,
+// k_bin copies it into the bin of every gradient tile it crosses, and
+// k_deposit accumulates every tile's bin in LDS.  A device-scope atomic add
+// per voxel crossing would run at the memory-side atomic rate, far below the
+// walk.
 //
 // k_trace: one photon per lane, the same transport, recording events.
+#include <algorithm>
+
 #include "mcrt_internal.hpp"
 
 namespace mcrt {
@@ -367,7 +370,7 @@ __device__ __forceinline__ int after_collision(const KArgs<Real>& A, Photon<Real
 // Local-estimate jobs.
 
 // LDS queue of one wavefront (structure of arrays, ring of QCAP entries).
-template <typename Real>
+template <typename Real, int MODE>
 struct JobQueue {
     uint32_t vox[QCAP];  // start voxel packed as ix | iy << 11 | iz << 22
     Real fx[QCAP], fy[QCAP], fz[QCAP];
@@ -389,6 +392,7 @@ struct Job {
     double tau;    // optical depth so far (FP64)
     double a;      // gradient weight of the second walk
     int pix;
+    double gwp;    // gradient weight of the pixel (loaded when the ray starts)
     int phase;     // 1: optical depth, 2: gradient scatter
     uint32_t steps;
     // start of the ray, kept for the second walk of the gradient
@@ -438,13 +442,11 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
 }
 
 // Tally of a finished ray.  For the gradient, a finished first walk with a
-// non-zero weight starts the second walk (returns true: the lane stays busy).
-//
-// With the tape, a ray with a non-zero weight instead starts a walk over the
-// grid of tiles (emit: its records are written by emit_records).
+// non-zero weight starts the second walk (returns true: the lane stays busy);
+// for the tape, such a ray is marked for the tape (rec) instead.
 template <typename Real, int MODE, int TALLY>
 __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J,
-                                           uint64_t& vconn, bool& emit) {
+                                           uint64_t& vconn, bool& rec) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     vconn += J.steps;
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
@@ -452,23 +454,13 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
         tally_f64<TALLY>(A.img, A.img32, J.pix, C);
         if (A.img_m2) unsafeAtomicAdd(A.img_m2 + J.pix, C * C);
         return false;
+    } else if (MODE == MODE_TAPE) {
+        J.a = J.gwp * C;
+        rec = J.a != 0.0;
+        return false;
     } else {
         const double a = A.gw[J.pix] * C;
         if (a == 0.0) return false;
-        if (A.tape) {
-            const Tape<Real>& P = A.tp;
-            const int tix = J.i0x / P.tx, tiy = J.i0y / P.ty, tiz = J.i0z / P.tz;
-            const Real ftx = ((Real)(J.i0x - tix * P.tx) + J.f0x) * P.itx;
-            const Real fty = ((Real)(J.i0y - tiy * P.ty) + J.f0y) * P.ity;
-            const Real ftz = ((Real)(J.i0z - tiz * P.tz) + J.f0z) * P.itz;
-            if (!walk_begin(J.W, P.T, tix, tiy, tiz, ftx, fty, ftz, J.vx, J.vy, J.vz)) {
-                // only the start tile
-                J.W.tx = J.W.ty = J.W.tz = (Real)INFINITY;
-            }
-            J.a = a;
-            emit = true;
-            return false;
-        }
         const int ke = J.i0x + A.G.nx * J.i0y + A.G.nxy * J.i0z;
         grad_add<Real, TALLY>(A, lds_grad, ke, a / (double)A.beta[ke]);
         J.a = a;
@@ -478,83 +470,46 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
     }
 }
 
-// Tape records of the rays whose lanes have `emit` set: one record per lane
-// and step, for the tile the lane's tile walk is in, then the walk moves to
-// the next tile.  Slots are handed out per wavefront: `tab` (LDS, private to
-// the wavefront) holds for every tile the base, the used count and the size
-// of the block of slots the wavefront reserved last.  Appends take positions
-// with LDS atomics; the first lane past the end of a block reserves the next
-// one from the tile's device counter (one device atomic per block, not per
-// record).  A reservation beyond the tile's capacity sets the overflow flag
-// and its records are dropped (the host then replays the chunk smaller).
+// The rays marked by job_finish go to the wavefront's slice of the ray tape,
+// in consecutive slots (one coalesced store per finishing batch; a wait on
+// a later load also waits for these stores, so they are made once per
+// batch, not per tile).  w_used counts the wavefront's rays, also past the
+// end of its slice (the host then replays the chunk smaller).
 template <typename Real>
-__device__ __forceinline__ void emit_records(const KArgs<Real>& A, uint32_t* tab, Job<Real>& J, bool& emit) {
-    const Tape<Real>& P = A.tp;
-    uint32_t* t_base = tab;
-    uint32_t* t_used = tab + P.n_tiles;
-    uint32_t* t_size = tab + 2 * P.n_tiles;
-    while (__ballot(emit)) {
-        const int t = emit ? J.W.k : 0;
-        uint32_t pos = 0, base = 0, size = 0;
-        if (emit) {
-            pos = atomicAdd(&t_used[t], 1u);
-            base = t_base[t];
-            size = t_size[t];
-        }
-        const bool spill = emit && pos >= size;
-        if (__ballot(spill)) {
-            if (spill && pos == size) {
-                // positions of one tile are consecutive from the used count,
-                // which never exceeds the size: exactly one lane per tile
-                // lands on the end of the block
-                const uint32_t n_sp = t_used[t] - size;
-                const uint32_t need = n_sp > P.block ? n_sp : P.block;
-                const uint32_t nb = atomicAdd(&P.count[t], need);
-                if ((uint64_t)nb + need > (uint64_t)P.cap[t]) P.overflow[0] = 1u;
-                t_base[t] = nb;
-                t_used[t] = n_sp;
-                t_size[t] = need;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            if (spill) {
-                base = t_base[t];
-                pos -= size;
-            }
-        }
-        if (emit) {
-            const uint32_t slot = base + pos;
-            if (slot < P.cap[t]) {
-                const uint32_t i = P.off[t] + slot;
-                P.vox[i] = (uint32_t)J.i0x | ((uint32_t)J.i0y << 11) | ((uint32_t)J.i0z << 22);
-                P.fx[i] = J.f0x;
-                P.fy[i] = J.f0y;
-                P.fz[i] = J.f0z;
-                P.vx[i] = J.vx;
-                P.vy[i] = J.vy;
-                P.vz[i] = J.vz;
-                P.r[i] = J.r;
-                P.a[i] = (Real)J.a;
-            }
-            bool cx, cy, cz;
-            const Real tn = walk_next(J.W, cx, cy, cz);
-            if (tn >= J.r || walk_cross(J.W, P.T, tn, cx, cy, cz)) emit = false;
+__device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>& J, bool rec, uint32_t& w_used,
+                                           uint32_t w_first) {
+    const unsigned long long m = __ballot(rec);
+    if (!m) return;
+    if (rec) {
+        const uint32_t pos = w_used + lanes_below(m);
+        if (pos < A.tp.rw) {
+            TapeRec<Real> R;
+            R.vox = (uint32_t)J.i0x | ((uint32_t)J.i0y << 11) | ((uint32_t)J.i0z << 22);
+            R.id = (uint32_t)J.pix;
+            R.fx = J.f0x;
+            R.fy = J.f0y;
+            R.fz = J.f0z;
+            R.a = (Real)J.a;
+            A.tp.rec[w_first + pos] = R;
         }
     }
+    w_used += (uint32_t)__popcll(m);
 }
 
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
 template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, uint32_t* tab,
-                                      JobQueue<Real>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
-                                      bool& fin, bool final_pass, uint64_t& vconn) {
+__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
+                                      JobQueue<Real, MODE>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
+                                      bool& fin, bool final_pass, uint64_t& vconn, uint32_t& w_used,
+                                      uint32_t w_first) {
     for (;;) {
-        bool emit = false;
+        bool rec = false;
         if (fin) {
             fin = false;
-            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn, emit);
+            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn, rec);
         }
-        if (MODE == MODE_GRAD && A.tape) emit_records(A, tab, J, emit);
+        if (MODE == MODE_TAPE) tape_write(A, J, rec, w_used, w_first);
         const uint32_t count = qtail - qhead;
         const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
         if (final_pass ? (count + nbusy == 0) : (count + nbusy < (uint32_t)WAVE)) break;
@@ -578,6 +533,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
                     J.r = Q.r[slot];
                     J.pre = Q.pre[slot];
                     J.pix = Q.pix[slot];
+                    if (MODE == MODE_TAPE) J.gwp = A.gw[J.pix];  // needed when the ray finishes
                     J.phase = 1;
                     job_begin(A, mask, J);
                     busy = true;
@@ -597,31 +553,23 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 }
 
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
-// the gradient is privatised, one double per voxel, or with the tape, every
-// wavefront's slot table (3 words per tile).
+// the gradient is privatised, one double per voxel.
 template <typename Real, int MODE, int TALLY>
 __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
-    __shared__ JobQueue<Real> s_q[WAVES];
+    __shared__ JobQueue<Real, MODE> s_q[WAVES];
     __shared__ unsigned long long s_st[ST_N];
     extern __shared__ uint32_t s_dyn[];
     uint32_t* s_mask = s_dyn;
     double* lds_grad = nullptr;
-    uint32_t* tab = nullptr;
     if (MODE == MODE_GRAD && A.grad_lds) {
         lds_grad = reinterpret_cast<double*>(s_dyn + ((A.mask_words + 1) & ~1));
         for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) lds_grad[i] = 0.0;
-    }
-    if (MODE == MODE_GRAD && A.tape) {
-        uint32_t* all = s_dyn + ((A.mask_words + 1) & ~1);
-        // used = size = 0: the first append to a tile reserves a block
-        for (int i = threadIdx.x; i < WAVES * 3 * A.tp.n_tiles; i += BLOCK) all[i] = 0u;
-        tab = all + (threadIdx.x / WAVE) * 3 * A.tp.n_tiles;
     }
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
     for (int i = threadIdx.x; i < A.mask_words; i += BLOCK) s_mask[i] = A.mask[i];
     __syncthreads();
     const uint32_t* mask = s_mask;
-    JobQueue<Real>& Q = s_q[threadIdx.x / WAVE];
+    JobQueue<Real, MODE>& Q = s_q[threadIdx.x / WAVE];
 
     Photon<Real> ph;
     Job<Real> J;
@@ -629,6 +577,9 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
     uint32_t qhead = 0, qtail = 0;
     uint32_t n_ev = 0, n_le = 0;
     uint64_t vfree = 0, vconn = 0;
+    const uint32_t wave_id = blockIdx.x * WAVES + threadIdx.x / WAVE;
+    const uint32_t w_first = MODE == MODE_TAPE ? wave_id * A.tp.rw : 0u;
+    uint32_t w_used = 0;
 
     for (;;) {
         if (!alive && !exhausted) {
@@ -678,7 +629,7 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, false, vconn);
+                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, w_used, w_first);
             }
         }
         if (collided) {
@@ -688,10 +639,14 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, false, vconn);
+        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, w_used, w_first);
     }
-    drain<Real, MODE, TALLY>(A, mask, lds_grad, tab, Q, qhead, qtail, J, busy, fin, true, vconn);
+    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, w_used, w_first);
 
+    if (MODE == MODE_TAPE && __lane_id() == 0) {
+        A.tp.wave_count[wave_id] = w_used;
+        if (w_used > A.tp.rw) A.tp.overflow[0] = 1u;
+    }
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
     if (n_le) atomicAdd(&s_st[ST_LE], (unsigned long long)n_le);
     if (vfree) atomicAdd(&s_st[ST_VFREE], (unsigned long long)vfree);
@@ -707,33 +662,203 @@ __global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
 }
 
 // ---------------------------------------------------------------------------
-// Gradient deposit of one tile: the block accumulates in LDS, for the tape
-// slots [lo, hi) of its tile, -a l(m) along every recorded ray inside the
+// Binning of the ray tape by gradient tile.
+
+// Ray of a tape record going to camera c: start voxel, unit direction to the
+// camera and length, recomputed as the local estimate formed them.  False
+// for a record outside the grid or the camera table.
+template <typename Real>
+__device__ __forceinline__ bool tape_ray(const KArgs<Real>& A, const TapeRec<Real>& R, uint32_t c, int& ix, int& iy,
+                                         int& iz, Real& vx, Real& vy, Real& vz, Real& r) {
+    ix = (int)(R.vox & 2047u);
+    iy = (int)((R.vox >> 11) & 2047u);
+    iz = (int)(R.vox >> 22);
+    if (ix >= A.G.nx || iy >= A.G.ny || iz >= A.G.nz || c >= (uint32_t)A.n_cams) return false;
+    const DevCam<Real>& cam = A.cams[c];
+    const Real dx = ((Real)(ix - cam.icx) + (R.fx - cam.fcx)) * A.G.dx;
+    const Real dy = ((Real)(iy - cam.icy) + (R.fy - cam.fcy)) * A.G.dy;
+    const Real dz = ((Real)(iz - cam.icz) + (R.fz - cam.fcz)) * A.G.dz;
+    r = m_sqrt(dx * dx + dy * dy + dz * dz);
+    const Real ir = (Real)1 / r;
+    vx = -dx * ir;
+    vy = -dy * ir;
+    vz = -dz * ir;
+    return true;
+}
+
+// Calls f(tile) for every tile the ray crosses, in order (a walk over the
+// grid of tiles; a ray without a usable direction only has its start tile).
+template <typename Real, typename F>
+__device__ __forceinline__ void for_each_tile(const Tape<Real>& P, const TapeRec<Real>& R, int ix, int iy, int iz,
+                                              Real vx, Real vy, Real vz, Real r, F&& f) {
+    WalkRegs<Real> W;
+    const int tix = ix >> P.shx, tiy = iy >> P.shy, tiz = iz >> P.shz;
+    const Real ftx = ((Real)(ix & ((1 << P.shx) - 1)) + R.fx) * P.itx;
+    const Real fty = ((Real)(iy & ((1 << P.shy) - 1)) + R.fy) * P.ity;
+    const Real ftz = ((Real)(iz & ((1 << P.shz) - 1)) + R.fz) * P.itz;
+    if (!walk_begin(W, P.T, tix, tiy, tiz, ftx, fty, ftz, vx, vy, vz)) {
+        f(tix + P.T.nx * tiy + P.T.nxy * tiz);
+        return;
+    }
+    for (;;) {
+        f(W.k);
+        bool cx, cy, cz;
+        const Real tn = walk_next(W, cx, cy, cz);
+        if (tn >= r || walk_cross(W, P.T, tn, cx, cy, cz)) return;
+    }
+}
+
+// Camera of global pixel p: the last camera whose first pixel is <= p
+// (binary search over the cameras' first pixels: in LDS for the first
+// BIN_LDS_CAMS cameras, else in the device table).
+template <typename Real>
+__device__ __forceinline__ uint32_t camera_of(const KArgs<Real>& A, const int32_t* s_off, uint32_t p) {
+    int lo = 0, hi = A.n_cams - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int32_t off = mid < BIN_LDS_CAMS ? s_off[mid] : A.cams[mid].pix_off;
+        if ((uint32_t)off <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return (uint32_t)lo;
+}
+
+// Every ray of the wavefront slices w = blockIdx.x, blockIdx.x + gridDim.x, ...
+// f(record with its camera index, start voxel, direction, length).
+template <typename Real, typename F>
+__device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const int32_t* s_off, int n_waves, F&& f) {
+    const Tape<Real>& P = A.tp;
+    for (int w = blockIdx.x; w < n_waves; w += gridDim.x) {
+        const uint32_t n = min(P.wave_count[w], P.rw);
+        for (uint32_t j = threadIdx.x; j < n; j += BLOCK) {
+            TapeRec<Real> R = P.rec[(size_t)w * P.rw + j];
+            R.id = camera_of(A, s_off, R.id);
+            int ix, iy, iz;
+            Real vx, vy, vz, r;
+            if (tape_ray(A, R, R.id, ix, iy, iz, vx, vy, vz, r)) f(R, ix, iy, iz, vx, vy, vz, r);
+        }
+    }
+}
+
+// SCATTER = false: tile_count[t] += rays crossing tile t (all tiles).
+// SCATTER = true: copy every ray, with its camera in place of its pixel,
+// into the bin of every tile in [t_lo, t_hi) it crosses.  The block counts its records per tile in LDS, reserves one
+// range per tile from the tile's cursor, then copies; a reservation is only
+// used up to the end of the tile's bin, and slots of it the copy did not
+// fill get empty records (a = 0), so the bins below the cursors hold no
+// stale data whatever the count pass found.
+//
+// Dynamic LDS: the first pixels of the cameras (bin_cams words), then one
+// counter per tile of the pass, and for the scatter two more per tile.
+template <typename Real, bool SCATTER>
+__global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves) {
+    extern __shared__ uint32_t s_bin[];
+    const Tape<Real>& P = A.tp;
+    const int lo = SCATTER ? P.t_lo : 0, hi = SCATTER ? P.t_hi : P.n_tiles;
+    const int n_off = min(A.n_cams, BIN_LDS_CAMS);
+    int32_t* s_off = reinterpret_cast<int32_t*>(s_bin);
+    uint32_t* s_cnt = s_bin + n_off;
+    uint32_t* s_base = s_cnt + (hi - lo);
+    uint32_t* s_valid = s_base + (hi - lo);
+    for (int i = threadIdx.x; i < hi - lo; i += BLOCK) s_cnt[i] = 0u;
+    for (int i = threadIdx.x; i < n_off; i += BLOCK) s_off[i] = A.cams[i].pix_off;
+    __syncthreads();
+    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
+        for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
+            if (t >= lo && t < hi) atomicAdd(&s_cnt[t - lo], 1u);
+        });
+    });
+    __syncthreads();
+    if (!SCATTER) {
+        for (int i = threadIdx.x; i < hi - lo; i += BLOCK)
+            if (s_cnt[i]) atomicAdd(&P.tile_count[lo + i], s_cnt[i]);
+        return;
+    }
+    for (int i = threadIdx.x; i < hi - lo; i += BLOCK) {
+        const uint32_t n = s_cnt[i];
+        const uint32_t b = n ? atomicAdd(&P.cursor[lo + i], n) : 0u;
+        const uint32_t end = P.tile_end[lo + i];
+        s_base[i] = b;
+        s_valid[i] = b < end ? min(n, end - b) : 0u;
+        s_cnt[i] = 0u;
+    }
+    __syncthreads();
+    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
+        for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
+            if (t >= lo && t < hi) {
+                const uint32_t p = atomicAdd(&s_cnt[t - lo], 1u);
+                if (p < s_valid[t - lo]) P.brec[s_base[t - lo] + p] = R;
+            }
+        });
+    });
+    __syncthreads();
+    TapeRec<Real> E;
+    E.vox = 0u;
+    E.id = 0u;
+    E.fx = E.fy = E.fz = E.a = (Real)0;
+    for (int i = 0; i < hi - lo; ++i)
+        for (uint32_t p = s_cnt[i] + threadIdx.x; p < s_valid[i]; p += BLOCK) P.brec[s_base[i] + p] = E;
+}
+
+// ---------------------------------------------------------------------------
+// Gradient deposit of one tile: the block accumulates in LDS, for the binned
+// records [lo, hi) of its tile, -a l(m) along every recorded ray inside the
 // tile and a / beta(k_e) for the rays that start in it, then adds the tile
 // to the gradient (one device atomic per touched voxel).
 
-// Start the walk of the tape record in slot i (tile-local coordinates; the
-// walk's linear index is the LDS index).  False when the record is empty or
-// the ray has no length inside the tile.
+// Walk of a deposit inside one tile.  The ray is clipped to the tile box
+// beforehand, so the walk ends at its length and needs no voxel indices:
+// only the linear index k (the LDS index) and the next crossing on each axis,
+// advanced by the per-voxel increment dt = d / |w| (in FP32 the error of the
+// crossings grows by an ulp per step; the error of a segment stays far
+// below the Monte Carlo noise).  Axes the ray does not move along have
+// dt = inf and are never chosen.
+template <typename Real>
+struct DepWalk {
+    int k, kx, ky, kz;
+    Real tx, ty, tz;
+    Real dtx, dty, dtz;
+    Real t, len;
+};
+
+template <typename Real>
+__device__ __forceinline__ void dep_axis(Real f, Real v, Real d, int stride, int& ks, Real& tn, Real& dt) {
+    const Real tiny = sizeof(Real) == 4 ? (Real)1e-20f : (Real)1e-200;
+    if (v > tiny) {
+        dt = d / v;
+        tn = ((Real)1 - f) * dt;
+        ks = stride;
+    } else if (v < -tiny) {
+        dt = -d / v;
+        tn = f * dt;
+        ks = -stride;
+    } else {
+        dt = (Real)INFINITY;
+        tn = (Real)INFINITY;
+        ks = 0;
+    }
+}
+
+// Start the deposit of the binned record i: a / beta(k_e) if the ray starts
+// in the tile, then the walk of the part of the ray inside the tile (false
+// when the record is empty or that part has no length).
 template <typename Real>
 __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
-                                              uint32_t i, double* s_g, WalkRegs<Real>& W, Real& len, double& a) {
-    const Tape<Real>& P = A.tp;
-    const Real ar = P.a[i];
-    if (ar == (Real)0) return false;
-    a = (double)ar;
-    const uint32_t v = P.vox[i];
-    const int i0x = (int)(v & 2047u), i0y = (int)((v >> 11) & 2047u), i0z = (int)(v >> 22);
-    const Real f0x = P.fx[i], f0y = P.fy[i], f0z = P.fz[i];
-    const Real vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
-    const Real r = P.r[i];
+                                              uint32_t i, double* s_g, DepWalk<Real>& D, double& a) {
+    const TapeRec<Real> R = A.tp.brec[i];
+    if (R.a == (Real)0) return false;
+    a = (double)R.a;
+    int i0x, i0y, i0z;
+    Real vx, vy, vz, r;
+    if (!tape_ray(A, R, R.id, i0x, i0y, i0z, vx, vy, vz, r)) return false;
     const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
     if ((unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz) {
         const int ke = i0x + A.G.nx * i0y + A.G.nxy * i0z;
         atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), a / (double)A.beta[ke]);
     }
-    // clip [0, r] to the tile box, in tile-local voxel units (double)
-    const double o[3] = {(double)jx + (double)f0x, (double)jy + (double)f0y, (double)jz + (double)f0z};
+    // clip [0, r] to the tile box, in tile-local voxel units (double); a ray
+    // in the plane of a face belongs to the tile above it
+    const double o[3] = {(double)jx + (double)R.fx, (double)jy + (double)R.fy, (double)jz + (double)R.fz};
     const double u[3] = {(double)vx / (double)L.dx, (double)vy / (double)L.dy, (double)vz / (double)L.dz};
     const int e[3] = {L.nx, L.ny, L.nz};
     double t0 = 0.0, t1 = (double)r;
@@ -742,7 +867,7 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
             const double ta = (0.0 - o[ax]) / u[ax], tb = ((double)e[ax] - o[ax]) / u[ax];
             t0 = fmax(t0, fmin(ta, tb));
             t1 = fmin(t1, fmax(ta, tb));
-        } else if (!(o[ax] >= 0.0 && o[ax] <= (double)e[ax])) {
+        } else if (!(o[ax] >= 0.0 && o[ax] < (double)e[ax])) {
             return false;
         }
     }
@@ -758,8 +883,12 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
         j[ax] = (int)fl;
         f[ax] = (Real)fr;
     }
-    if (!walk_begin(W, L, j[0], j[1], j[2], f[0], f[1], f[2], vx, vy, vz)) return false;
-    len = (Real)(t1 - t0);
+    D.k = j[0] + L.nx * j[1] + L.nxy * j[2];
+    dep_axis(f[0], vx, L.dx, 1, D.kx, D.tx, D.dtx);
+    dep_axis(f[1], vy, L.dy, L.nx, D.ky, D.ty, D.dty);
+    dep_axis(f[2], vz, L.dz, L.nxy, D.kz, D.tz, D.dtz);
+    D.t = (Real)0;
+    D.len = (Real)(t1 - t0);
     return true;
 }
 
@@ -770,20 +899,20 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     const Tape<Real>& P = A.tp;
     const DepositItem it = items[blockIdx.x];
     const int tix = it.tile % P.T.nx, tiy = (it.tile / P.T.nx) % P.T.ny, tiz = it.tile / P.T.nxy;
-    const int b0x = tix * P.tx, b0y = tiy * P.ty, b0z = tiz * P.tz;
+    const int b0x = tix << P.shx, b0y = tiy << P.shy, b0z = tiz << P.shz;
     DevGrid<Real> L = A.G;
-    L.nx = min(P.tx, A.G.nx - b0x);
-    L.ny = min(P.ty, A.G.ny - b0y);
-    L.nz = min(P.tz, A.G.nz - b0z);
+    L.nx = min(1 << P.shx, A.G.nx - b0x);
+    L.ny = min(1 << P.shy, A.G.ny - b0y);
+    L.nz = min(1 << P.shz, A.G.nz - b0z);
     L.nxy = L.nx * L.ny;
     const int nloc = L.nxy * L.nz;
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
+    // every slot below the tile's cursor holds a record (or an empty one)
+    const uint32_t hi = min(it.hi, P.cursor[it.tile]);
     if (threadIdx.x == 0) s_next = it.lo;
     __syncthreads();
 
-    const uint32_t base = P.off[it.tile];
-    WalkRegs<Real> W;
-    Real len = (Real)0;
+    DepWalk<Real> D;
     double a = 0.0;
     bool busy = false, more = true;
     for (;;) {
@@ -795,10 +924,10 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
                 uint32_t first = 0;
                 if (__lane_id() == leader) first = atomicAdd(&s_next, (uint32_t)__popcll(idle));
                 first = __shfl(first, leader);
-                if (first >= it.hi) more = false;
+                if (first >= hi) more = false;
                 if (!busy) {
                     const uint32_t s = first + lanes_below(idle);
-                    if (s < it.hi) busy = deposit_begin(A, L, b0x, b0y, b0z, base + s, s_g, W, len, a);
+                    if (s < hi) busy = deposit_begin(A, L, b0x, b0y, b0z, s, s_g, D, a);
                 }
             }
         }
@@ -806,12 +935,20 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
         const uint32_t keep = more ? (uint32_t)WAVE - REFILL_IDLE : 0u;
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
             if (busy) {
-                bool cx, cy, cz;
-                const Real tn = walk_next(W, cx, cy, cz);
-                const bool last = tn >= len;
-                const Real l = (last ? len : tn) - W.t;
-                atomicAdd(s_g + W.k, -a * (double)l);
-                if (walk_cross(W, L, tn, cx, cy, cz) || last) busy = false;
+                const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
+                const bool cy = !cx && (D.ty <= D.tz);
+                const Real tn = fmin(D.tx, fmin(D.ty, D.tz));
+                const bool last = tn >= D.len;
+                const Real l = (last ? D.len : tn) - D.t;
+                atomicAdd(s_g + D.k, -a * (double)l);
+                D.k += cx ? D.kx : (cy ? D.ky : D.kz);
+                D.tx += cx ? D.dtx : (Real)0;
+                D.ty += cy ? D.dty : (Real)0;
+                D.tz += (!cx && !cy) ? D.dtz : (Real)0;
+                D.t = tn;
+                // a crossing that rounding put just before the end of the
+                // clipped ray must not leave the tile's LDS copy
+                if (last || (unsigned)D.k >= (unsigned)nloc) busy = false;
             }
         }
     }
@@ -1029,7 +1166,6 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
     size_t words = (size_t)((a.mask_words + 1) & ~1);
     size_t bytes = words * sizeof(uint32_t);
     if (mode == MODE_GRAD && a.grad_lds) bytes += (size_t)a.n_vox * sizeof(double);
-    if (mode == MODE_GRAD && a.tape) bytes += (size_t)WAVES * 3 * a.tp.n_tiles * sizeof(uint32_t);
     return bytes;
 }
 
@@ -1050,6 +1186,7 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
         return tally == TALLY_F64 ? launch_r<Real, MODE_GRAD, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_GRAD, TALLY_K32>(a, grid, s);
     }
+    if (mode == MODE_TAPE) return launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
     hipLaunchKernelGGL(k_trace<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -1066,6 +1203,7 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
                                                        : occ_r<Real, MODE_RENDER, TALLY_K32>(a, b);
     if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
                                                      : occ_r<Real, MODE_GRAD, TALLY_K32>(a, b);
+    if (mode == MODE_TAPE) return occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
 
@@ -1074,6 +1212,22 @@ hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipS
     hipLaunchKernelGGL(k_build_mask<Real>, dim3(blocks_for(a.mask_words)), dim3(BLOCK), 0, s, a, mask, ncz);
     return hipGetLastError();
 }
+
+template <typename Real>
+hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s) {
+    if (n_waves <= 0) return hipSuccess;
+    const int grid = n_waves;  // one wavefront slice per block
+    const size_t tiles = scatter ? (size_t)(a.tp.t_hi - a.tp.t_lo) : (size_t)a.tp.n_tiles;
+    const size_t dyn = sizeof(uint32_t) * ((size_t)std::min(a.n_cams, BIN_LDS_CAMS) + (scatter ? 3 : 1) * tiles);
+    if (scatter)
+        hipLaunchKernelGGL((k_bin<Real, true>), dim3(grid), dim3(BLOCK), dyn, s, a, n_waves);
+    else
+        hipLaunchKernelGGL((k_bin<Real, false>), dim3(grid), dim3(BLOCK), dyn, s, a, n_waves);
+    return hipGetLastError();
+}
+
+template hipError_t launch_bin<float>(const KArgs<float>&, bool, int, hipStream_t);
+template hipError_t launch_bin<double>(const KArgs<double>&, bool, int, hipStream_t);
 
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s) {

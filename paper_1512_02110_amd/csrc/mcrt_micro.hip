@@ -85,6 +85,36 @@ __global__ void k_atomic(void* data, uint32_t n, uint32_t ops) {
     if (KIND == 3 && keep == -1.f) ((float*)data)[0] = keep;
 }
 
+// Dependent gathers from a small working set (as in a voxel walk) with a
+// side write every `period` iterations: KIND 0 none, 1 a 4-byte store, 2 an
+// FP64 atomic add without return, 3 a 32-byte store, all to hashed
+// addresses of `out` (n_out elements of 32 bytes).  Measures what writes
+// in flight cost the loads that follow them.
+template <int KIND>
+__global__ void k_gather_write(const float* __restrict__ data, uint32_t n, uint32_t iters, uint32_t period,
+                               float4* out, uint32_t n_out, float* sink) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t h = mix32(tid * 0x9E3779B9u + 3u);
+    float acc = 0.f;
+    for (uint32_t j = 0; j < iters; ++j) {
+        const float v = data[h % n];
+        acc += v;
+        h = mix32(h + __float_as_uint(v));  // the next address depends on the load
+        if (KIND != 0 && (j % period) == period - 1) {
+            const uint32_t o = mix32(h ^ 0x5bd1e995u) % n_out;
+            if (KIND == 1) {
+                ((float*)out)[8 * (size_t)o] = acc;
+            } else if (KIND == 2) {
+                unsafeAtomicAdd((double*)out + 4 * (size_t)o, (double)acc);
+            } else {
+                out[2 * (size_t)o] = make_float4(acc, acc, acc, acc);
+                out[2 * (size_t)o + 1] = make_float4(acc, acc, acc, acc);
+            }
+        }
+    }
+    if (acc == 1234.5f) sink[tid] = acc;
+}
+
 __global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -121,6 +151,21 @@ int mc_micro_atomic(void* data, uint32_t n, uint32_t blocks, uint32_t ops, int k
         case 4: hipLaunchKernelGGL(k_atomic<4>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
         case 5: hipLaunchKernelGGL(k_atomic<5>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
         default: hipLaunchKernelGGL(k_atomic<6>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+    }
+    return (int)hipGetLastError();
+}
+
+int mc_micro_gather_write(const float* data, uint32_t n, uint32_t blocks, uint32_t iters, uint32_t period, int kind,
+                          void* out, uint32_t n_out, float* sink, void* stream) {
+    if (!data || n == 0 || !sink || period == 0 || kind < 0 || kind > 3) return (int)hipErrorInvalidValue;
+    if (kind != 0 && (!out || n_out == 0)) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    float4* o = (float4*)out;
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(k_gather_write<0>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
+        case 1: hipLaunchKernelGGL(k_gather_write<1>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
+        case 2: hipLaunchKernelGGL(k_gather_write<2>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
+        default: hipLaunchKernelGGL(k_gather_write<3>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
     }
     return (int)hipGetLastError();
 }

@@ -22,7 +22,9 @@ def _lib():
                                   C.c_void_p]
     L.mc_micro_atomic.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
     L.mc_micro_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]
-    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy):
+    L.mc_micro_gather_write.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                        C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_gather_write):
         f.restype = C.c_int
     return L
 
@@ -87,6 +89,28 @@ def main(quick=False):
             out["atomic"].append({"addresses": nn, "kind": name, "ms": ms,
                                   "gatomics_per_s": total / (ms / 1e3) / 1e9})
             print(f"[micro] atomic {name} n={nn}: {out['atomic'][-1]['gatomics_per_s']:.2f} G/s", flush=True)
+    # dependent gathers (1 MiB working set) with a write every `period` loads
+    data = torch.rand((1 << 20) // 4, dtype=torch.float32, device=dev)
+    iters = 256 if quick else 1024
+    out["gather_write"] = []
+    for n_out_bytes in (1 << 20, 1 << 30):
+        n_out = n_out_bytes // 32
+        dst = torch.zeros(n_out_bytes // 4, dtype=torch.float32, device=dev)
+        for kind, name in ((0, "none"), (1, "store 4 B"), (2, "f64 atomic"), (3, "store 32 B")):
+            for period in ((1,) if kind == 0 else (32, 8, 2)):
+                def run_gw():
+                    rc = L.mc_micro_gather_write(C.c_void_p(data.data_ptr()), data.numel(), blocks, iters, period,
+                                                 kind, C.c_void_p(dst.data_ptr()), n_out,
+                                                 C.c_void_p(sink.data_ptr()), st)
+                    assert rc == 0, rc
+                ms = _time(torch, run_gw)
+                loads = blocks * 256 * iters
+                rec = {"write": name, "period": period, "out_bytes": n_out_bytes, "ms": ms,
+                       "ns_per_load_per_lane": ms * 1e6 / iters, "gloads_per_s": loads / (ms / 1e3) / 1e9}
+                out["gather_write"].append(rec)
+                print(f"[micro] gather+write {name} every {period} (out {n_out_bytes >> 20} MiB): "
+                      f"{rec['gloads_per_s']:.1f} G loads/s", flush=True)
+        del dst
     nb = 1 << 30
     src = torch.empty(nb // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
