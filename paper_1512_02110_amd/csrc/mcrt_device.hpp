@@ -55,6 +55,9 @@ __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
 __device__ __forceinline__ double m_floor(double x) { return floor(x); }
 __device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
 __device__ __forceinline__ void m_sincospi(double x, double* s, double* c) { sincospi(x, s, c); }
+// reciprocal: one hardware instruction (about 1 ulp) in FP32, exact division in FP64
+__device__ __forceinline__ float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double m_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
 

@@ -54,6 +54,7 @@ struct alignas(16) TapeRec {
     uint32_t id;        // pixel (ray tape) or camera index (bins)
     Real fx, fy, fz;    // start fraction in the voxel
     Real a;             // gradient weight dL/di_p * norm_p * C
+    Real ab;            // bins: a / beta(start voxel)
 };
 
 template <typename Real>
@@ -112,6 +113,7 @@ constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: 
 constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS
 constexpr int BIN_GROUP_TILES = 4096; // tiles per scatter pass (3 LDS words each)
 constexpr int DEPOSIT_BLOCK = 1024;
+constexpr int DEP_LDS_CAMS = 512;     // camera centres the deposit keeps in LDS
 
 // Work item of the deposit kernel: slots [lo, hi) of one tile's range.
 struct DepositItem {

@@ -490,6 +490,7 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>
             R.fy = J.f0y;
             R.fz = J.f0z;
             R.a = (Real)J.a;
+            R.ab = (Real)0;
             A.tp.rec[w_first + pos] = R;
         }
     }
@@ -783,7 +784,9 @@ __global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves) {
         s_cnt[i] = 0u;
     }
     __syncthreads();
-    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
+    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R0, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
+        TapeRec<Real> R = R0;
+        R.ab = (Real)((double)R.a / (double)A.beta[ix + A.G.nx * iy + A.G.nxy * iz]);
         for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
             if (t >= lo && t < hi) {
                 const uint32_t p = atomicAdd(&s_cnt[t - lo], 1u);
@@ -795,7 +798,7 @@ __global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves) {
     TapeRec<Real> E;
     E.vox = 0u;
     E.id = 0u;
-    E.fx = E.fy = E.fz = E.a = (Real)0;
+    E.fx = E.fy = E.fz = E.a = E.ab = (Real)0;
     for (int i = 0; i < hi - lo; ++i)
         for (uint32_t p = s_cnt[i] + threadIdx.x; p < s_valid[i]; p += BLOCK) P.brec[s_base[i] + p] = E;
 }
@@ -821,80 +824,116 @@ struct DepWalk {
     Real t, len;
 };
 
+// Camera centre in voxel units (integer and fraction), as the deposit keeps
+// it in LDS.
 template <typename Real>
-__device__ __forceinline__ void dep_axis(Real f, Real v, Real d, int stride, int& ks, Real& tn, Real& dt) {
-    const Real tiny = sizeof(Real) == 4 ? (Real)1e-20f : (Real)1e-200;
-    if (v > tiny) {
-        dt = d / v;
-        tn = ((Real)1 - f) * dt;
-        ks = stride;
-    } else if (v < -tiny) {
-        dt = -d / v;
-        tn = f * dt;
-        ks = -stride;
-    } else {
-        dt = (Real)INFINITY;
-        tn = (Real)INFINITY;
-        ks = 0;
-    }
-}
+struct CamCentre {
+    int ix, iy, iz;
+    Real fx, fy, fz;
+};
 
-// Start the deposit of the binned record i: a / beta(k_e) if the ray starts
-// in the tile, then the walk of the part of the ray inside the tile (false
+// Start the deposit of binned record R: a / beta(k_e) if the ray starts in
+// the tile, then the walk of the part of the ray inside the tile (false
 // when the record is empty or that part has no length).
 template <typename Real>
 __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
-                                              uint32_t i, double* s_g, DepWalk<Real>& D, double& a) {
-    const TapeRec<Real> R = A.tp.brec[i];
+                                              const CamCentre<Real>* s_cam, const TapeRec<Real>& R, double* s_g,
+                                              DepWalk<Real>& D, double& a) {
     if (R.a == (Real)0) return false;
     a = (double)R.a;
-    int i0x, i0y, i0z;
-    Real vx, vy, vz, r;
-    if (!tape_ray(A, R, R.id, i0x, i0y, i0z, vx, vy, vz, r)) return false;
-    const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
-    if ((unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz) {
-        const int ke = i0x + A.G.nx * i0y + A.G.nxy * i0z;
-        atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), a / (double)A.beta[ke]);
+    const int i0x = (int)(R.vox & 2047u), i0y = (int)((R.vox >> 11) & 2047u), i0z = (int)(R.vox >> 22);
+    if (i0x >= A.G.nx || i0y >= A.G.ny || i0z >= A.G.nz || R.id >= (uint32_t)A.n_cams) return false;
+    CamCentre<Real> cc;
+    if (R.id < (uint32_t)DEP_LDS_CAMS) {
+        cc = s_cam[R.id];
+    } else {
+        const DevCam<Real>& cam = A.cams[R.id];
+        cc.ix = cam.icx;
+        cc.iy = cam.icy;
+        cc.iz = cam.icz;
+        cc.fx = cam.fcx;
+        cc.fy = cam.fcy;
+        cc.fz = cam.fcz;
     }
-    // clip [0, r] to the tile box, in tile-local voxel units (double); a ray
-    // in the plane of a face belongs to the tile above it
-    const double o[3] = {(double)jx + (double)R.fx, (double)jy + (double)R.fy, (double)jz + (double)R.fz};
-    const double u[3] = {(double)vx / (double)L.dx, (double)vy / (double)L.dy, (double)vz / (double)L.dz};
+    // direction and length to the camera, as the local estimate formed them
+    const Real dx = ((Real)(i0x - cc.ix) + (R.fx - cc.fx)) * A.G.dx;
+    const Real dy = ((Real)(i0y - cc.iy) + (R.fy - cc.fy)) * A.G.dy;
+    const Real dz = ((Real)(i0z - cc.iz) + (R.fz - cc.fz)) * A.G.dz;
+    const Real r = m_sqrt(dx * dx + dy * dy + dz * dz);
+    const Real ir = m_rcp(r);
+    const Real vx = -dx * ir, vy = -dy * ir, vz = -dz * ir;
+    const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
+    if ((unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz)
+        atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), (double)R.ab);
+    // clip [0, r] to the tile box; o = start in tile-local voxel units,
+    // w = km per voxel along each axis (inf: no motion).  A ray in the plane
+    // of a face belongs to the tile above it.
+    const Real tiny = sizeof(Real) == 4 ? (Real)1e-20f : (Real)1e-200;
+    const Real o[3] = {(Real)jx + R.fx, (Real)jy + R.fy, (Real)jz + R.fz};
+    const Real v[3] = {vx, vy, vz};
+    const Real d[3] = {A.G.dx, A.G.dy, A.G.dz};
+    const Real id[3] = {A.G.idx, A.G.idy, A.G.idz};
     const int e[3] = {L.nx, L.ny, L.nz};
-    double t0 = 0.0, t1 = (double)r;
+    Real w[3];
+    Real t0 = (Real)0, t1 = r;
     for (int ax = 0; ax < 3; ++ax) {
-        if (u[ax] > 1e-300 || u[ax] < -1e-300) {
-            const double ta = (0.0 - o[ax]) / u[ax], tb = ((double)e[ax] - o[ax]) / u[ax];
+        if (v[ax] > tiny || v[ax] < -tiny) {
+            w[ax] = d[ax] * m_rcp(v[ax]);
+            const Real ta = ((Real)0 - o[ax]) * w[ax], tb = ((Real)e[ax] - o[ax]) * w[ax];
             t0 = fmax(t0, fmin(ta, tb));
             t1 = fmin(t1, fmax(ta, tb));
-        } else if (!(o[ax] >= 0.0 && o[ax] < (double)e[ax])) {
-            return false;
+        } else {
+            if (!(o[ax] >= (Real)0 && o[ax] < (Real)e[ax])) return false;
+            w[ax] = (Real)INFINITY;
         }
     }
     if (!(t1 > t0)) return false;
-    int j[3];
-    Real f[3];
+    const int stride[3] = {1, L.nx, L.nxy};
+    int ks[3];
+    Real tn[3], dt[3];
+    D.k = 0;
     for (int ax = 0; ax < 3; ++ax) {
-        const double p = o[ax] + t0 * u[ax];
-        double fl = floor(p);
-        fl = fl < 0.0 ? 0.0 : (fl > (double)(e[ax] - 1) ? (double)(e[ax] - 1) : fl);
-        double fr = p - fl;
-        fr = fr < 0.0 ? 0.0 : (fr > 1.0 ? 1.0 : fr);
-        j[ax] = (int)fl;
-        f[ax] = (Real)fr;
+        // entry voxel and fraction; the first crossing; the increment
+        const Real p = o[ax] + t0 * v[ax] * id[ax];
+        Real fl = m_floor(p);
+        fl = fl < (Real)0 ? (Real)0 : (fl > (Real)(e[ax] - 1) ? (Real)(e[ax] - 1) : fl);
+        Real fr = p - fl;
+        fr = fr < (Real)0 ? (Real)0 : (fr > (Real)1 ? (Real)1 : fr);
+        D.k += (int)fl * stride[ax];
+        if (w[ax] == (Real)INFINITY) {
+            ks[ax] = 0;
+            dt[ax] = (Real)INFINITY;
+            tn[ax] = (Real)INFINITY;
+        } else if (w[ax] > (Real)0) {
+            ks[ax] = stride[ax];
+            dt[ax] = w[ax];
+            tn[ax] = ((Real)1 - fr) * w[ax];
+        } else {
+            ks[ax] = -stride[ax];
+            dt[ax] = -w[ax];
+            tn[ax] = fr * -w[ax];
+        }
     }
-    D.k = j[0] + L.nx * j[1] + L.nxy * j[2];
-    dep_axis(f[0], vx, L.dx, 1, D.kx, D.tx, D.dtx);
-    dep_axis(f[1], vy, L.dy, L.nx, D.ky, D.ty, D.dty);
-    dep_axis(f[2], vz, L.dz, L.nxy, D.kz, D.tz, D.dtz);
+    D.kx = ks[0];
+    D.ky = ks[1];
+    D.kz = ks[2];
+    D.tx = tn[0];
+    D.ty = tn[1];
+    D.tz = tn[2];
+    D.dtx = dt[0];
+    D.dty = dt[1];
+    D.dtz = dt[2];
     D.t = (Real)0;
     D.len = (Real)(t1 - t0);
     return true;
 }
 
+// Each lane keeps the next record it will walk in registers, loaded one
+// refill ahead, so that a refill does not wait for memory.
 template <typename Real, int TALLY>
 __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const DepositItem* items) {
     __shared__ double s_g[TILE_VOX];
+    __shared__ CamCentre<Real> s_cam[DEP_LDS_CAMS];
     __shared__ uint32_t s_next;
     const Tape<Real>& P = A.tp;
     const DepositItem it = items[blockIdx.x];
@@ -907,32 +946,57 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     L.nxy = L.nx * L.ny;
     const int nloc = L.nxy * L.nz;
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
+    for (int i = threadIdx.x; i < A.n_cams && i < DEP_LDS_CAMS; i += DEPOSIT_BLOCK) {
+        const DevCam<Real>& cam = A.cams[i];
+        CamCentre<Real> cc;
+        cc.ix = cam.icx;
+        cc.iy = cam.icy;
+        cc.iz = cam.icz;
+        cc.fx = cam.fcx;
+        cc.fy = cam.fcy;
+        cc.fz = cam.fcz;
+        s_cam[i] = cc;
+    }
     // every slot below the tile's cursor holds a record (or an empty one)
     const uint32_t hi = min(it.hi, P.cursor[it.tile]);
     if (threadIdx.x == 0) s_next = it.lo;
     __syncthreads();
 
     DepWalk<Real> D;
+    TapeRec<Real> nxt;
     double a = 0.0;
-    bool busy = false, more = true;
+    bool busy = false, has = false, more = true;
     for (;;) {
+        // idle lanes start their prefetched record
+        if (!busy && has) {
+            busy = deposit_begin(A, L, b0x, b0y, b0z, s_cam, nxt, s_g, D, a);
+            has = false;
+        }
+        // lanes without a prefetched record take the next slots of the range
         if (more) {
-            // idle lanes take the next slots of the block's range
-            const unsigned long long idle = __ballot(!busy);
-            if (idle) {
-                const int leader = __ffsll((long long)idle) - 1;
+            const unsigned long long want = __ballot(!has);
+            if (want) {
+                const int leader = __ffsll((long long)want) - 1;
                 uint32_t first = 0;
-                if (__lane_id() == leader) first = atomicAdd(&s_next, (uint32_t)__popcll(idle));
+                if (__lane_id() == leader) first = atomicAdd(&s_next, (uint32_t)__popcll(want));
                 first = __shfl(first, leader);
-                if (first >= hi) more = false;
-                if (!busy) {
-                    const uint32_t s = first + lanes_below(idle);
-                    if (s < hi) busy = deposit_begin(A, L, b0x, b0y, b0z, s, s_g, D, a);
+                if (first + (uint32_t)__popcll(want) >= hi) more = false;
+                if (!has) {
+                    const uint32_t s = first + lanes_below(want);
+                    if (s < hi) {
+                        nxt = P.brec[s];
+                        has = true;
+                    }
                 }
             }
         }
-        if (!more && __ballot(busy) == 0ull) break;
-        const uint32_t keep = more ? (uint32_t)WAVE - REFILL_IDLE : 0u;
+        const bool pending = __ballot(has) != 0ull;
+        const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
+        if (!pending && nbusy == 0) break;
+        // walk until a quarter of the lanes are idle while slots are left;
+        // after that, until one more lane is idle (a busy lane may hold the
+        // last prefetched records), and at the very end until all are
+        const uint32_t keep = more ? (uint32_t)WAVE - REFILL_IDLE : (pending && nbusy > 0 ? nbusy - 1 : 0u);
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
             if (busy) {
                 const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
