@@ -284,7 +284,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     int sh[3] = {0, 0, 0};
     const int nn[3] = {grid->nx, grid->ny, grid->nz};
     auto ncell = [&](int a) { return (int64_t)((nn[a] + (1 << sh[a]) - 1) >> sh[a]); };
-    while (ncell(0) * ncell(1) * ncell(2) > (int64_t)MASK_WORDS * 32) {
+    const int64_t mask_budget = sizeof(Real) == 4 ? MASK_WORDS_FP32 : MASK_WORDS;
+    while (ncell(0) * ncell(1) * ncell(2) > mask_budget * 32) {
         int a = 0;
         if (ncell(1) > ncell(a)) a = 1;
         if (ncell(2) > ncell(a)) a = 2;

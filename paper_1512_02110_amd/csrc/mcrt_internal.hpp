@@ -107,7 +107,11 @@ struct KArgs {
     mc_path* paths;
 };
 
-constexpr int MASK_WORDS = 8192;  // 32 KB of LDS: up to 262144 cells
+// LDS budget of the occupancy bitmask: 16 KB (131072 cells) for FP32
+// transport, so that four 256-thread blocks fit a CU's 160 KB of LDS; 32 KB
+// for FP64 transport (two blocks per CU, register bound).
+constexpr int MASK_WORDS_FP32 = 4096;
+constexpr int MASK_WORDS = 8192;
 constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)
 constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: up to 104 KB of LDS
 constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS

@@ -553,10 +553,19 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
     }
 }
 
+// Wavefronts per SIMD the compiler must leave room for: 4 (at most 128
+// VGPRs) for the FP32 forward and tape replay, which are latency bound and
+// gain more from a fourth wavefront than they lose to the tighter register
+// budget; the FP64 and small-grid gradient kernels keep their registers.
+template <typename Real, int MODE>
+struct RenderWaves {
+    static constexpr int value = sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE) ? 4 : 1;
+};
+
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
 // the gradient is privatised, one double per voxel.
 template <typename Real, int MODE, int TALLY>
-__global__ void __launch_bounds__(BLOCK) k_render(KArgs<Real> A) {
+__global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_render(KArgs<Real> A) {
     __shared__ JobQueue<Real, MODE> s_q[WAVES];
     __shared__ unsigned long long s_st[ST_N];
     extern __shared__ uint32_t s_dyn[];
