@@ -279,19 +279,12 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const int tally = prm->tally == MC_TALLY_KAHAN32 ? TALLY_K32 : TALLY_F64;
     const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE;
 
-    // occupancy-mask cells: 2^sh voxels per axis, coarsened along the axis
-    // with the most cells until the mask fits the kernels' LDS copy
-    int sh[3] = {0, 0, 0};
-    const int nn[3] = {grid->nx, grid->ny, grid->nz};
-    auto ncell = [&](int a) { return (int64_t)((nn[a] + (1 << sh[a]) - 1) >> sh[a]); };
+    // occupancy mask: one bit per run of 2^msh consecutive voxels, the
+    // shortest runs whose bits fit the kernels' LDS copy
     const int64_t mask_budget = sizeof(Real) == 4 ? MASK_WORDS_FP32 : MASK_WORDS;
-    while (ncell(0) * ncell(1) * ncell(2) > mask_budget * 32) {
-        int a = 0;
-        if (ncell(1) > ncell(a)) a = 1;
-        if (ncell(2) > ncell(a)) a = 2;
-        ++sh[a];
-    }
-    const int64_t mask_words = (ncell(0) * ncell(1) * ncell(2) + 31) / 32;
+    int msh = 0;
+    while (((n_vox + ((int64_t)1 << msh) - 1) >> msh) > mask_budget * 32) ++msh;
+    const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
     size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
@@ -378,13 +371,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.stats = counters + 1;
     A.n_pix = n_pix;
     A.n_vox = n_vox;
-    A.mshx = sh[0];
-    A.mshy = sh[1];
-    A.mshz = sh[2];
-    A.mncx = (int)ncell(0);
-    A.mncy = (int)ncell(1);
+    A.msh = msh;
     A.mask_words = (int)mask_words;
-    A.mask_fine = (sh[0] | sh[1] | sh[2]) == 0;
     A.grad_lds = mode == MODE_GRAD &&
                  ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
     if (mode == MODE_GRAD && !A.grad_lds) {
@@ -417,7 +405,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
-        CHECK_HIP(launch_build_mask<Real>(A, mask, (int)ncell(2), stream));
+        CHECK_HIP(launch_build_mask<Real>(A, mask, stream));
     }
     base_norm = n_norm ? std::cos(prm->sun_zenith) * (grid->nx * grid->dx) * (grid->ny * grid->dy) / (double)n_norm
                        : 0.0;

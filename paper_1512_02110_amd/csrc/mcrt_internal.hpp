@@ -93,9 +93,9 @@ struct KArgs {
     double* grad;               // F64 gradient
     float* grad32;              // [2 n_vox] (K32 gradient)
     int64_t n_pix, n_vox;
-    // occupancy bitmask of beta > 0 over cells of 2^msh voxels per axis
+    // occupancy bitmask of beta > 0: bit c covers voxels [c 2^msh, (c+1) 2^msh)
     const uint32_t* mask;
-    int mshx, mshy, mshz, mncx, mncy, mask_words, mask_fine;
+    int msh, mask_words;
     int grad_lds;               // gradient privatised in LDS (small grids)
     int tape;                   // gradient through the tape (large grids)
     Tape<Real> tp;
@@ -107,7 +107,7 @@ struct KArgs {
     mc_path* paths;
 };
 
-// LDS budget of the occupancy bitmask: 16 KB (131072 cells) for FP32
+// LDS budget of the occupancy bitmask: 16 KB (131072 bits) for FP32
 // transport, so that four 256-thread blocks fit a CU's 160 KB of LDS; 32 KB
 // for FP64 transport (two blocks per CU, register bound).
 constexpr int MASK_WORDS_FP32 = 4096;
@@ -146,7 +146,7 @@ hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams
                                double base, hipStream_t s);
 hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipStream_t s);
 template <typename Real>
-hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipStream_t s);
+hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
 template <typename Real>
 hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s);
 template <typename Real>

@@ -218,22 +218,22 @@ __device__ __forceinline__ Real walk_frac(Real f0, Real sf, Real r, Real w, Real
     return q > (Real)1 ? (Real)1 : q;
 }
 
-// Occupancy of the voxel (ix, iy, iz) / linear k in the bitmask of cells
+// Occupancy of voxel k in the bitmask of runs of 2^msh consecutive voxels
 // that hold a non-zero extinction: an empty voxel contributes nothing to any
-// optical depth, so its extinction need not be fetched.
+// optical depth, so its extinction need not be fetched.  (A run of voxels
+// along x, possibly wrapping to the next row, costs one shift to index.)
 template <typename Real>
-__device__ __forceinline__ bool occupied(const KArgs<Real>& A, const uint32_t* mask, int ix, int iy, int iz, int k) {
-    const uint32_t cell = A.mask_fine ? (uint32_t)k
-                                      : (uint32_t)((ix >> A.mshx) + A.mncx * ((iy >> A.mshy) + A.mncy * (iz >> A.mshz)));
+__device__ __forceinline__ bool occupied(const KArgs<Real>& A, const uint32_t* mask, int k) {
+    const uint32_t cell = (uint32_t)k >> A.msh;
     return (mask[cell >> 5] >> (cell & 31u)) & 1u;
 }
 
-// Extinction of the walk's current voxel, or 0 without a fetch when its cell
-// is empty (no mask: always fetched).
+// Extinction of voxel k, or 0 without a fetch when its run is empty (no
+// mask: always fetched).
 template <typename Real>
-__device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* mask, const WalkRegs<Real>& W) {
-    if (mask && !occupied(A, mask, W.ix, W.iy, W.iz, W.k)) return (Real)0;
-    return A.beta[W.k];
+__device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* mask, int k) {
+    if (mask && !occupied(A, mask, k)) return (Real)0;
+    return A.beta[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -278,7 +278,7 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
         return 3;
     }
     Real tau = (Real)0, tc = (Real)0;
-    Real b = beta_at(A, mask, W);
+    Real b = beta_at(A, mask, W.k);
     uint32_t steps = 0;
     int left = 0;
     for (;;) {
@@ -296,7 +296,7 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
             left = cz ? (W.sz > 0 ? 1 : 2) : 3;
             break;
         }
-        b = beta_at(A, mask, W);
+        b = beta_at(A, mask, W.k);
     }
     vfree += steps;
     if (left == 0) {
@@ -379,14 +379,76 @@ struct JobQueue {
     int32_t pix[QCAP];
 };
 
+// Walk of a connection ray.  Its length is clipped at job start to where
+// the ray leaves the domain, so that the walk ends at its length and keeps
+// only the linear voxel index, not the voxel indices: the next crossing on
+// axis a is t_a = r_a g_a as in the free-flight walk (r_a counted from the
+// start voxel, t recomputed after every crossing), and a crossing that
+// rounding put just before the clipped end (so that k left the grid) ends
+// the walk too.
+template <typename Real>
+struct ConnWalk {
+    int k, kx, ky, kz;
+    Real sfx, sfy, sfz;
+    Real rx, ry, rz;
+    Real gx, gy, gz;
+    Real tx, ty, tz;
+    Real t;
+};
+
+// Start at voxel-local (i, f) along unit w; returns the parameter where the
+// ray leaves the domain (inf when the walk cannot start: no usable
+// direction component, or a non-finite fraction).
+template <typename Real>
+__device__ __forceinline__ Real conn_begin(ConnWalk<Real>& C, const DevGrid<Real>& G, int ix, int iy, int iz, Real fx,
+                                           Real fy, Real fz, Real wx, Real wy, Real wz) {
+    int sx, sy, sz;
+    C.k = ix + G.nx * iy + G.nxy * iz;
+    walk_axis(fx, wx, G.dx, sx, C.sfx, C.rx, C.gx, C.tx);
+    walk_axis(fy, wy, G.dy, sy, C.sfy, C.ry, C.gy, C.ty);
+    walk_axis(fz, wz, G.dz, sz, C.sfz, C.rz, C.gz, C.tz);
+    C.kx = sx;
+    C.ky = sy * G.nx;
+    C.kz = sz * G.nxy;
+    C.t = (Real)0;
+    // the domain face on each axis lies (n - 1 - i) voxels beyond the first
+    // face when moving up, i voxels beyond it when moving down
+    const Real ex = sx > 0 ? ((Real)(G.nx - 1 - ix) + C.rx) * C.gx : (sx < 0 ? (C.rx - (Real)ix) * C.gx : (Real)INFINITY);
+    const Real ey = sy > 0 ? ((Real)(G.ny - 1 - iy) + C.ry) * C.gy : (sy < 0 ? (C.ry - (Real)iy) * C.gy : (Real)INFINITY);
+    const Real ez = sz > 0 ? ((Real)(G.nz - 1 - iz) + C.rz) * C.gz : (sz < 0 ? (C.rz - (Real)iz) * C.gz : (Real)INFINITY);
+    const bool finite_f = fabs(fx) < (Real)4 && fabs(fy) < (Real)4 && fabs(fz) < (Real)4;
+    if (!finite_f || (sx | sy | sz) == 0) return (Real)-1;
+    return fmin(ex, fmin(ey, ez));
+}
+
+template <typename Real>
+__device__ __forceinline__ Real conn_next(const ConnWalk<Real>& C, bool& cx, bool& cy, bool& cz) {
+    cx = (C.tx <= C.ty) && (C.tx <= C.tz);
+    cy = !cx && (C.ty <= C.tz);
+    cz = !cx && !cy;
+    return fmin(C.tx, fmin(C.ty, C.tz));
+}
+
+template <typename Real>
+__device__ __forceinline__ void conn_cross(ConnWalk<Real>& C, Real tn, bool cx, bool cy, bool cz) {
+    C.t = tn;
+    C.k += (cx ? C.kx : 0) + (cy ? C.ky : 0) + (cz ? C.kz : 0);
+    C.rx += cx ? C.sfx : (Real)0;
+    C.ry += cy ? C.sfy : (Real)0;
+    C.rz += cz ? C.sfz : (Real)0;
+    C.tx = C.rx * C.gx;
+    C.ty = C.ry * C.gy;
+    C.tz = C.rz * C.gz;
+}
+
 // One lane's connection ray in flight.  The optical depth of a voxel is
 // added one step after the walk entered it, so that the fetch of its
 // extinction has a whole step to arrive: bn is in flight for the current
 // voxel, (bp, lp) is the previous voxel's pending term.
 template <typename Real>
 struct Job {
-    WalkRegs<Real> W;
-    Real r;        // length to the camera
+    ConnWalk<Real> W;
+    Real r;        // length to the camera, then clipped to the domain
     Real bn, bp, lp;
     Real pre;      // albedo * I_s * P / r^2
     double tau;    // optical depth so far (FP64)
@@ -402,12 +464,15 @@ struct Job {
 
 template <typename Real>
 __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J) {
-    if (!walk_begin(J.W, A.G, J.i0x, J.i0y, J.i0z, J.f0x, J.f0y, J.f0z, J.vx, J.vy, J.vz)) {
+    const Real texit = conn_begin(J.W, A.G, J.i0x, J.i0y, J.i0z, J.f0x, J.f0y, J.f0z, J.vx, J.vy, J.vz);
+    if (texit < (Real)0) {
         // cannot start: the first step ends the walk with zero length
         J.r = (Real)0;
         J.W.tx = J.W.ty = J.W.tz = (Real)0;
+    } else {
+        J.r = fmin(J.r, texit);
     }
-    J.bn = J.phase == 2 ? (Real)0 : beta_at(A, mask, J.W);
+    J.bn = J.phase == 2 ? (Real)0 : beta_at(A, mask, J.W.k);
     J.bp = (Real)0;
     J.lp = (Real)0;
     J.tau = 0.0;
@@ -418,7 +483,7 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
 template <typename Real, int MODE, int TALLY>
 __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J) {
     bool cx, cy, cz;
-    const Real tn = walk_next(J.W, cx, cy, cz);
+    const Real tn = conn_next(J.W, cx, cy, cz);
     const bool last = tn >= J.r;
     const Real tend = last ? J.r : tn;
     const Real l = tend - J.W.t;
@@ -431,12 +496,12 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
         J.lp = l;
         ++J.steps;
     }
-    const bool out = walk_cross(J.W, A.G, tn, cx, cy, cz);
-    const bool done = last || out;
+    conn_cross(J.W, tn, cx, cy, cz);
+    const bool done = last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
     if (done) {
         if (!scatter) J.tau += (double)J.bp * (double)J.lp;
     } else if (!scatter) {
-        J.bn = beta_at(A, mask, J.W);
+        J.bn = beta_at(A, mask, J.W.k);
     }
     return done;
 }
@@ -1190,28 +1255,18 @@ __global__ void k_grad_weights(double* gw, const double* dl, const NormCam* cams
 }
 
 // One 32-bit word of the occupancy bitmask per thread: bit j of word w is
-// set when cell 32 w + j holds a voxel with beta > 0 (or a non-finite beta,
+// set when a voxel of run 32 w + j has beta > 0 (or a non-finite beta,
 // which must reach the walk unchanged).
 template <typename Real>
-__global__ void k_build_mask(KArgs<Real> A, uint32_t* mask, int ncz) {
+__global__ void k_build_mask(KArgs<Real> A, uint32_t* mask) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= A.mask_words) return;
-    const int64_t ncells = (int64_t)A.mncx * A.mncy * ncz;
     uint32_t word = 0;
     for (int j = 0; j < 32; ++j) {
-        const int64_t cell = (int64_t)w * 32 + j;
-        if (cell >= ncells) break;
-        const int cx = (int)(cell % A.mncx), cy = (int)((cell / A.mncx) % A.mncy), cz = (int)(cell / ((int64_t)A.mncx * A.mncy));
-        const int x0 = cx << A.mshx, y0 = cy << A.mshy, z0 = cz << A.mshz;
-        const int x1 = min(x0 + (1 << A.mshx), A.G.nx), y1 = min(y0 + (1 << A.mshy), A.G.ny),
-                  z1 = min(z0 + (1 << A.mshz), A.G.nz);
+        const int64_t k0 = ((int64_t)w * 32 + j) << A.msh;
+        const int64_t k1 = min(k0 + ((int64_t)1 << A.msh), A.n_vox);
         bool any = false;
-        for (int z = z0; z < z1 && !any; ++z)
-            for (int y = y0; y < y1 && !any; ++y)
-                for (int x = x0; x < x1 && !any; ++x) {
-                    const Real b = A.beta[x + A.G.nx * y + A.G.nxy * z];
-                    any = !(b == (Real)0);
-                }
+        for (int64_t k = k0; k < k1 && !any; ++k) any = !(A.beta[k] == (Real)0);
         if (any) word |= 1u << j;
     }
     mask[w] = word;
@@ -1281,8 +1336,8 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
 }
 
 template <typename Real>
-hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, int ncz, hipStream_t s) {
-    hipLaunchKernelGGL(k_build_mask<Real>, dim3(blocks_for(a.mask_words)), dim3(BLOCK), 0, s, a, mask, ncz);
+hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_mask<Real>, dim3(blocks_for(a.mask_words)), dim3(BLOCK), 0, s, a, mask);
     return hipGetLastError();
 }
 
@@ -1314,8 +1369,8 @@ hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* it
 
 template hipError_t launch_deposit<float>(const KArgs<float>&, int, const DepositItem*, int, hipStream_t);
 template hipError_t launch_deposit<double>(const KArgs<double>&, int, const DepositItem*, int, hipStream_t);
-template hipError_t launch_build_mask<float>(const KArgs<float>&, uint32_t*, int, hipStream_t);
-template hipError_t launch_build_mask<double>(const KArgs<double>&, uint32_t*, int, hipStream_t);
+template hipError_t launch_build_mask<float>(const KArgs<float>&, uint32_t*, hipStream_t);
+template hipError_t launch_build_mask<double>(const KArgs<double>&, uint32_t*, hipStream_t);
 template hipError_t launch_write_cams<float>(const CamChunk&, DevCam<float>*, NormCam*, hipStream_t);
 template hipError_t launch_write_cams<double>(const CamChunk&, DevCam<double>*, NormCam*, hipStream_t);
 template hipError_t launch_transport<float>(const KArgs<float>&, int, int, int, hipStream_t);

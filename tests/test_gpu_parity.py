@@ -216,8 +216,13 @@ def test_random_scenes_fp64(M, oracle):
         s = scenes.random_scene(rng, n_photons=int(rng.integers(1, 3000)))
         print(f"case random scene {i}: {s.nx}x{s.ny}x{s.nz} cams={s.n_cams} n={s.n_photons}", flush=True)
         img, st, ref, rst, m2 = _render_both(M, oracle, s, "fp64", max_events=int(rng.integers(1, 50)))
-        assert st == rst
         assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * max(1e-300, np.abs(ref).max()))
+        # a connection ray ends where it leaves the domain: a crossing that
+        # rounding puts on the other side of that point adds or drops one
+        # zero-length voxel (the optical depth is unchanged)
+        assert abs(st["vox_conn"] - rst["vox_conn"]) <= max(2, 1e-3 * rst["vox_conn"])
+        st.pop("vox_conn"), rst.pop("vox_conn")
+        assert st == rst
 
 
 def test_moments_match_oracle_without_repeat_visits(M, oracle):
