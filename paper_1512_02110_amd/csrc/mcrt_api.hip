@@ -286,7 +286,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     while (((n_vox + ((int64_t)1 << msh) - 1) >> msh) > mask_budget * 32) ++msh;
     const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
-    size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
+    size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) + round256(sizeof(double)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
     if (mode == MODE_GRAD) bytes += round256(sizeof(double) * n_pix);
@@ -298,6 +298,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     KArgs<Real> A;
     std::memset(&A, 0, sizeof(A));
     unsigned long long* counters = nullptr;
+    double* zero = nullptr;
     DevCam<Real>* dcams = nullptr;
     NormCam* ncams = nullptr;
     unsigned long long host_counters[1 + ST_N];
@@ -311,6 +312,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     CHECK_HIP(hipMallocAsync((void**)&S.base, bytes, stream));
     counters = S.take<unsigned long long>(1 + ST_N);
+    zero = S.take<double>(1);
     dcams = S.take<DevCam<Real>>(n_cams);
     ncams = S.take<NormCam>(n_cams);
 
@@ -343,6 +345,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         }
     }
     CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
+    CHECK_HIP(launch_fill_f64(zero, 1, stream));
 
     A.G.nx = grid->nx;
     A.G.ny = grid->ny;
@@ -355,6 +358,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.G.idy = (Real)(1.0 / grid->dy);
     A.G.idz = (Real)(1.0 / grid->dz);
     A.beta = static_cast<const Real*>(beta);
+    A.zero = reinterpret_cast<const Real*>(zero);
     A.cams = dcams;
     A.n_cams = n_cams;
     A.wsx = (Real)(-std::sin(prm->sun_zenith) * std::cos(prm->sun_azimuth));

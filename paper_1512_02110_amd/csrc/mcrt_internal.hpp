@@ -78,6 +78,7 @@ template <typename Real>
 struct KArgs {
     DevGrid<Real> G;
     const Real* beta;
+    const Real* zero;           // a zero in device memory (fetched for empty voxels)
     const DevCam<Real>* cams;
     int n_cams;
     Real wsx, wsy, wsz;     // sun propagation direction

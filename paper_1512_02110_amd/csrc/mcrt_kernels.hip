@@ -228,12 +228,21 @@ __device__ __forceinline__ bool occupied(const KArgs<Real>& A, const uint32_t* m
     return (mask[cell >> 5] >> (cell & 31u)) & 1u;
 }
 
-// Extinction of voxel k, or 0 without a fetch when its run is empty (no
-// mask: always fetched).
+// Extinction of voxel k, or 0 without a gather when its run is empty (no
+// mask: always gathered).
 template <typename Real>
 __device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* mask, int k) {
     if (mask && !occupied(A, mask, k)) return (Real)0;
     return A.beta[k];
+}
+
+// The same value as one unconditional load: an empty voxel reads a zero word
+// that every lane shares (one cache line, no gather), so that the loaded
+// register can stay in flight across a step without a select or a copy.
+template <typename Real>
+__device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k) {
+    const Real* p = (mask && !occupied(A, mask, k)) ? A.zero : A.beta + k;
+    return *p;
 }
 
 // ---------------------------------------------------------------------------
@@ -442,14 +451,18 @@ __device__ __forceinline__ void conn_cross(ConnWalk<Real>& C, Real tn, bool cx, 
 }
 
 // One lane's connection ray in flight.  The optical depth of a voxel is
-// added one step after the walk entered it, so that the fetch of its
-// extinction has a whole step to arrive: bn is in flight for the current
-// voxel, (bp, lp) is the previous voxel's pending term.
+// added one step after the walk left it, so that the fetch of its extinction
+// has a whole step to arrive.  The walk runs in pairs of steps with b0 and b1
+// trading roles (job_step<PH>): in step PH, b[PH] is the current voxel's
+// extinction (in flight) and b[1-PH] the previous voxel's, whose term
+// b[1-PH] * lp is added and whose register then receives the fetch for the
+// next voxel.  With fixed roles and no register copies, the wait for a fetch
+// falls one step after it was issued.
 template <typename Real>
 struct Job {
     ConnWalk<Real> W;
     Real r;        // length to the camera, then clipped to the domain
-    Real bn, bp, lp;
+    Real b0, b1, lp;
     Real pre;      // albedo * I_s * P / r^2
     double tau;    // optical depth so far (FP64)
     double a;      // gradient weight of the second walk
@@ -472,16 +485,18 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
     } else {
         J.r = fmin(J.r, texit);
     }
-    J.bn = J.phase == 2 ? (Real)0 : beta_at(A, mask, J.W.k);
-    J.bp = (Real)0;
+    J.b0 = J.phase == 2 ? (Real)0 : beta_load(A, mask, J.W.k);
+    J.b1 = (Real)0;
     J.lp = (Real)0;
     J.tau = 0.0;
     J.steps = 0;
 }
 
-// One voxel of the connection ray; returns true when the ray is done.
-template <typename Real, int MODE, int TALLY>
+// One voxel of the connection ray (step PH of a pair); returns true when the
+// ray is done.
+template <typename Real, int MODE, int TALLY, int PH>
 __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J) {
+    Real& prev = PH == 0 ? J.b1 : J.b0;
     bool cx, cy, cz;
     const Real tn = conn_next(J.W, cx, cy, cz);
     const bool last = tn >= J.r;
@@ -491,18 +506,20 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     if (scatter) {
         grad_add<Real, TALLY>(A, lds_grad, J.W.k, -J.a * (double)l);
     } else {
-        J.tau += (double)J.bp * (double)J.lp;
-        J.bp = J.bn;
+        J.tau += (double)prev * (double)J.lp;
         J.lp = l;
         ++J.steps;
     }
     conn_cross(J.W, tn, cx, cy, cz);
     const bool done = last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
-    if (done) {
-        if (!scatter) J.tau += (double)J.bp * (double)J.lp;
-    } else if (!scatter) {
-        J.bn = beta_at(A, mask, J.W.k);
-    }
+    // the next fetch is issued unconditionally (the shared zero word when the
+    // ray is done, scatters, or enters an empty run).  When the ray is done,
+    // the last voxel's term cur * lp is left to job_finish, as
+    // (b0 + b1) * lp with the other register zero, so that no step waits for
+    // a fetch it has just issued.
+    const int kk = done ? 0 : J.W.k;
+    const bool none = scatter || done || (mask && !occupied(A, mask, kk));
+    prev = *(none ? A.zero : A.beta + kk);
     return done;
 }
 
@@ -514,6 +531,7 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
                                            uint64_t& vconn, bool& rec) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     vconn += J.steps;
+    J.tau += ((double)J.b0 + (double)J.b1) * (double)J.lp;  // the last voxel
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
     if (MODE == MODE_RENDER) {
         tally_f64<TALLY>(A.img, A.img32, J.pix, C);
@@ -607,10 +625,15 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
             }
             qhead += take;
         }
-        // walk until a quarter of the lanes are idle (all, if nothing is queued)
+        // walk until a quarter of the lanes are idle (all, if nothing is
+        // queued), in pairs of steps (a job always starts with step 0)
         const uint32_t keep = (qtail - qhead) > 0 ? (uint32_t)WAVE - REFILL_IDLE : 0u;
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-            if (busy && job_step<Real, MODE, TALLY>(A, mask, lds_grad, J)) {
+            if (busy && job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J)) {
+                busy = false;
+                fin = true;
+            }
+            if (busy && job_step<Real, MODE, TALLY, 1>(A, mask, lds_grad, J)) {
                 busy = false;
                 fin = true;
             }
