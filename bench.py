@@ -31,6 +31,32 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32, dense
 PEAK_HBM_GBPS = 8000.0
+# random 4-byte gathers from a 1 MiB working set (the 64^3 FP32 grid) at
+# full occupancy, 4 useful bytes per load: paper_1512_02110_amd/micro.py
+GATHER_CEILING_GBPS = 1006.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1512_02110_amd", "csrc", "mcrt_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_render_c2_hbm_traffic.md")
+
+
+def _source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per forward launch from the committed rocprofv3 counter
+    summary, or None when the kernels changed since it was taken."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    h = re.search(r"kernel source sha256\[:16\]: ([0-9a-f]{16})", text)
+    b = re.search(r"hbm_bytes_per_launch: ([0-9.eE+]+)", text)
+    if not h or not b or h.group(1) != _source_hash():
+        return None
+    return float(b.group(1))
 
 
 def _cpu_worker(args):
@@ -169,18 +195,28 @@ def main():
     fwd_s = sum(fwd_ms) / 1e3
     value = events / fwd_s
 
-    # roofline of the transport kernel (one launch per render): algorithmic
-    # work per scattering event, counted from the launch's own statistics
-    flops = (10.0 * (st["vox_free"] + st["vox_conn"]) + 60.0 * st["le_jobs"] + 150.0 * st["events"])
-    gbytes = 4.0 * (st["vox_free"] + st["vox_conn"]) + 16.0 * st["le_jobs"]
-    achieved_tflops = flops / fwd_s / 1e12
+    # roofline of the transport kernel k_render (one launch per render),
+    # timed by the library with HIP events on the launch stream; algorithmic
+    # work from the launch's own counters: per voxel step (free flight or
+    # connection ray) 10 flops and one 4-byte extinction read, per local
+    # estimate 60 flops and a 16-byte FP64 tally, per event 150 flops
+    k_ms = [r[1].timing["transport_ms"] for r in recs]
+    k_s = sum(k_ms) / 1e3
+    steps = st["vox_free"] + st["vox_conn"]
+    flops = 10.0 * steps + 60.0 * st["le_jobs"] + 150.0 * st["events"]
+    gbytes = 4.0 * steps + 16.0 * st["le_jobs"]
+    achieved_tflops = flops / k_s / 1e12
+    traffic = measured_traffic()
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": None,
-                "kernel": "k_transport<float, render, f64 tally>",
-                "kernel_ms_avg": round(sum(fwd_ms) / len(fwd_ms), 3),
-                "gather_GBps": round(gbytes / fwd_s / 1e9, 1),
-                "voxel_steps_per_s": (st["vox_free"] + st["vox_conn"]) / fwd_s}
+                "traffic": traffic,
+                "kernel": "k_render<float, MODE_RENDER, TALLY_F64>",
+                "kernel_ms_avg": round(sum(k_ms) / len(k_ms), 3),
+                "algorithmic_bytes_per_launch": gbytes / len(recs),
+                "gather_GBps_algorithmic": round(gbytes / k_s / 1e9, 1),
+                "gather_ceiling_GBps_measured": GATHER_CEILING_GBPS,
+                "frac_of_gather_ceiling": round(gbytes / k_s / 1e9 / GATHER_CEILING_GBPS, 3),
+                "voxel_steps_per_s": steps / k_s}
 
     out = {
         "metric": "scattering events/s fwd; fwd+adjoint time vs fwd, FP32 vs FP64 at <=1e-4 error",
@@ -207,6 +243,8 @@ def main():
     if not args.no_adjoint:
         out["adj_ms"] = round(sum(adj_ms) / len(adj_ms), 3)
         out["fwd_plus_adj_over_fwd"] = round((sum(fwd_ms) + sum(adj_ms)) / sum(fwd_ms), 4)
+        out["adj_replay_ms"] = round(sum(r[2].timing["transport_ms"] for r in recs) / len(recs), 3)
+        out["adj_bin_deposit_ms"] = round(sum(r[2].timing["tape_ms"] for r in recs) / len(recs), 3)
 
     if not args.no_fp64:
         beta64 = M.beta_tensor(s, "fp64")

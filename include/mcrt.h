@@ -128,6 +128,10 @@ typedef struct mc_stats {
     uint64_t esc_top, esc_bottom, esc_side;  /* photons that left through each face */
     uint64_t rr_killed;   /* photons ended by Russian roulette */
     uint64_t capped;      /* photons stopped at max_events */
+    double transport_ms;  /* device time of the transport kernel (all its launches), from
+                             HIP events recorded on hip_stream around each launch */
+    double tape_ms;       /* mc_grad_beta on large grids: device time of the binning and
+                             deposit passes (events around each chunk's passes); else 0 */
 } mc_stats;
 
 /* Forward render (FMC + local estimation).

@@ -132,8 +132,13 @@ constexpr int TAPE_FALLBACK = 1;
 // into host_sum.
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
-             int n_cu, unsigned long long* counters, unsigned long long* host_sum, hipStream_t stream) {
+             int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
+             double* t_tape, hipStream_t stream) {
     int rc = MC_OK;
+    // device times: replay (r0, r1), binning + deposit of the last chunk (b0, b1)
+    hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr;
+    bool pending_b = false;
+    float ms = 0.f;
     const int nt = A.tp.n_tiles;
     const size_t rec = sizeof(TapeRec<Real>);
     const int wpb = BLOCK / 64;  // wavefronts per block
@@ -162,6 +167,12 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     if (r_cap < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_cap / (64 * (uint64_t)wpb));
     if (max_blocks < 1 || b_cap < 64) return TAPE_FALLBACK;
 
+    if (t_transport) {
+        CHECK_HIP(hipEventCreate(&r0));
+        CHECK_HIP(hipEventCreate(&r1));
+        CHECK_HIP(hipEventCreate(&b0));
+        CHECK_HIP(hipEventCreate(&b1));
+    }
     CHECK_HIP(hipMallocAsync((void**)&pool, P * rec, stream));
     CHECK_HIP(hipMallocAsync((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_blocks * wpb),
                              stream));
@@ -186,7 +197,9 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
         CHECK_HIP(launch_fill_u32(A.tp.overflow, 1, stream));
         CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
+        if (r0) CHECK_HIP(hipEventRecord(r0, stream));
         CHECK_HIP(launch_transport<Real>(A, MODE_TAPE, TALLY_F64, grid, stream));
+        if (r1) CHECK_HIP(hipEventRecord(r1, stream));
         CHECK_HIP(launch_bin<Real>(A, false, nw, stream));
         CHECK_HIP(hipMemcpyAsync(h_count.data(), A.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost,
                                  stream));
@@ -195,6 +208,15 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
                                  stream));
         CHECK_HIP(hipMemcpyAsync(h_ctr, counters, sizeof(h_ctr), hipMemcpyDeviceToHost, stream));
         CHECK_HIP(hipStreamSynchronize(stream));
+        if (r0) {
+            CHECK_HIP(hipEventElapsedTime(&ms, r0, r1));
+            *t_transport += ms;
+            if (pending_b) {
+                CHECK_HIP(hipEventElapsedTime(&ms, b0, b1));
+                *t_tape += ms;
+                pending_b = false;
+            }
+        }
         uint32_t busiest = 0;
         for (int w = 0; w < nw; ++w) busiest = std::max(busiest, h_wave[w]);
         const double rate = (double)busiest * nw / (double)n;  // rays per photon, busiest wavefront
@@ -209,6 +231,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
             continue;
         }
         for (int i = 1; i < 1 + ST_N; ++i) host_sum[i] += h_ctr[i];
+        if (b0) CHECK_HIP(hipEventRecord(b0, stream));
         for (int g0 = 0; g0 < nt;) {
             // the next group of tiles whose bins fit together
             uint64_t sum = 0;
@@ -250,11 +273,19 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
             g0 = g1;
             if (g0 < nt) CHECK_HIP(hipStreamSynchronize(stream));  // host arrays are reused
         }
+        if (b1) {
+            CHECK_HIP(hipEventRecord(b1, stream));
+            pending_b = true;
+        }
         done += n;
         // next chunk: the busiest wavefront's slice about 80% full
         chunk = rate > 0.0 ? (uint64_t)std::max(1.0, std::floor(0.8 * (double)r_cap / rate)) : n_photons - done;
     }
     CHECK_HIP(hipStreamSynchronize(stream));
+    if (pending_b) {
+        CHECK_HIP(hipEventElapsedTime(&ms, b0, b1));
+        *t_tape += ms;
+    }
 
 done:
     for (void* p : {(void*)ditems, (void*)meta, (void*)pool}) {
@@ -264,6 +295,8 @@ done:
     }
     // the host arrays above were sources of asynchronous copies
     (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : {r0, r1, b0, b1})
+        if (e) (void)hipEventDestroy(e);
     return rc;
 }
 
@@ -286,7 +319,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     while (((n_vox + ((int64_t)1 << msh) - 1) >> msh) > mask_budget * 32) ++msh;
     const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
-    size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) + round256(sizeof(double)) +
+    size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
+                   round256(sizeof(Real) * (n_vox + BETA_PAD)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
     if (mode == MODE_GRAD) bytes += round256(sizeof(double) * n_pix);
@@ -298,7 +332,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     KArgs<Real> A;
     std::memset(&A, 0, sizeof(A));
     unsigned long long* counters = nullptr;
-    double* zero = nullptr;
+    Real* betap = nullptr;
     DevCam<Real>* dcams = nullptr;
     NormCam* ncams = nullptr;
     unsigned long long host_counters[1 + ST_N];
@@ -307,12 +341,14 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const uint64_t n_norm = prm->n_photons_norm ? prm->n_photons_norm : prm->n_photons;
     const int64_t need_blocks = (int64_t)((prm->n_photons + BLOCK - 1) / BLOCK);
     bool tape_counts = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the transport launch (stats only)
+    double t_transport = 0.0, t_tape = 0.0;
 
     CHECK_HIP(hipGetDevice(&dev));
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     CHECK_HIP(hipMallocAsync((void**)&S.base, bytes, stream));
     counters = S.take<unsigned long long>(1 + ST_N);
-    zero = S.take<double>(1);
+    betap = S.take<Real>(n_vox + BETA_PAD);
     dcams = S.take<DevCam<Real>>(n_cams);
     ncams = S.take<NormCam>(n_cams);
 
@@ -345,7 +381,13 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         }
     }
     CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
-    CHECK_HIP(launch_fill_f64(zero, 1, stream));
+    // the kernels read a copy of beta followed by zeros (an empty voxel
+    // fetches beta[n_vox])
+    CHECK_HIP(hipMemcpyAsync(betap, beta, sizeof(Real) * n_vox, hipMemcpyDeviceToDevice, stream));
+    if (sizeof(Real) == 4)
+        CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(betap) + n_vox, BETA_PAD, stream));
+    else
+        CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(betap) + n_vox, BETA_PAD, stream));
 
     A.G.nx = grid->nx;
     A.G.ny = grid->ny;
@@ -357,8 +399,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.G.idx = (Real)(1.0 / grid->dx);
     A.G.idy = (Real)(1.0 / grid->dy);
     A.G.idz = (Real)(1.0 / grid->dz);
-    A.beta = static_cast<const Real*>(beta);
-    A.zero = reinterpret_cast<const Real*>(zero);
+    A.beta = betap;
     A.cams = dcams;
     A.n_cams = n_cams;
     A.wsx = (Real)(-std::sin(prm->sun_zenith) * std::cos(prm->sun_azimuth));
@@ -454,7 +495,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         std::memset(host_counters, 0, sizeof(host_counters));
         rc = run_tape<Real>(A, tally, prm->n_photons, prm->photon_offset, prm->tape_limit,
                             (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
-                            stream);
+                            stats ? &t_transport : nullptr, &t_tape, stream);
         if (rc == TAPE_FALLBACK) {
             // tape too small even for one block: device atomics
             rc = MC_OK;
@@ -462,14 +503,26 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             CHECK_HIP(transport_occupancy<Real>(A, mode, tally, &per_cu));
             const int64_t full = (int64_t)n_cu * (per_cu > 0 ? per_cu : 1);
             grid_blocks = (int)(need_blocks < full ? need_blocks : full);
+            if (stats) {
+                CHECK_HIP(hipEventCreate(&ev0));
+                CHECK_HIP(hipEventCreate(&ev1));
+                CHECK_HIP(hipEventRecord(ev0, stream));
+            }
             CHECK_HIP(launch_transport<Real>(A, mode, tally, grid_blocks, stream));
+            if (stats) CHECK_HIP(hipEventRecord(ev1, stream));
         } else if (rc != MC_OK) {
             goto done;
         } else {
             tape_counts = true;
         }
     } else if (grid_blocks > 0 && (mode == MODE_TRACE || prm->n_photons > 0)) {
+        if (stats) {
+            CHECK_HIP(hipEventCreate(&ev0));
+            CHECK_HIP(hipEventCreate(&ev1));
+            CHECK_HIP(hipEventRecord(ev0, stream));
+        }
         CHECK_HIP(launch_transport<Real>(A, mode, tally, grid_blocks, stream));
+        if (stats) CHECK_HIP(hipEventRecord(ev1, stream));
     }
 
     if (mode == MODE_RENDER) {
@@ -496,10 +549,19 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             stats->esc_side = host_counters[1 + ST_SIDE];
             stats->rr_killed = host_counters[1 + ST_RR];
             stats->capped = host_counters[1 + ST_CAP];
+            if (ev0) {
+                float ms = 0.f;
+                CHECK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+                t_transport = ms;
+            }
+            stats->transport_ms = t_transport;
+            stats->tape_ms = t_tape;
         }
     }
 
 done:
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     if (S.base) {
         hipError_t e = hipFreeAsync(S.base, stream);
         if (rc == MC_OK && e != hipSuccess) rc = map_err(e);

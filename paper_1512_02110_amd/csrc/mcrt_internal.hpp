@@ -77,8 +77,8 @@ struct Tape {
 template <typename Real>
 struct KArgs {
     DevGrid<Real> G;
-    const Real* beta;
-    const Real* zero;           // a zero in device memory (fetched for empty voxels)
+    const Real* beta;           // the library's copy: n_vox values, then zeros
+                                // (beta[n_vox] is fetched for empty voxels)
     const DevCam<Real>* cams;
     int n_cams;
     Real wsx, wsy, wsz;     // sun propagation direction
@@ -129,6 +129,7 @@ struct DepositItem {
 constexpr int64_t GRAD_LDS_BYTES = 64 * 1024;  // dynamic LDS budget of a privatised gradient
 
 constexpr int BLOCK = 256;
+constexpr int BETA_PAD = 64;  // zeros after the library's copy of beta
 
 // Launchers (mcrt_kernels.hip).
 template <typename Real>

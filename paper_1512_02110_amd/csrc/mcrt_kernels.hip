@@ -67,15 +67,33 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
     return (uint32_t)__popcll(mask & __lanemask_lt());
 }
 
-// The active lanes take consecutive photon ids with one atomic.
-__device__ __forceinline__ uint64_t wave_fetch(unsigned long long* work) {
-    const unsigned long long mask = __ballot(1);
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (__lane_id() == leader) base = atomicAdd(work, (unsigned long long)__popcll(mask));
-    const unsigned lo = __shfl((unsigned)base, leader);
-    const unsigned hi = __shfl((unsigned)(base >> 32), leader);
-    return (((uint64_t)hi << 32) | lo) + lanes_below(mask);
+// Photon ids for the lanes in `need`, in order, from the wavefront's pool
+// [pool_next, pool_end), which is refilled FETCH_BLOCK ids at a time with
+// one atomic on the global counter (a returning device atomic takes
+// microseconds; one per photon phase would stall every phase).  Called by
+// the whole wavefront, so that the pool stays uniform.
+constexpr uint32_t FETCH_BLOCK = 256;
+
+__device__ __forceinline__ uint64_t wave_fetch(unsigned long long* work, unsigned long long need, uint64_t& pool_next,
+                                               uint64_t& pool_end) {
+    const uint32_t n = (uint32_t)__popcll(need);
+    const uint32_t rank = lanes_below(need);
+    const uint64_t left = pool_end - pool_next;
+    const uint32_t avail = left < n ? (uint32_t)left : n;
+    uint64_t id = pool_next + rank;
+    if (avail < n) {
+        unsigned long long base = 0;
+        if (__lane_id() == 0) base = atomicAdd(work, (unsigned long long)FETCH_BLOCK);
+        const unsigned lo = __shfl((unsigned)base, 0);
+        const unsigned hi = __shfl((unsigned)(base >> 32), 0);
+        pool_next = ((uint64_t)hi << 32) | lo;
+        pool_end = pool_next + FETCH_BLOCK;
+        if (rank >= avail) id = pool_next + (rank - avail);
+        pool_next += n - avail;
+    } else {
+        pool_next += n;
+    }
+    return id;
 }
 
 // Error-free FP32 accumulation: the sum goes to pair[0], the rounding error
@@ -236,13 +254,13 @@ __device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* ma
     return A.beta[k];
 }
 
-// The same value as one unconditional load: an empty voxel reads a zero word
-// that every lane shares (one cache line, no gather), so that the loaded
-// register can stay in flight across a step without a select or a copy.
+// The same value as one unconditional load: an empty voxel reads the zero
+// after the last voxel, which every lane shares (one cache line, no
+// gather), so that the loaded register can stay in flight across a step
+// without a select or a copy.
 template <typename Real>
 __device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k) {
-    const Real* p = (mask && !occupied(A, mask, k)) ? A.zero : A.beta + k;
-    return *p;
+    return A.beta[occupied(A, mask, k) ? (uint32_t)k : (uint32_t)A.n_vox];
 }
 
 // ---------------------------------------------------------------------------
@@ -272,12 +290,19 @@ __device__ __forceinline__ void launch_photon(const KArgs<Real>& A, uint64_t pid
 }
 
 // Steps (ii)-(iii): returns 0 on a collision (position and voxel updated),
-// else 1 + face code (0 top, 1 bottom, 2 side), with the position unchanged
-// and t_exit set.  The extinction of the next voxel is loaded one crossing
-// ahead of its use.
+// 1 + face code (0 top, 1 bottom, 2 side) when the photon left the domain
+// (position unchanged, t_exit set), or FLIGHT_GOES_ON when `budget` voxels
+// were crossed without either: the photon then stands at the entry point of
+// its current voxel with the optical depth still to fly, and the next call
+// continues the flight.  (A wavefront steps all its photons' flights
+// together; a budget keeps the lanes whose flights are short from waiting
+// for the longest one.)
+constexpr int FLIGHT_GOES_ON = 4;
+constexpr uint32_t FLIGHT_BUDGET = 32;
+
 template <typename Real>
 __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t* mask, Photon<Real>& ph,
-                                           uint64_t& vfree) {
+                                           uint64_t& vfree, uint32_t budget) {
     WalkRegs<Real> W;
     const Real f0x = ph.fx, f0y = ph.fy, f0z = ph.fz;
     const Real wx = ph.wx, wy = ph.wy, wz = ph.wz;
@@ -305,16 +330,22 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
             left = cz ? (W.sz > 0 ? 1 : 2) : 3;
             break;
         }
+        if (steps >= budget) {
+            left = FLIGHT_GOES_ON;
+            tc = W.t;
+            break;
+        }
         b = beta_at(A, mask, W.k);
     }
     vfree += steps;
-    if (left == 0) {
+    if (left == 0 || left == FLIGHT_GOES_ON) {
         ph.fx = walk_frac(f0x, W.sfx, W.rx, wx, A.G.idx, tc);
         ph.fy = walk_frac(f0y, W.sfy, W.ry, wy, A.G.idy, tc);
         ph.fz = walk_frac(f0z, W.sfz, W.rz, wz, A.G.idz, tc);
         ph.ix = W.ix;
         ph.iy = W.iy;
         ph.iz = W.iz;
+        if (left == FLIGHT_GOES_ON) ph.taustar = taustar - tau;
     } else {
         ph.t_exit = W.t;
     }
@@ -517,9 +548,11 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     // the last voxel's term cur * lp is left to job_finish, as
     // (b0 + b1) * lp with the other register zero, so that no step waits for
     // a fetch it has just issued.
+    // (branch free: the job phase always has the LDS mask, and voxel 0 is a
+    // valid index to test when the ray is done)
     const int kk = done ? 0 : J.W.k;
-    const bool none = scatter || done || (mask && !occupied(A, mask, kk));
-    prev = *(none ? A.zero : A.beta + kk);
+    const bool none = (int)scatter | (int)done | (int)!occupied(A, mask, kk);
+    prev = A.beta[none ? (uint32_t)A.n_vox : (uint32_t)kk];
     return done;
 }
 
@@ -629,13 +662,15 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
         // queued), in pairs of steps (a job always starts with step 0)
         const uint32_t keep = (qtail - qhead) > 0 ? (uint32_t)WAVE - REFILL_IDLE : 0u;
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-            if (busy && job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J)) {
-                busy = false;
-                fin = true;
+            if (busy) {
+                const bool d = job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J);
+                busy = !d;
+                fin = d;
             }
-            if (busy && job_step<Real, MODE, TALLY, 1>(A, mask, lds_grad, J)) {
-                busy = false;
-                fin = true;
+            if (busy) {
+                const bool d = job_step<Real, MODE, TALLY, 1>(A, mask, lds_grad, J);
+                busy = !d;
+                fin = d;
             }
         }
     }
@@ -672,6 +707,7 @@ __global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_ren
     Photon<Real> ph;
     Job<Real> J;
     bool alive = false, exhausted = false, busy = false, fin = false;
+    uint64_t pool_next = 0, pool_end = 0;
     uint32_t qhead = 0, qtail = 0;
     uint32_t n_ev = 0, n_le = 0;
     uint64_t vfree = 0, vconn = 0;
@@ -680,20 +716,25 @@ __global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_ren
     uint32_t w_used = 0;
 
     for (;;) {
-        if (!alive && !exhausted) {
-            const uint64_t k = wave_fetch(A.work);
-            if (k < A.n_photons) {
-                launch_photon(A, A.pid0 + k, ph);
-                alive = true;
-            } else {
-                exhausted = true;
+        const unsigned long long need = __ballot(!alive && !exhausted);
+        if (need) {
+            const uint64_t k = wave_fetch(A.work, need, pool_next, pool_end);
+            if (!alive && !exhausted) {
+                if (k < A.n_photons) {
+                    launch_photon(A, A.pid0 + k, ph);
+                    alive = true;
+                } else {
+                    exhausted = true;
+                }
             }
         }
         if (__ballot(alive) == 0ull) break;
         bool collided = false;
         if (alive) {
-            const int left = free_flight(A, mask, ph, vfree);
-            if (left) {
+            const int left = free_flight(A, mask, ph, vfree, FLIGHT_BUDGET);
+            if (left == FLIGHT_GOES_ON) {
+                // still flying: continues at the next photon phase
+            } else if (left) {
                 atomicAdd(&s_st[ST_TOP + left - 1], 1ull);
                 alive = false;
             } else {
@@ -1150,7 +1191,7 @@ __global__ void __launch_bounds__(BLOCK) k_trace(KArgs<Real> A) {
     launch_photon(A, A.first_pid + tid, ph);
     uint64_t vfree = 0;
     for (;;) {
-        const int left = free_flight(A, (const uint32_t*)nullptr, ph, vfree);
+        const int left = free_flight(A, (const uint32_t*)nullptr, ph, vfree, 0xffffffffu);
         if (left) {
             record_path(A, tid, ph, left - 1);
             return;

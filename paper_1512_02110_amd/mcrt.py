@@ -50,11 +50,31 @@ STAT_FIELDS = ["photons", "events", "le_jobs", "vox_free", "vox_conn", "esc_top"
                "esc_side", "rr_killed", "capped"]
 
 
+TIMING_FIELDS = ["transport_ms", "tape_ms"]
+
+
+class Stats(dict):
+    """The counters of a call (a dict, compared as one); `.timing` holds the
+    device times the library measured with HIP events."""
+    timing: dict = {}
+
+
+def _stats(st) -> "Stats":
+    out = Stats(st.as_dict())
+    out.timing = st.timing()
+    return out
+
+
 class McStats(C.Structure):
-    _fields_ = [(n, C.c_uint64) for n in STAT_FIELDS]
+    _fields_ = [(n, C.c_uint64) for n in STAT_FIELDS] + [(n, C.c_double) for n in TIMING_FIELDS]
 
     def as_dict(self):
+        """The counters (deterministic for a given photon range)."""
         return {n: int(getattr(self, n)) for n in STAT_FIELDS}
+
+    def timing(self):
+        """Device times (ms) the library measured with HIP events."""
+        return {n: float(getattr(self, n)) for n in TIMING_FIELDS}
 
 
 EVENT_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("w", "<f8"),
@@ -177,7 +197,7 @@ def mc_render(s, beta, transport="fp32", tally="f64", stats=True, out=None, stre
                                   C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
                                   C.c_void_p(_stream(torch, stream)))
     _check("mc_render", rc)
-    return img, (st.as_dict() if stats else None)
+    return img, (_stats(st) if stats else None)
 
 
 def mc_render_moments(s, beta, transport="fp32", tally="f64", stats=True, stream=None, **kw):
@@ -195,7 +215,7 @@ def mc_render_moments(s, beta, transport="fp32", tally="f64", stats=True, stream
                                           C.c_void_p(img.data_ptr()), C.c_void_p(m2.data_ptr()),
                                           C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
     _check("mc_render_moments", rc)
-    return img, m2, (st.as_dict() if stats else None)
+    return img, m2, (_stats(st) if stats else None)
 
 
 def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True, out=None,
@@ -214,7 +234,7 @@ def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True,
                                      C.c_void_p(dl.data_ptr()), C.c_void_p(g.data_ptr()),
                                      C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
     _check("mc_grad_beta", rc)
-    return g, (st.as_dict() if stats else None)
+    return g, (_stats(st) if stats else None)
 
 
 def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pix=True,
