@@ -39,9 +39,11 @@
 namespace mcrt {
 
 constexpr int WAVE = 64;
-constexpr int WAVES = BLOCK / WAVE;
 constexpr uint32_t QCAP = 128;     // local-estimate jobs per wavefront queue
 constexpr uint32_t REFILL_IDLE = 16;
+// The deposit refills later: its per-record set-up is long and runs on the
+// refilled lanes only.
+constexpr uint32_t DEP_REFILL_IDLE = 32;
 
 // Photon packet: voxel-local position (voxel i, fraction f of the voxel
 // edge), direction, weight and the optical depth still to fly.
@@ -533,25 +535,26 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     const bool last = tn >= J.r;
     const Real tend = last ? J.r : tn;
     const Real l = tend - J.W.t;
-    const bool scatter = MODE == MODE_GRAD && J.phase == 2;
-    if (scatter) {
+    if (MODE == MODE_GRAD && J.phase == 2) {
+        // second walk of the gradient: only the deposit
         grad_add<Real, TALLY>(A, lds_grad, J.W.k, -J.a * (double)l);
-    } else {
-        J.tau += (double)prev * (double)J.lp;
-        J.lp = l;
-        ++J.steps;
+        conn_cross(J.W, tn, cx, cy, cz);
+        return last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
     }
+    J.tau += (double)prev * (double)J.lp;
+    J.lp = l;
+    ++J.steps;
     conn_cross(J.W, tn, cx, cy, cz);
     const bool done = last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
     // the next fetch is issued unconditionally (the shared zero word when the
-    // ray is done, scatters, or enters an empty run).  When the ray is done,
+    // ray is done or enters an empty run).  When the ray is done,
     // the last voxel's term cur * lp is left to job_finish, as
     // (b0 + b1) * lp with the other register zero, so that no step waits for
     // a fetch it has just issued.
     // (branch free: the job phase always has the LDS mask, and voxel 0 is a
     // valid index to test when the ray is done)
     const int kk = done ? 0 : J.W.k;
-    const bool none = (int)scatter | (int)done | (int)!occupied(A, mask, kk);
+    const bool none = (int)done | (int)!occupied(A, mask, kk);
     prev = A.beta[none ? (uint32_t)A.n_vox : (uint32_t)kk];
     return done;
 }
@@ -685,21 +688,32 @@ struct RenderWaves {
     static constexpr int value = sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE) ? 4 : 1;
 };
 
+// Threads per block: 512 for the gradient, whose privatised copy of the
+// gradient (up to 64 KB of LDS per block) is then shared by 8 wavefronts, so
+// that the copies do not limit the wavefronts per CU; 256 otherwise.
+template <int MODE>
+struct RenderThreads {
+    static constexpr int value = MODE == MODE_GRAD ? 512 : 256;
+};
+
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
 // the gradient is privatised, one double per voxel.
 template <typename Real, int MODE, int TALLY>
-__global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_render(KArgs<Real> A) {
-    __shared__ JobQueue<Real, MODE> s_q[WAVES];
+__global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Real, MODE>::value))
+    k_render(KArgs<Real> A) {
+    constexpr int NT = RenderThreads<MODE>::value;
+    constexpr int NW = NT / WAVE;
+    __shared__ JobQueue<Real, MODE> s_q[NW];
     __shared__ unsigned long long s_st[ST_N];
     extern __shared__ uint32_t s_dyn[];
     uint32_t* s_mask = s_dyn;
     double* lds_grad = nullptr;
     if (MODE == MODE_GRAD && A.grad_lds) {
         lds_grad = reinterpret_cast<double*>(s_dyn + ((A.mask_words + 1) & ~1));
-        for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) lds_grad[i] = 0.0;
+        for (int64_t i = threadIdx.x; i < A.n_vox; i += NT) lds_grad[i] = 0.0;
     }
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
-    for (int i = threadIdx.x; i < A.mask_words; i += BLOCK) s_mask[i] = A.mask[i];
+    for (int i = threadIdx.x; i < A.mask_words; i += NT) s_mask[i] = A.mask[i];
     __syncthreads();
     const uint32_t* mask = s_mask;
     JobQueue<Real, MODE>& Q = s_q[threadIdx.x / WAVE];
@@ -711,7 +725,7 @@ __global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_ren
     uint32_t qhead = 0, qtail = 0;
     uint32_t n_ev = 0, n_le = 0;
     uint64_t vfree = 0, vconn = 0;
-    const uint32_t wave_id = blockIdx.x * WAVES + threadIdx.x / WAVE;
+    const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
     const uint32_t w_first = MODE == MODE_TAPE ? wave_id * A.tp.rw : 0u;
     uint32_t w_used = 0;
 
@@ -793,7 +807,7 @@ __global__ void __launch_bounds__(BLOCK, (RenderWaves<Real, MODE>::value)) k_ren
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
     if (lds_grad) {
-        for (int64_t i = threadIdx.x; i < A.n_vox; i += BLOCK) {
+        for (int64_t i = threadIdx.x; i < A.n_vox; i += NT) {
             const double v = lds_grad[i];
             if (v != 0.0) tally_f64<TALLY>(A.grad, A.grad32, i, v);
         }
@@ -1134,7 +1148,7 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
         // walk until a quarter of the lanes are idle while slots are left;
         // after that, until one more lane is idle (a busy lane may hold the
         // last prefetched records), and at the very end until all are
-        const uint32_t keep = more ? (uint32_t)WAVE - REFILL_IDLE : (pending && nbusy > 0 ? nbusy - 1 : 0u);
+        const uint32_t keep = more ? (uint32_t)WAVE - DEP_REFILL_IDLE : (pending && nbusy > 0 ? nbusy - 1 : 0u);
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
             if (busy) {
                 const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
@@ -1364,7 +1378,7 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
 template <typename Real, int MODE, int TALLY>
 static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
     const size_t dyn = render_dyn_lds(a, MODE);
-    hipLaunchKernelGGL((k_render<Real, MODE, TALLY>), dim3(grid), dim3(BLOCK), dyn, s, a);
+    hipLaunchKernelGGL((k_render<Real, MODE, TALLY>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn, s, a);
     return hipGetLastError();
 }
 
@@ -1385,8 +1399,8 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
 
 template <typename Real, int MODE, int TALLY>
 static hipError_t occ_r(const KArgs<Real>& a, int* b) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY>, BLOCK,
-                                                        render_dyn_lds(a, MODE));
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY>,
+                                                        RenderThreads<MODE>::value, render_dyn_lds(a, MODE));
 }
 
 template <typename Real>
