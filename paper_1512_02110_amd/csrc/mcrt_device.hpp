@@ -49,6 +49,10 @@ __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+// Square root without the IEEE refinement (float: the hardware's ~1 ulp
+// result); for lengths whose last bit does not matter.
+__device__ __forceinline__ float m_sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double m_sqrt_fast(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_rsqrt(float x) { return 1.0f / sqrtf(x); }
 __device__ __forceinline__ double m_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }

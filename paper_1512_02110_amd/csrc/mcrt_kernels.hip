@@ -979,7 +979,7 @@ struct DepWalk {
 // Camera centre in voxel units (integer and fraction), as the deposit keeps
 // it in LDS.
 template <typename Real>
-struct CamCentre {
+struct alignas(16) CamCentre {
     int ix, iy, iz;
     Real fx, fy, fz;
 };
@@ -987,7 +987,7 @@ struct CamCentre {
 // Start the deposit of binned record R: a / beta(k_e) if the ray starts in
 // the tile, then the walk of the part of the ray inside the tile (false
 // when the record is empty or that part has no length).
-template <typename Real>
+template <typename Real, bool CAMS_LDS>
 __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
                                               const CamCentre<Real>* s_cam, const TapeRec<Real>& R, double* s_g,
                                               DepWalk<Real>& D, double& a) {
@@ -995,8 +995,10 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     a = (double)R.a;
     const int i0x = (int)(R.vox & 2047u), i0y = (int)((R.vox >> 11) & 2047u), i0z = (int)(R.vox >> 22);
     if (i0x >= A.G.nx || i0y >= A.G.ny || i0z >= A.G.nz || R.id >= (uint32_t)A.n_cams) return false;
+    // all cameras in LDS, or all read from global memory: one kind of load
+    // (a choice per lane would become a generic-address load)
     CamCentre<Real> cc;
-    if (R.id < (uint32_t)DEP_LDS_CAMS) {
+    if (CAMS_LDS) {
         cc = s_cam[R.id];
     } else {
         const DevCam<Real>& cam = A.cams[R.id];
@@ -1011,7 +1013,7 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     const Real dx = ((Real)(i0x - cc.ix) + (R.fx - cc.fx)) * A.G.dx;
     const Real dy = ((Real)(i0y - cc.iy) + (R.fy - cc.fy)) * A.G.dy;
     const Real dz = ((Real)(i0z - cc.iz) + (R.fz - cc.fz)) * A.G.dz;
-    const Real r = m_sqrt(dx * dx + dy * dy + dz * dz);
+    const Real r = m_sqrt_fast(dx * dx + dy * dy + dz * dz);
     const Real ir = m_rcp(r);
     const Real vx = -dx * ir, vy = -dy * ir, vz = -dz * ir;
     const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
@@ -1082,10 +1084,10 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
 
 // Each lane keeps the next record it will walk in registers, loaded one
 // refill ahead, so that a refill does not wait for memory.
-template <typename Real, int TALLY>
+template <typename Real, int TALLY, bool CAMS_LDS>
 __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const DepositItem* items) {
     __shared__ double s_g[TILE_VOX];
-    __shared__ CamCentre<Real> s_cam[DEP_LDS_CAMS];
+    __shared__ CamCentre<Real> s_cam[CAMS_LDS ? DEP_LDS_CAMS : 1];
     __shared__ uint32_t s_next;
     const Tape<Real>& P = A.tp;
     const DepositItem it = items[blockIdx.x];
@@ -1098,7 +1100,7 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     L.nxy = L.nx * L.ny;
     const int nloc = L.nxy * L.nz;
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
-    for (int i = threadIdx.x; i < A.n_cams && i < DEP_LDS_CAMS; i += DEPOSIT_BLOCK) {
+    for (int i = threadIdx.x; CAMS_LDS && i < A.n_cams; i += DEPOSIT_BLOCK) {
         const DevCam<Real>& cam = A.cams[i];
         CamCentre<Real> cc;
         cc.ix = cam.icx;
@@ -1121,7 +1123,7 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     for (;;) {
         // idle lanes start their prefetched record
         if (!busy && has) {
-            busy = deposit_begin(A, L, b0x, b0y, b0z, s_cam, nxt, s_g, D, a);
+            busy = deposit_begin<Real, CAMS_LDS>(A, L, b0x, b0y, b0z, s_cam, nxt, s_g, D, a);
             has = false;
         }
         // lanes without a prefetched record take the next slots of the range
@@ -1438,10 +1440,15 @@ template hipError_t launch_bin<double>(const KArgs<double>&, bool, int, hipStrea
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (tally == TALLY_F64)
-        hipLaunchKernelGGL((k_deposit<Real, TALLY_F64>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+    const bool lds = a.n_cams <= DEP_LDS_CAMS;
+    if (tally == TALLY_F64 && lds)
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_F64, true>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+    else if (tally == TALLY_F64)
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_F64, false>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+    else if (lds)
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_K32, true>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
     else
-        hipLaunchKernelGGL((k_deposit<Real, TALLY_K32>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
+        hipLaunchKernelGGL((k_deposit<Real, TALLY_K32, false>), dim3(n_items), dim3(DEPOSIT_BLOCK), 0, s, a, items);
     return hipGetLastError();
 }
 
