@@ -1082,6 +1082,28 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     return true;
 }
 
+// One voxel of a deposit walk.  Every lane of the wavefront runs the
+// arithmetic (no branch around it); only busy lanes deposit, and an idle
+// lane's walk state is reset by deposit_begin before it is used again.
+template <typename Real>
+__device__ __forceinline__ void dep_step(DepWalk<Real>& D, double* s_g, double a, int nloc, bool& busy) {
+    const int kx = D.kx, ky = D.ky, kz = D.kz;
+    const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
+    const bool cy = !cx && (D.ty <= D.tz);
+    const Real tn = fmin(D.tx, fmin(D.ty, D.tz));
+    const bool last = tn >= D.len;
+    const Real l = (last ? D.len : tn) - D.t;
+    if (busy) atomicAdd(s_g + D.k, -a * (double)l);
+    D.k += cx ? kx : (cy ? ky : kz);
+    D.tx += cx ? D.dtx : (Real)0;
+    D.ty += cy ? D.dty : (Real)0;
+    D.tz += (!cx && !cy) ? D.dtz : (Real)0;
+    D.t = tn;
+    // a crossing that rounding put just before the end of the clipped ray
+    // must not leave the tile's LDS copy
+    busy = busy && !(last || (unsigned)D.k >= (unsigned)nloc);
+}
+
 // Each lane keeps the next record it will walk in registers, loaded one
 // refill ahead, so that a refill does not wait for memory.
 template <typename Real, int TALLY, bool CAMS_LDS>
@@ -1133,7 +1155,9 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
                 const int leader = __ffsll((long long)want) - 1;
                 uint32_t first = 0;
                 if (__lane_id() == leader) first = atomicAdd(&s_next, (uint32_t)__popcll(want));
-                first = __shfl(first, leader);
+                // the leader's value, read into a scalar register, keeps the
+                // loop below uniform for the compiler
+                first = __builtin_amdgcn_readlane(first, leader);
                 if (first + (uint32_t)__popcll(want) >= hi) more = false;
                 if (!has) {
                     const uint32_t s = first + lanes_below(want);
@@ -1152,22 +1176,8 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
         // last prefetched records), and at the very end until all are
         const uint32_t keep = more ? (uint32_t)WAVE - DEP_REFILL_IDLE : (pending && nbusy > 0 ? nbusy - 1 : 0u);
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-            if (busy) {
-                const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
-                const bool cy = !cx && (D.ty <= D.tz);
-                const Real tn = fmin(D.tx, fmin(D.ty, D.tz));
-                const bool last = tn >= D.len;
-                const Real l = (last ? D.len : tn) - D.t;
-                atomicAdd(s_g + D.k, -a * (double)l);
-                D.k += cx ? D.kx : (cy ? D.ky : D.kz);
-                D.tx += cx ? D.dtx : (Real)0;
-                D.ty += cy ? D.dty : (Real)0;
-                D.tz += (!cx && !cy) ? D.dtz : (Real)0;
-                D.t = tn;
-                // a crossing that rounding put just before the end of the
-                // clipped ray must not leave the tile's LDS copy
-                if (last || (unsigned)D.k >= (unsigned)nloc) busy = false;
-            }
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
         }
     }
     __syncthreads();
