@@ -121,15 +121,17 @@ constexpr int TAPE_FALLBACK = 1;
 // Gradient of a large grid through the tape, in chunks of photons:
 //   1. replay the chunk (k_render, MODE_TAPE): every wavefront writes the
 //      connection rays with a non-zero weight to its slice of the ray tape;
-//   2. count the rays crossing each tile (k_bin, count pass) and read the
-//      counts back;
-//   3. for groups of tiles whose bins fit the bin space: copy the rays into
-//      the bins (k_bin, scatter pass) and deposit every tile (k_deposit).
-// A chunk whose rays overflowed a wavefront slice, or with a tile bin larger
+//   2. count the rays crossing each tile, per block of the binning passes
+//      (k_bin, count pass), and read the totals back;
+//   3. for groups of tiles whose bins fit the bin space: turn the block
+//      counts into bin slots (k_bin_scan), copy the rays into the bins (k_bin,
+//      scatter pass) and deposit every tile (k_deposit).
+// The tape space is split between rays and bins per chunk, from the rays
+// per photon of the busiest wavefront and the tile crossings per photon of
+// the chunks so far, so that a chunk's bins usually fit in one group.  A
+// chunk whose rays overflowed a wavefront slice, or with a tile bin larger
 // than the bin space, is replayed smaller before anything of it reaches the
-// gradient.  Chunks are sized from the rays per photon of the busiest
-// wavefront of the chunks so far.  Stats of the completed chunks are summed
-// into host_sum.
+// gradient.  Stats of the completed chunks are summed into host_sum.
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
@@ -144,14 +146,17 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     const int wpb = BLOCK / 64;  // wavefronts per block
     size_t free_b = 0, total_b = 0;
     char* pool = nullptr;
-    uint32_t* meta = nullptr;  // tile_count[nt], cursor[nt], tile_end[nt], overflow, wave_count[]
+    // tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
+    uint32_t* meta = nullptr;
     DepositItem* ditems = nullptr;
     const int max_items = nt + 4 * n_cu + 1;
-    std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt), h_wave((size_t)max_blocks * wpb);
+    std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
+    std::vector<uint32_t> h_wave;
     std::vector<DepositItem> h_items;
     unsigned long long h_ctr[1 + ST_N];
     uint32_t h_over = 0;
-    uint64_t P = 0, r_cap = 0, b_cap = 0, done = 0, chunk = 0;
+    uint64_t P = 0, r_cap = 0, r_min = 0, done = 0, chunk = 0;
+    int max_nw = 0;
 
     CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
     {
@@ -160,12 +165,14 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
         if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
     }
-    // half for the rays, half for the bins; at least 64 ray slots per
-    // wavefront (fewer resident blocks if the tape is small)
+    // the rays get between an eighth and seven eighths of the space, and at
+    // least 64 slots per wavefront (fewer resident blocks if the tape is small)
+    r_min = P / 8;
+    if (r_min < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_min / (64 * (uint64_t)wpb));
+    if (max_blocks < 1 || P - r_min < 64) return TAPE_FALLBACK;
+    max_nw = max_blocks * wpb;
+    h_wave.resize(max_nw);
     r_cap = P / 2;
-    b_cap = P - r_cap;
-    if (r_cap < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_cap / (64 * (uint64_t)wpb));
-    if (max_blocks < 1 || b_cap < 64) return TAPE_FALLBACK;
 
     if (t_transport) {
         CHECK_HIP(hipEventCreate(&r0));
@@ -174,24 +181,27 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(hipEventCreate(&b1));
     }
     CHECK_HIP(hipMallocAsync((void**)&pool, P * rec, stream));
-    CHECK_HIP(hipMallocAsync((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_blocks * wpb),
-                             stream));
+    CHECK_HIP(hipMallocAsync((void**)&meta,
+                             sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
     CHECK_HIP(hipMallocAsync((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     A.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool);
-    A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + r_cap;
     A.tp.tile_count = meta;
-    A.tp.cursor = meta + nt;
+    A.tp.bin_start = meta + nt;
     A.tp.tile_end = meta + 2 * nt;
     A.tp.overflow = meta + 3 * nt;
     A.tp.wave_count = meta + 3 * nt + 1;
+    A.tp.slice = meta + 3 * nt + 1 + max_nw;
 
     // first chunk: a guess of 64 rays per photon
     chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, r_cap / 64));
     while (done < n_photons) {
         const uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
+        const uint64_t b_cap = P - r_cap;
         const int grid = (int)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, (uint64_t)max_blocks);
         const int nw = grid * wpb;
         A.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / nw, 0xffffffffu);
+        A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + r_cap;
+        A.tp.n_slices = nw;  // one binning block per wavefront slice
         A.pid0 = pid0 + done;
         A.n_photons = n;
         CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
@@ -220,8 +230,12 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         uint32_t busiest = 0;
         for (int w = 0; w < nw; ++w) busiest = std::max(busiest, h_wave[w]);
         const double rate = (double)busiest * nw / (double)n;  // rays per photon, busiest wavefront
+        uint64_t crossings = 0;
         bool too_big = h_over != 0;
-        for (int i = 0; i < nt; ++i) too_big = too_big || h_count[i] > b_cap;
+        for (int i = 0; i < nt; ++i) {
+            crossings += h_count[i];
+            too_big = too_big || h_count[i] > b_cap;
+        }
         if (too_big) {
             if (n == 1) {
                 rc = MC_ERR_OUT_OF_MEMORY;
@@ -260,10 +274,11 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
             }
             A.tp.t_lo = g0;
             A.tp.t_hi = g1;
-            CHECK_HIP(hipMemcpyAsync(A.tp.cursor + g0, h_bins.data() + g0, sizeof(uint32_t) * (g1 - g0),
-                                     hipMemcpyHostToDevice, stream));
+            CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.bin_start) + g0, h_bins.data() + g0,
+                                     sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
             CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.tile_end) + g0, h_bins.data() + nt + g0,
                                      sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
+            CHECK_HIP(launch_bin_scan<Real>(A, stream));
             CHECK_HIP(launch_bin<Real>(A, true, nw, stream));
             if (!h_items.empty()) {
                 CHECK_HIP(hipMemcpyAsync(ditems, h_items.data(), sizeof(DepositItem) * h_items.size(),
@@ -278,8 +293,19 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
             pending_b = true;
         }
         done += n;
-        // next chunk: the busiest wavefront's slice about 80% full
-        chunk = rate > 0.0 ? (uint64_t)std::max(1.0, std::floor(0.8 * (double)r_cap / rate)) : n_photons - done;
+        // next chunk: the busiest wavefront's slice about 80% full and the
+        // crossings (with 5% to spare) in the bin space
+        if (rate > 0.0) {
+            const double rays = rate / 0.8, bins = 1.05 * (double)crossings / (double)n;
+            const double fit = std::floor((double)P / (rays + bins));
+            r_cap = (uint64_t)std::ceil(std::max(1.0, fit) * rays);
+            r_cap = std::min(std::max(r_cap, r_min), P - r_min);
+            double next = std::floor((double)r_cap / rays);
+            if (bins > 0.0) next = std::min(next, std::floor((double)(P - r_cap) / bins));
+            chunk = (uint64_t)std::max(1.0, next);
+        } else {
+            chunk = n_photons - done;
+        }
     }
     CHECK_HIP(hipStreamSynchronize(stream));
     if (pending_b) {

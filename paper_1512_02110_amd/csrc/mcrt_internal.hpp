@@ -65,8 +65,12 @@ struct Tape {
     uint32_t* overflow;       // set when a wavefront ran out of slots
     TapeRec<Real>* brec;      // rays binned by tile
     uint32_t* tile_count;     // [n_tiles] records per tile
-    uint32_t* cursor;         // [n_tiles] next binned slot of each tile
-    const uint32_t* tile_end; // [n_tiles] end of each tile's bin
+    // [n_tiles][n_slices]: records of tile t from the rays of block (slice)
+    // b of the binning passes; the scan turns them into first bin slots
+    uint32_t* slice;
+    int n_slices;
+    const uint32_t* bin_start; // [n_tiles] first slot of each tile's bin
+    const uint32_t* tile_end;  // [n_tiles] end of each tile's bin
     int t_lo, t_hi;           // tiles binned by this pass
     int shx, shy, shz;        // tile edges are 2^sh voxels
     int n_tiles;
@@ -117,6 +121,7 @@ constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 L
 constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: up to 104 KB of LDS
 constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS
 constexpr int BIN_GROUP_TILES = 4096; // tiles per scatter pass (3 LDS words each)
+constexpr int SCAN_BLOCK = 256;
 constexpr int DEPOSIT_BLOCK = 1024;
 constexpr int DEP_LDS_CAMS = 512;     // camera centres the deposit keeps in LDS
 
@@ -151,6 +156,8 @@ template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
 template <typename Real>
 hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s);
+template <typename Real>
+hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s);
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s);
 

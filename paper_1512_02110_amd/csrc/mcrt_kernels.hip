@@ -893,66 +893,95 @@ __device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const i
     }
 }
 
-// SCATTER = false: tile_count[t] += rays crossing tile t (all tiles).
-// SCATTER = true: copy every ray, with its camera in place of its pixel,
-// into the bin of every tile in [t_lo, t_hi) it crosses.  The block counts its records per tile in LDS, reserves one
-// range per tile from the tile's cursor, then copies; a reservation is only
-// used up to the end of the tile's bin, and slots of it the copy did not
-// fill get empty records (a = 0), so the bins below the cursors hold no
-// stale data whatever the count pass found.
+// Count pass (scatter = 0): for every tile t, the records of the block's
+// rays in t go to slice[t][block] and are added to tile_count[t].
+// Scatter pass (scatter = 1), after the scan: every ray, with its camera in
+// place of its pixel, is copied into the bin of every tile in [t_lo, t_hi)
+// it crosses, at the block's slots from slice[t][block] on.  Both passes run
+// the same code, so they find the same tiles; should they ever disagree, a
+// block only fills its own slots (extra records are dropped, unfilled slots
+// get empty records with a = 0), so every bin slot holds valid data.
 //
 // Dynamic LDS: the first pixels of the cameras (bin_cams words), then one
 // counter per tile of the pass, and for the scatter two more per tile.
-template <typename Real, bool SCATTER>
-__global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves) {
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves, int scatter) {
     extern __shared__ uint32_t s_bin[];
     const Tape<Real>& P = A.tp;
-    const int lo = SCATTER ? P.t_lo : 0, hi = SCATTER ? P.t_hi : P.n_tiles;
+    const int lo = scatter ? P.t_lo : 0, hi = scatter ? P.t_hi : P.n_tiles;
     const int n_off = min(A.n_cams, BIN_LDS_CAMS);
+    const int b = blockIdx.x;
     int32_t* s_off = reinterpret_cast<int32_t*>(s_bin);
     uint32_t* s_cnt = s_bin + n_off;
     uint32_t* s_base = s_cnt + (hi - lo);
-    uint32_t* s_valid = s_base + (hi - lo);
-    for (int i = threadIdx.x; i < hi - lo; i += BLOCK) s_cnt[i] = 0u;
-    for (int i = threadIdx.x; i < n_off; i += BLOCK) s_off[i] = A.cams[i].pix_off;
-    __syncthreads();
-    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
-        for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
-            if (t >= lo && t < hi) atomicAdd(&s_cnt[t - lo], 1u);
-        });
-    });
-    __syncthreads();
-    if (!SCATTER) {
-        for (int i = threadIdx.x; i < hi - lo; i += BLOCK)
-            if (s_cnt[i]) atomicAdd(&P.tile_count[lo + i], s_cnt[i]);
-        return;
-    }
+    uint32_t* s_lim = s_base + (hi - lo);
     for (int i = threadIdx.x; i < hi - lo; i += BLOCK) {
-        const uint32_t n = s_cnt[i];
-        const uint32_t b = n ? atomicAdd(&P.cursor[lo + i], n) : 0u;
-        const uint32_t end = P.tile_end[lo + i];
-        s_base[i] = b;
-        s_valid[i] = b < end ? min(n, end - b) : 0u;
         s_cnt[i] = 0u;
+        if (scatter) {
+            const size_t row = (size_t)(lo + i) * P.n_slices;
+            const uint32_t first = P.slice[row + b];
+            const uint32_t next = b + 1 < P.n_slices ? P.slice[row + b + 1] : P.tile_end[lo + i];
+            s_base[i] = first;
+            s_lim[i] = next > first ? next - first : 0u;
+        }
     }
+    for (int i = threadIdx.x; i < n_off; i += BLOCK) s_off[i] = A.cams[i].pix_off;
     __syncthreads();
     for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R0, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
         TapeRec<Real> R = R0;
-        R.ab = (Real)((double)R.a / (double)A.beta[ix + A.G.nx * iy + A.G.nxy * iz]);
+        if (scatter) R.ab = (Real)((double)R.a / (double)A.beta[ix + A.G.nx * iy + A.G.nxy * iz]);
         for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
             if (t >= lo && t < hi) {
                 const uint32_t p = atomicAdd(&s_cnt[t - lo], 1u);
-                if (p < s_valid[t - lo]) P.brec[s_base[t - lo] + p] = R;
+                if (scatter && p < s_lim[t - lo]) P.brec[s_base[t - lo] + p] = R;
             }
         });
     });
     __syncthreads();
+    if (!scatter) {
+        for (int i = threadIdx.x; i < hi - lo; i += BLOCK) {
+            const uint32_t n = s_cnt[i];
+            P.slice[(size_t)(lo + i) * P.n_slices + b] = n;
+            if (n) atomicAdd(&P.tile_count[lo + i], n);
+        }
+        return;
+    }
     TapeRec<Real> E;
     E.vox = 0u;
     E.id = 0u;
     E.fx = E.fy = E.fz = E.a = E.ab = (Real)0;
     for (int i = 0; i < hi - lo; ++i)
-        for (uint32_t p = s_cnt[i] + threadIdx.x; p < s_valid[i]; p += BLOCK) P.brec[s_base[i] + p] = E;
+        for (uint32_t p = s_cnt[i] + threadIdx.x; p < s_lim[i]; p += BLOCK) P.brec[s_base[i] + p] = E;
+}
+
+// Scan of the count pass: for each tile t of [t_lo, t_hi) (one block per
+// tile), slice[t][b] becomes bin_start[t] + the records of slices 0..b-1.
+template <typename Real>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_bin_scan(KArgs<Real> A) {
+    __shared__ uint32_t s_sum[SCAN_BLOCK];
+    const Tape<Real>& P = A.tp;
+    const int t = P.t_lo + blockIdx.x;
+    const int n = P.n_slices;
+    uint32_t* row = P.slice + (size_t)t * n;
+    const int per = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const int i0 = min(n, (int)threadIdx.x * per), i1 = min(n, i0 + per);
+    uint32_t sum = 0u;
+    for (int i = i0; i < i1; ++i) sum += row[i];
+    s_sum[threadIdx.x] = sum;
+    __syncthreads();
+    // inclusive scan of the per-thread sums (Hillis-Steele)
+    for (int d = 1; d < SCAN_BLOCK; d <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)d ? s_sum[threadIdx.x - d] : 0u;
+        __syncthreads();
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = P.bin_start[t] + (threadIdx.x ? s_sum[threadIdx.x - 1] : 0u);
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t c = row[i];
+        row[i] = run;
+        run += c;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1133,8 +1162,8 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
         cc.fz = cam.fcz;
         s_cam[i] = cc;
     }
-    // every slot below the tile's cursor holds a record (or an empty one)
-    const uint32_t hi = min(it.hi, P.cursor[it.tile]);
+    // every slot of the tile's bin holds a record (or an empty one)
+    const uint32_t hi = it.hi;
     if (threadIdx.x == 0) s_next = it.lo;
     __syncthreads();
 
@@ -1437,15 +1466,22 @@ hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream
     const int grid = n_waves;  // one wavefront slice per block
     const size_t tiles = scatter ? (size_t)(a.tp.t_hi - a.tp.t_lo) : (size_t)a.tp.n_tiles;
     const size_t dyn = sizeof(uint32_t) * ((size_t)std::min(a.n_cams, BIN_LDS_CAMS) + (scatter ? 3 : 1) * tiles);
-    if (scatter)
-        hipLaunchKernelGGL((k_bin<Real, true>), dim3(grid), dim3(BLOCK), dyn, s, a, n_waves);
-    else
-        hipLaunchKernelGGL((k_bin<Real, false>), dim3(grid), dim3(BLOCK), dyn, s, a, n_waves);
+    if (grid != a.tp.n_slices) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bin<Real>, dim3(grid), dim3(BLOCK), dyn, s, a, n_waves, scatter ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s) {
+    if (a.tp.t_hi <= a.tp.t_lo) return hipSuccess;
+    hipLaunchKernelGGL(k_bin_scan<Real>, dim3(a.tp.t_hi - a.tp.t_lo), dim3(SCAN_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
 template hipError_t launch_bin<float>(const KArgs<float>&, bool, int, hipStream_t);
 template hipError_t launch_bin<double>(const KArgs<double>&, bool, int, hipStream_t);
+template hipError_t launch_bin_scan<float>(const KArgs<float>&, hipStream_t);
+template hipError_t launch_bin_scan<double>(const KArgs<double>&, hipStream_t);
 
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s) {
