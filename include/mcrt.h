@@ -33,7 +33,11 @@
  *   - The library allocates its own scratch (counters, the camera table,
  *     per-pixel weights and, for mc_grad_beta on large grids, the ray tape
  *     bounded by params->tape_limit) stream-ordered on `hip_stream` and
- *     releases it stream-ordered before returning.
+ *     releases it stream-ordered before returning.  The allocations come
+ *     from a memory pool of the library (one per device) that keeps freed
+ *     memory for later calls instead of returning it to the device, and the
+ *     two large buffers (a kept render's rays, a gradient's bins) stay
+ *     allocated between calls for reuse; mc_release_memory returns both.
  *   - 1 <= n_cams <= 65535; the pixels of all cameras number < 2^31.
  *   - Return value: MC_OK (0) or a negative MC_ERR_* code; the library never
  *     prints or aborts.  On an argument error nothing is enqueued.  On
@@ -114,7 +118,7 @@ typedef struct mc_params {
     int32_t tape_limit;       /* mc_grad_beta on grids too large for an LDS copy of the
                                  gradient: most records of its ray tape (stream-ordered
                                  scratch of 4 + 8 sizeof(real) bytes each); 0 = automatic
-                                 (up to a quarter of free device memory, at most 16 GiB).
+                                 (up to a quarter of free device memory, at most 32 GiB).
                                  A smaller tape means more, smaller replay chunks.  >= 0. */
 } mc_params;
 
@@ -172,6 +176,42 @@ int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const m
 int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
                  const mc_params* params, const double* dl_dimages, double* grad_beta,
                  mc_stats* stats, void* hip_stream);
+
+/* Reverse mode with a stored tape instead of a replay.
+ * mc_render_tape is mc_render that also keeps, in device memory the library
+ * allocates, every connection ray of the render (start point, pixel, local
+ * estimate C_e) for mc_grad_beta_tape, which then bins and deposits those
+ * rays (Eq. DivTc with the weights of Sec. 5.2) without tracing the photons
+ * again.  *tape is set to NULL (and the call still renders) when the grid
+ * is small enough for mc_grad_beta's in-LDS gradient (no tape needed), when
+ * the rays do not fit (params->tape_limit records if > 0, else three
+ * eighths of the free device memory) or when the grid has too many tiles.
+ * mc_render_tape always waits for the stream.
+ * mc_grad_beta_tape: same contract as mc_grad_beta for the render that made
+ * the tape: grid, cameras and every parameter except tally and tape_limit
+ * must equal those of mc_render_tape (MC_ERR_INVALID_ARG otherwise), and
+ * beta must hold the same values (not checked).  The tape is not consumed;
+ * params->tape_limit bounds the bin space.  stats reports the render's
+ * counters, transport_ms = 0 and the binning and deposit time in tape_ms.
+ * mc_tape_free releases the tape's memory (stream-ordered on hip_stream, so
+ * work already enqueued that reads it completes first); NULL is accepted.
+ * A tape belongs to the device that was current for mc_render_tape. */
+typedef struct mc_tape mc_tape;
+
+int mc_render_tape(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                   const mc_params* params, double* images, mc_stats* stats, void* hip_stream, mc_tape** tape);
+
+int mc_grad_beta_tape(const mc_tape* tape, const mc_grid* grid, const void* beta, int n_cams,
+                      const mc_camera* cams, const mc_params* params, const double* dl_dimages, double* grad_beta,
+                      mc_stats* stats, void* hip_stream);
+
+int mc_tape_free(mc_tape* tape, void* hip_stream);
+
+/* Returns the device memory the library keeps for reuse on the current
+ * device (its pool and its cached large buffers, except what a live tape or
+ * a call in flight uses) to the device.  Call it when the streams the
+ * library used are idle. */
+int mc_release_memory(void);
 
 /* Test and diagnostics export: the first max_rec collisions of each of the
  * photons first_pid .. first_pid+count-1, for path-by-path comparison.

@@ -4,11 +4,31 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mcrt_internal.hpp"
 
 using namespace mcrt;
+
+// The rays of a render kept for a later gradient (mc_render_tape): one
+// slice of rw records per wavefront of the render, and what the render was
+// called with, so that mc_grad_beta_tape can check that it asks for the
+// gradient of the same render.
+struct mc_tape {
+    uint32_t magic;
+    int device;
+    mc_grid grid;
+    mc_params params;
+    int n_cams;
+    uint64_t cam_hash;          // FNV-1a of the camera structs
+    size_t rec_bytes;           // bytes of one record (precision)
+    void* rec;                  // device: nw slices of rw records
+    uint32_t* wave_count;       // device: [nw] records per slice, then the overflow flag
+    int nw;
+    uint32_t rw;
+    unsigned long long counters[1 + ST_N];  // the render's counters (host copy)
+};
 
 namespace {
 
@@ -96,6 +116,139 @@ struct Scratch {
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// Device memory of the library comes from one memory pool per device that
+// keeps what the calls free (release threshold: unlimited), so that the
+// tapes and bins, tens of GB each, are not mapped and unmapped on every
+// call; mc_release_memory hands the cached memory back to the device.  The
+// same lock guards the tape sizing hint (rays per photon of the busiest
+// wavefront of the last kept render on the device).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_mu;
+hipMemPool_t g_pool[MAX_DEVICES] = {};
+double g_tape_rate[MAX_DEVICES] = {};
+
+hipError_t lib_pool(int dev, hipMemPool_t* out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_pool[dev]) {
+        hipMemPoolProps props;
+        std::memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t p = nullptr;
+        hipError_t e = hipMemPoolCreate(&p, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep_all = ~0ull;
+        e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep_all);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(p);
+            return e;
+        }
+        g_pool[dev] = p;
+    }
+    *out = g_pool[dev];
+    return hipSuccess;
+}
+
+// Stream-ordered allocation from the library's pool of the current device
+// (released with hipFreeAsync).
+hipError_t lib_alloc(void** ptr, size_t bytes, hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipMemPool_t pool = nullptr;
+    if ((e = lib_pool(dev, &pool)) != hipSuccess) return e;
+    return hipMallocFromPoolAsync(ptr, bytes, pool, stream);
+}
+
+// The two large buffers of the library, kept per device between calls: the
+// rays of a kept render (BUF_TAPE) and the bins (or replay tape) of a
+// gradient (BUF_BINS).  Freeing and mapping buffers of tens of GB on every
+// call costs hundreds of ms, so a released buffer stays cached, and a later
+// request of at most its size takes it back (its stream first waits for the
+// work of the releasing stream).  A request while the buffer is taken (two
+// tapes alive) is served from the pool.
+enum { BUF_TAPE = 0, BUF_BINS = 1, N_BUFS = 2 };
+struct CachedBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    bool in_use = false;
+    hipEvent_t ready = nullptr;  // recorded where the last user released it
+};
+CachedBuf g_buf[MAX_DEVICES][N_BUFS];
+
+hipError_t buf_acquire(int slot, size_t bytes, hipStream_t stream, void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        CachedBuf& b = g_buf[dev][slot];
+        if (!b.in_use) {
+            if (b.bytes < bytes) {
+                if (b.ptr) {
+                    (void)hipFree(b.ptr);  // waits for the device
+                    b.ptr = nullptr;
+                    b.bytes = 0;
+                }
+                if ((e = hipMalloc(&b.ptr, bytes)) != hipSuccess) {
+                    b.ptr = nullptr;
+                    return e;
+                }
+                b.bytes = bytes;
+            }
+            if (!b.ready) {
+                if ((e = hipEventCreateWithFlags(&b.ready, hipEventDisableTiming)) != hipSuccess) return e;
+            } else if ((e = hipStreamWaitEvent(stream, b.ready, 0)) != hipSuccess) {
+                return e;
+            }
+            b.in_use = true;
+            *ptr = b.ptr;
+            return hipSuccess;
+        }
+    }
+    return lib_alloc(ptr, bytes, stream);
+}
+
+void buf_release(int dev, int slot, void* ptr, hipStream_t stream) {
+    if (!ptr) return;
+    if (dev >= 0 && dev < MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_mu);
+        CachedBuf& b = g_buf[dev][slot];
+        if (b.in_use && b.ptr == ptr) {
+            (void)hipEventRecord(b.ready, stream);
+            b.in_use = false;
+            return;
+        }
+    }
+    (void)hipFreeAsync(ptr, stream);
+}
+
+// Device memory a call can use: free memory plus what the library's pool
+// and buffers hold unused.
+hipError_t available_bytes(size_t* avail) {
+    size_t free_b = 0, total_b = 0;
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    hipMemPool_t pool = nullptr;
+    if ((e = lib_pool(dev, &pool)) != hipSuccess) return e;
+    uint64_t reserved = 0, used = 0;
+    if (hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &reserved) != hipSuccess ||
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrUsedMemCurrent, &used) != hipSuccess) {
+        (void)hipGetLastError();
+        reserved = used = 0;
+    }
+    *avail = free_b + (reserved > used ? (size_t)(reserved - used) : 0);
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (int i = 0; i < N_BUFS; ++i)
+        if (dev < MAX_DEVICES && !g_buf[dev][i].in_use) *avail += g_buf[dev][i].bytes;
+    return hipSuccess;
+}
+
 // Tile edges of the gradient tape, as powers of two (so that the tile of a
 // voxel is a shift away): columns of at most 64 voxels in z and TILE_VOX
 // voxels in all.  Connection rays to cameras below or above the cloud are
@@ -117,6 +270,60 @@ void tape_tiles(const mc_grid* g, int& shx, int& shy, int& shz) {
 }
 
 constexpr int TAPE_FALLBACK = 1;
+
+// Bins and deposits the rays of the binning pass set up in A.tp (slices,
+// records, tile counts h_count from its count pass): groups of tiles whose
+// bins fit together in b_cap slots, each turned into bin slots (k_bin_scan),
+// filled (k_bin, scatter pass) and deposited tile by tile (k_deposit).
+template <typename Real>
+int deposit_groups(KArgs<Real>& A, int tally, const std::vector<uint32_t>& h_count, uint64_t b_cap, int n_cu,
+                   DepositItem* ditems, int max_items, std::vector<uint32_t>& h_bins,
+                   std::vector<DepositItem>& h_items, hipStream_t stream) {
+    int rc = MC_OK;
+    const int nt = A.tp.n_tiles;
+    for (int g0 = 0; g0 < nt;) {
+        // the next group of tiles whose bins fit together
+        uint64_t sum = 0;
+        int g1 = g0;
+        while (g1 < nt && g1 - g0 < BIN_GROUP_TILES && sum + h_count[g1] <= b_cap) sum += h_count[g1++];
+        if (g1 == g0) return MC_ERR_OUT_OF_MEMORY;  // one bin larger than the space (checked by the callers)
+        uint32_t o = 0;
+        for (int i = g0; i < g1; ++i) {
+            h_bins[i] = o;
+            h_bins[nt + i] = o + h_count[i];
+            o += h_count[i];
+        }
+        const uint64_t R = std::max<uint64_t>(8192, (sum + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
+        h_items.clear();
+        for (int i = g0; i < g1; ++i)
+            for (uint64_t lo = 0; lo < h_count[i]; lo += R) {
+                DepositItem d;
+                d.tile = i;
+                d.lo = h_bins[i] + (uint32_t)lo;
+                d.hi = h_bins[i] + (uint32_t)std::min<uint64_t>(h_count[i], lo + R);
+                d.pad_ = 0;
+                h_items.push_back(d);
+            }
+        if ((int)h_items.size() > max_items) return MC_ERR_HIP;
+        A.tp.t_lo = g0;
+        A.tp.t_hi = g1;
+        CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.bin_start) + g0, h_bins.data() + g0,
+                                 sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
+        CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.tile_end) + g0, h_bins.data() + nt + g0,
+                                 sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
+        CHECK_HIP(launch_bin_scan<Real>(A, stream));
+        CHECK_HIP(launch_bin<Real>(A, true, stream));
+        if (!h_items.empty()) {
+            CHECK_HIP(hipMemcpyAsync(ditems, h_items.data(), sizeof(DepositItem) * h_items.size(),
+                                     hipMemcpyHostToDevice, stream));
+            CHECK_HIP(launch_deposit<Real>(A, tally, ditems, (int)h_items.size(), stream));
+        }
+        g0 = g1;
+        if (g0 < nt) CHECK_HIP(hipStreamSynchronize(stream));  // host arrays are reused
+    }
+done:
+    return rc;
+}
 
 // Gradient of a large grid through the tape, in chunks of photons:
 //   1. replay the chunk (k_render, MODE_TAPE): every wavefront writes the
@@ -158,7 +365,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     uint64_t P = 0, r_cap = 0, r_min = 0, done = 0, chunk = 0;
     int max_nw = 0;
 
-    CHECK_HIP(hipMemGetInfo(&free_b, &total_b));
+    CHECK_HIP(available_bytes(&free_b));
     {
         const uint64_t lim = std::min<uint64_t>(free_b / 4, (uint64_t)32 << 30) / rec;
         P = std::max<uint64_t>(n_photons * 48, (uint64_t)1 << 20);
@@ -180,10 +387,10 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(hipEventCreate(&b0));
         CHECK_HIP(hipEventCreate(&b1));
     }
-    CHECK_HIP(hipMallocAsync((void**)&pool, P * rec, stream));
-    CHECK_HIP(hipMallocAsync((void**)&meta,
-                             sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
-    CHECK_HIP(hipMallocAsync((void**)&ditems, sizeof(DepositItem) * max_items, stream));
+    CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
+    CHECK_HIP(lib_alloc((void**)&meta,
+                        sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
+    CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     A.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool);
     A.tp.tile_count = meta;
     A.tp.bin_start = meta + nt;
@@ -201,6 +408,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         const int nw = grid * wpb;
         A.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / nw, 0xffffffffu);
         A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + r_cap;
+        A.tp.w0 = 0;
         A.tp.n_slices = nw;  // one binning block per wavefront slice
         A.pid0 = pid0 + done;
         A.n_photons = n;
@@ -210,7 +418,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         if (r0) CHECK_HIP(hipEventRecord(r0, stream));
         CHECK_HIP(launch_transport<Real>(A, MODE_TAPE, TALLY_F64, grid, stream));
         if (r1) CHECK_HIP(hipEventRecord(r1, stream));
-        CHECK_HIP(launch_bin<Real>(A, false, nw, stream));
+        CHECK_HIP(launch_bin<Real>(A, false, stream));
         CHECK_HIP(hipMemcpyAsync(h_count.data(), A.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost,
                                  stream));
         CHECK_HIP(hipMemcpyAsync(&h_over, A.tp.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
@@ -246,48 +454,8 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         }
         for (int i = 1; i < 1 + ST_N; ++i) host_sum[i] += h_ctr[i];
         if (b0) CHECK_HIP(hipEventRecord(b0, stream));
-        for (int g0 = 0; g0 < nt;) {
-            // the next group of tiles whose bins fit together
-            uint64_t sum = 0;
-            int g1 = g0;
-            while (g1 < nt && g1 - g0 < BIN_GROUP_TILES && sum + h_count[g1] <= b_cap) sum += h_count[g1++];
-            uint32_t o = 0;
-            for (int i = g0; i < g1; ++i) {
-                h_bins[i] = o;
-                h_bins[nt + i] = o + h_count[i];
-                o += h_count[i];
-            }
-            const uint64_t R = std::max<uint64_t>(8192, (sum + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
-            h_items.clear();
-            for (int i = g0; i < g1; ++i)
-                for (uint64_t lo = 0; lo < h_count[i]; lo += R) {
-                    DepositItem d;
-                    d.tile = i;
-                    d.lo = h_bins[i] + (uint32_t)lo;
-                    d.hi = h_bins[i] + (uint32_t)std::min<uint64_t>(h_count[i], lo + R);
-                    d.pad_ = 0;
-                    h_items.push_back(d);
-                }
-            if ((int)h_items.size() > max_items) {
-                rc = MC_ERR_HIP;
-                goto done;
-            }
-            A.tp.t_lo = g0;
-            A.tp.t_hi = g1;
-            CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.bin_start) + g0, h_bins.data() + g0,
-                                     sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
-            CHECK_HIP(hipMemcpyAsync(const_cast<uint32_t*>(A.tp.tile_end) + g0, h_bins.data() + nt + g0,
-                                     sizeof(uint32_t) * (g1 - g0), hipMemcpyHostToDevice, stream));
-            CHECK_HIP(launch_bin_scan<Real>(A, stream));
-            CHECK_HIP(launch_bin<Real>(A, true, nw, stream));
-            if (!h_items.empty()) {
-                CHECK_HIP(hipMemcpyAsync(ditems, h_items.data(), sizeof(DepositItem) * h_items.size(),
-                                         hipMemcpyHostToDevice, stream));
-                CHECK_HIP(launch_deposit<Real>(A, tally, ditems, (int)h_items.size(), stream));
-            }
-            g0 = g1;
-            if (g0 < nt) CHECK_HIP(hipStreamSynchronize(stream));  // host arrays are reused
-        }
+        rc = deposit_groups<Real>(A, tally, h_count, b_cap, n_cu, ditems, max_items, h_bins, h_items, stream);
+        if (rc != MC_OK) goto done;
         if (b1) {
             CHECK_HIP(hipEventRecord(b1, stream));
             pending_b = true;
@@ -314,10 +482,15 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     }
 
 done:
-    for (void* p : {(void*)ditems, (void*)meta, (void*)pool}) {
+    for (void* p : {(void*)ditems, (void*)meta}) {
         if (!p) continue;
         hipError_t e = hipFreeAsync(p, stream);
         if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        buf_release(dev, BUF_BINS, pool, stream);
     }
     // the host arrays above were sources of asynchronous copies
     (void)hipStreamSynchronize(stream);
@@ -326,12 +499,135 @@ done:
     return rc;
 }
 
+constexpr uint32_t TAPE_MAGIC = 0x6d637470u;
+
+uint64_t camera_hash(int n_cams, const mc_camera* cams) {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(cams);
+    for (size_t i = 0; i < sizeof(mc_camera) * (size_t)n_cams; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+// Gradient of a large grid from the rays a render kept: the record weights
+// are local estimates, scaled by the pixel weights in the binning passes;
+// the slices are binned and deposited in passes whose tile crossings fit
+// the bin space (crossings per ray estimated from the passes so far).
+template <typename Real>
+int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit, int n_cu, double* t_tape,
+                  hipStream_t stream) {
+    int rc = MC_OK;
+    hipEvent_t b0 = nullptr, b1 = nullptr;
+    float ms = 0.f;
+    const int nt = A.tp.n_tiles;
+    const size_t rec = sizeof(TapeRec<Real>);
+    size_t free_b = 0, total_b = 0;
+    char* pool = nullptr;
+    uint32_t* meta = nullptr;  // tile_count[nt], bin_start[nt], tile_end[nt], slice[nt][nw]
+    DepositItem* ditems = nullptr;
+    const int max_items = nt + 4 * n_cu + 1;
+    std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
+    std::vector<uint32_t> h_wave((size_t)T->nw);
+    std::vector<DepositItem> h_items;
+    uint64_t P = 0;
+    double per_ray = 4.0;  // tile crossings per ray (first guess)
+    int w0 = 0;
+
+    CHECK_HIP(available_bytes(&free_b));
+    P = std::min<uint64_t>(free_b / 4, (uint64_t)32 << 30) / rec;
+    P = std::min<uint64_t>(P, ((uint64_t)1 << 31) - 1);
+    if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
+    if (P < 64) return MC_ERR_OUT_OF_MEMORY;
+    CHECK_HIP(hipEventCreate(&b0));
+    CHECK_HIP(hipEventCreate(&b1));
+    CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
+    CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + (size_t)nt * T->nw), stream));
+    CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
+    CHECK_HIP(hipMemcpyAsync(h_wave.data(), T->wave_count, sizeof(uint32_t) * T->nw, hipMemcpyDeviceToHost,
+                             stream));
+    A.tp.rec = reinterpret_cast<TapeRec<Real>*>(T->rec);
+    A.tp.rw = T->rw;
+    A.tp.wave_count = T->wave_count;
+    A.tp.scale_gw = 1;
+    A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool);
+    A.tp.tile_count = meta;
+    A.tp.bin_start = meta + nt;
+    A.tp.tile_end = meta + 2 * nt;
+    A.tp.slice = meta + 3 * nt;
+    CHECK_HIP(hipEventRecord(b0, stream));
+    CHECK_HIP(hipStreamSynchronize(stream));  // h_wave
+    while (w0 < T->nw) {
+        // the slices whose estimated crossings fit the bin space
+        int ns = 0;
+        double rays = 0.0;
+        while (w0 + ns < T->nw) {
+            const double r = (double)std::min(h_wave[w0 + ns], T->rw);
+            if (ns > 0 && (rays + r) * per_ray * 1.05 > (double)P) break;
+            rays += r;
+            ++ns;
+        }
+        A.tp.w0 = w0;
+        A.tp.n_slices = ns;
+        CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
+        CHECK_HIP(launch_bin<Real>(A, false, stream));
+        CHECK_HIP(hipMemcpyAsync(h_count.data(), A.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost,
+                                 stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        uint64_t crossings = 0;
+        bool too_big = false;
+        for (int i = 0; i < nt; ++i) {
+            crossings += h_count[i];
+            too_big = too_big || h_count[i] > P;
+        }
+        if (too_big) {
+            if (ns == 1) {
+                rc = MC_ERR_OUT_OF_MEMORY;
+                goto done;
+            }
+            per_ray = std::max(2.0 * per_ray, (double)crossings / std::max(rays, 1.0));
+            continue;
+        }
+        rc = deposit_groups<Real>(A, tally, h_count, P, n_cu, ditems, max_items, h_bins, h_items, stream);
+        if (rc != MC_OK) goto done;
+        if (rays > 0.0) per_ray = std::max(1.0, (double)crossings / rays);
+        w0 += ns;
+    }
+    CHECK_HIP(hipEventRecord(b1, stream));
+    CHECK_HIP(hipStreamSynchronize(stream));
+    CHECK_HIP(hipEventElapsedTime(&ms, b0, b1));
+    if (t_tape) *t_tape += ms;
+
+done:
+    for (void* p : {(void*)ditems, (void*)meta}) {
+        if (!p) continue;
+        hipError_t e = hipFreeAsync(p, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        buf_release(dev, BUF_BINS, pool, stream);
+    }
+    (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : {b0, b1})
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// Releases a tape's device memory (stream-ordered) and the tape.
+void tape_release(mc_tape* t, hipStream_t stream) {
+    if (!t) return;
+    buf_release(t->device, BUF_TAPE, t->rec, stream);
+    if (t->wave_count) (void)hipFreeAsync(t->wave_count, stream);
+    t->magic = 0;
+    delete t;
+}
+
 // One call of the transport kernel with all its preparation.
 template <typename Real>
 int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
-        mc_path* paths, hipStream_t stream) {
+        mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr) {
     int rc = MC_OK;
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -369,10 +665,15 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     bool tape_counts = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the transport launch (stats only)
     double t_transport = 0.0, t_tape = 0.0;
+    // a render that keeps its rays (only where the gradient would use tiles)
+    mc_tape* kt = nullptr;
+    bool keep_rays = false;
+    int launch_mode = mode;
+    if (keep) *keep = nullptr;
 
     CHECK_HIP(hipGetDevice(&dev));
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    CHECK_HIP(hipMallocAsync((void**)&S.base, bytes, stream));
+    CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
     counters = S.take<unsigned long long>(1 + ST_N);
     betap = S.take<Real>(n_vox + BETA_PAD);
     dcams = S.take<DevCam<Real>>(n_cams);
@@ -444,9 +745,13 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.n_vox = n_vox;
     A.msh = msh;
     A.mask_words = (int)mask_words;
-    A.grad_lds = mode == MODE_GRAD &&
-                 ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
-    if (mode == MODE_GRAD && !A.grad_lds) {
+    {
+        const bool lds_fits =
+            ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
+        A.grad_lds = mode == MODE_GRAD && lds_fits;
+        keep_rays = mode == MODE_RENDER && keep && !lds_fits && prm->n_photons > 0;
+    }
+    if ((mode == MODE_GRAD && !A.grad_lds) || keep_rays) {
         int shx, shy, shz;
         tape_tiles(grid, shx, shy, shz);
         const int tx = 1 << shx, ty = 1 << shy, tz = 1 << shz;
@@ -472,7 +777,12 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             A.tp.T.idz = (Real)(1.0 / (grid->dz * tz));
         }
     }
-    CHECK_HIP(transport_occupancy<Real>(A, A.tape ? MODE_TAPE : mode, tally, &per_cu));
+    if (keep_rays && !A.tape) keep_rays = false;  // too many tiles: the gradient replays
+    if (keep_rays) {
+        A.tape = 0;  // the render itself runs in one launch
+        launch_mode = MODE_RTAPE;
+    }
+    CHECK_HIP(transport_occupancy<Real>(A, A.tape ? MODE_TAPE : launch_mode, tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
@@ -517,7 +827,53 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         const int64_t full = (int64_t)n_cu * (per_cu > 0 ? per_cu : 1);
         grid_blocks = (int)(need_blocks < full ? need_blocks : full);
     }
-    if (A.tape && prm->n_photons > 0) {
+    if (keep_rays) {
+        // one slice of rw records per wavefront; slots are 32-bit indices
+        // (at most three eighths of the available memory; after a kept render
+        // on this device, 1.25 times its busiest wavefront's rays per photon)
+        const int nw = grid_blocks * (BLOCK / 64);
+        size_t avail = 0;
+        CHECK_HIP(available_bytes(&avail));
+        uint64_t cap = prm->tape_limit > 0 ? (uint64_t)prm->tape_limit
+                                           : (uint64_t)(avail / 8 * 3) / sizeof(TapeRec<Real>);
+        double rate = 0.0;
+        {
+            std::lock_guard<std::mutex> lock(g_mu);
+            rate = dev < MAX_DEVICES ? g_tape_rate[dev] : 0.0;
+        }
+        if (rate > 0.0 && prm->tape_limit == 0)
+            cap = std::min<uint64_t>(cap, (uint64_t)(1.25 * rate * (double)prm->n_photons) + 64 * (uint64_t)nw);
+        const uint64_t rw = std::min<uint64_t>(cap / nw, 0xffffffffull / nw);
+        kt = new mc_tape();
+        kt->magic = 0;
+        kt->device = dev;
+        kt->nw = nw;
+        kt->rw = (uint32_t)rw;
+        kt->rec_bytes = sizeof(TapeRec<Real>);
+        if (rw < 64 ||
+            buf_acquire(BUF_TAPE, sizeof(TapeRec<Real>) * rw * nw, stream, &kt->rec) != hipSuccess ||
+            lib_alloc((void**)&kt->wave_count, sizeof(uint32_t) * (nw + 1), stream) != hipSuccess) {
+            // no room for the rays: a plain render
+            (void)hipGetLastError();
+            tape_release(kt, stream);
+            kt = nullptr;
+            keep_rays = false;
+            launch_mode = mode;
+        } else {
+            A.tp.rec = reinterpret_cast<TapeRec<Real>*>(kt->rec);
+            A.tp.rw = kt->rw;
+            A.tp.wave_count = kt->wave_count;
+            A.tp.overflow = kt->wave_count + nw;
+            CHECK_HIP(launch_fill_u32(kt->wave_count, nw + 1, stream));
+        }
+    }
+    if (A.tape && prm->n_photons > 0 && src) {
+        // the rays of the render: no replay
+        std::memcpy(host_counters, src->counters, sizeof(host_counters));
+        rc = run_tape_kept<Real>(A, tally, src, prm->tape_limit, n_cu, &t_tape, stream);
+        if (rc != MC_OK) goto done;
+        tape_counts = true;
+    } else if (A.tape && prm->n_photons > 0) {
         std::memset(host_counters, 0, sizeof(host_counters));
         rc = run_tape<Real>(A, tally, prm->n_photons, prm->photon_offset, prm->tape_limit,
                             (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
@@ -547,7 +903,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             CHECK_HIP(hipEventCreate(&ev1));
             CHECK_HIP(hipEventRecord(ev0, stream));
         }
-        CHECK_HIP(launch_transport<Real>(A, mode, tally, grid_blocks, stream));
+        CHECK_HIP(launch_transport<Real>(A, launch_mode, tally, grid_blocks, stream));
         if (stats) CHECK_HIP(hipEventRecord(ev1, stream));
     }
 
@@ -557,6 +913,35 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         if (images_m2) CHECK_HIP(launch_normalize(images_m2, ncams, n_cams, n_pix, base_norm, 2, stream));
     } else if (mode == MODE_GRAD && k32) {
         CHECK_HIP(launch_kahan_reduce(grad, A.grad32, n_vox, stream));
+    }
+
+    if (keep_rays) {
+        // the tape is kept only when no slice overflowed
+        std::vector<uint32_t> h_wave((size_t)kt->nw + 1);
+        CHECK_HIP(hipMemcpyAsync(h_wave.data(), kt->wave_count, sizeof(uint32_t) * (kt->nw + 1),
+                                 hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipMemcpyAsync(kt->counters, counters, sizeof(kt->counters), hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        const bool over = h_wave[kt->nw] != 0;
+        {
+            uint32_t busiest = 0;
+            for (int w = 0; w < kt->nw; ++w) busiest = std::max(busiest, h_wave[w]);
+            const double r = (double)busiest * kt->nw / (double)prm->n_photons;
+            std::lock_guard<std::mutex> lock(g_mu);
+            if (dev < MAX_DEVICES) g_tape_rate[dev] = over ? std::max(2.0 * g_tape_rate[dev], r) : r;
+        }
+        if (over) {
+            tape_release(kt, stream);
+        } else {
+            kt->magic = TAPE_MAGIC;
+            kt->device = dev;
+            kt->grid = *grid;
+            kt->params = *prm;
+            kt->n_cams = n_cams;
+            kt->cam_hash = camera_hash(n_cams, cams);
+            *keep = kt;
+        }
+        kt = nullptr;
     }
 
     if (stats || mode == MODE_TRACE) {
@@ -586,6 +971,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     }
 
 done:
+    if (kt) tape_release(kt, stream);  // an error before the tape was handed over
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (S.base) {
@@ -663,6 +1049,80 @@ int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_cam
                            stats, 0, 0, 0, nullptr, nullptr, nullptr, s);
     return run<float>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta, stats,
                       0, 0, 0, nullptr, nullptr, nullptr, s);
+}
+
+int mc_render_tape(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                   const mc_params* params, double* images, mc_stats* stats, void* hip_stream, mc_tape** tape) {
+    if (!tape) return MC_ERR_INVALID_ARG;
+    *tape = nullptr;
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!images) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats,
+                           0, 0, 0, nullptr, nullptr, nullptr, s, tape);
+    return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0,
+                      0, 0, nullptr, nullptr, nullptr, s, tape);
+}
+
+int mc_grad_beta_tape(const mc_tape* tape, const mc_grid* grid, const void* beta, int n_cams,
+                      const mc_camera* cams, const mc_params* params, const double* dl_dimages, double* grad_beta,
+                      mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!tape || tape->magic != TAPE_MAGIC || !dl_dimages || !grad_beta) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != tape->device) return MC_ERR_INVALID_ARG;
+    // the same render: grid, cameras and every parameter that shapes the photons
+    const mc_grid& g = tape->grid;
+    const mc_params& p = tape->params;
+    if (g.nx != grid->nx || g.ny != grid->ny || g.nz != grid->nz || g.dx != grid->dx || g.dy != grid->dy ||
+        g.dz != grid->dz || tape->n_cams != n_cams || tape->cam_hash != camera_hash(n_cams, cams) ||
+        p.albedo != params->albedo || p.g != params->g || p.sun_zenith != params->sun_zenith ||
+        p.sun_azimuth != params->sun_azimuth || p.rr_weight != params->rr_weight ||
+        p.n_photons != params->n_photons || p.seed != params->seed ||
+        p.photon_offset != params->photon_offset || p.n_photons_norm != params->n_photons_norm ||
+        p.max_events != params->max_events || p.transport != params->transport)
+        return MC_ERR_INVALID_ARG;
+    if (!is_device_ptr(beta) || !is_device_ptr(dl_dimages) || !is_device_ptr(grad_beta)) return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta,
+                           stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, tape);
+    return run<float>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta, stats,
+                      0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, tape);
+}
+
+int mc_release_memory(void) {
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev >= MAX_DEVICES) return MC_ERR_HIP;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        pool = g_pool[dev];
+        for (int i = 0; i < N_BUFS; ++i) {
+            CachedBuf& b = g_buf[dev][i];
+            if (b.in_use || !b.ptr) continue;
+            if (hipFree(b.ptr) != hipSuccess) return MC_ERR_HIP;
+            b.ptr = nullptr;
+            b.bytes = 0;
+        }
+    }
+    if (!pool) return MC_OK;
+    return map_err(hipMemPoolTrimTo(pool, 0));
+}
+
+int mc_tape_free(mc_tape* tape, void* hip_stream) {
+    if (!tape) return MC_OK;
+    if (tape->magic != TAPE_MAGIC) return MC_ERR_INVALID_ARG;
+    tape_release(tape, static_cast<hipStream_t>(hip_stream));
+    return MC_OK;
 }
 
 int mc_trace_paths(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams, const mc_params* params,

@@ -9,7 +9,10 @@
 
 namespace mcrt {
 
-enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3 };
+// MODE_TAPE: gradient replay that writes rays with their gradient weight to
+// the tape; MODE_RTAPE: render (image tallies) that also writes every ray
+// with its local estimate to the tape, for a later gradient without replay.
+enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4 };
 enum { TALLY_F64 = 0, TALLY_K32 = 1 };
 enum {
     ST_PHOTONS = 0, ST_EVENTS, ST_LE, ST_VFREE, ST_VCONN,
@@ -61,6 +64,8 @@ template <typename Real>
 struct Tape {
     TapeRec<Real>* rec;       // rays: wavefront w owns slots [w rw, (w + 1) rw)
     uint32_t rw;              // ray slots per wavefront
+    int w0;                   // first wavefront slice of a binning pass (block b: slice w0 + b)
+    int scale_gw;             // records hold local estimates: weight = gw[pixel] * a
     uint32_t* wave_count;     // [wavefronts] rays written (more than rw: overflow)
     uint32_t* overflow;       // set when a wavefront ran out of slots
     TapeRec<Real>* brec;      // rays binned by tile
@@ -155,7 +160,7 @@ hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipSt
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
 template <typename Real>
-hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s);
+hipError_t launch_bin(const KArgs<Real>& a, bool scatter, hipStream_t s);
 template <typename Real>
 hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s);
 template <typename Real>

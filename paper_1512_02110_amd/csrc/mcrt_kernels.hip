@@ -569,9 +569,13 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
     vconn += J.steps;
     J.tau += ((double)J.b0 + (double)J.b1) * (double)J.lp;  // the last voxel
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
-    if (MODE == MODE_RENDER) {
+    if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
         tally_f64<TALLY>(A.img, A.img32, J.pix, C);
         if (A.img_m2) unsafeAtomicAdd(A.img_m2 + J.pix, C * C);
+        if (MODE == MODE_RTAPE) {
+            J.a = C;
+            rec = C != 0.0;
+        }
         return false;
     } else if (MODE == MODE_TAPE) {
         J.a = J.gwp * C;
@@ -629,7 +633,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
             fin = false;
             busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn, rec);
         }
-        if (MODE == MODE_TAPE) tape_write(A, J, rec, w_used, w_first);
+        if (MODE == MODE_TAPE || MODE == MODE_RTAPE) tape_write(A, J, rec, w_used, w_first);
         const uint32_t count = qtail - qhead;
         const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
         if (final_pass ? (count + nbusy == 0) : (count + nbusy < (uint32_t)WAVE)) break;
@@ -685,7 +689,8 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 // budget; the FP64 and small-grid gradient kernels keep their registers.
 template <typename Real, int MODE>
 struct RenderWaves {
-    static constexpr int value = sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE) ? 4 : 1;
+    static constexpr int value =
+        sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE || MODE == MODE_RTAPE) ? 4 : 1;
 };
 
 // Threads per block: 512 for the gradient, whose privatised copy of the
@@ -726,7 +731,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     uint32_t n_ev = 0, n_le = 0;
     uint64_t vfree = 0, vconn = 0;
     const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
-    const uint32_t w_first = MODE == MODE_TAPE ? wave_id * A.tp.rw : 0u;
+    const uint32_t w_first = MODE == MODE_TAPE || MODE == MODE_RTAPE ? wave_id * A.tp.rw : 0u;
     uint32_t w_used = 0;
 
     for (;;) {
@@ -796,7 +801,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     }
     drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, w_used, w_first);
 
-    if (MODE == MODE_TAPE && __lane_id() == 0) {
+    if ((MODE == MODE_TAPE || MODE == MODE_RTAPE) && __lane_id() == 0) {
         A.tp.wave_count[wave_id] = w_used;
         if (w_used > A.tp.rw) A.tp.overflow[0] = 1u;
     }
@@ -876,20 +881,23 @@ __device__ __forceinline__ uint32_t camera_of(const KArgs<Real>& A, const int32_
     return (uint32_t)lo;
 }
 
-// Every ray of the wavefront slices w = blockIdx.x, blockIdx.x + gridDim.x, ...
-// f(record with its camera index, start voxel, direction, length).
+// Every ray of wavefront slice w0 + blockIdx.x: f(record with its weight and
+// camera index, start voxel, direction, length).  A tape of local estimates
+// (scale_gw) takes the weight gw[pixel] * a here; rays of zero weight are
+// skipped.
 template <typename Real, typename F>
-__device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const int32_t* s_off, int n_waves, F&& f) {
+__device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const int32_t* s_off, F&& f) {
     const Tape<Real>& P = A.tp;
-    for (int w = blockIdx.x; w < n_waves; w += gridDim.x) {
-        const uint32_t n = min(P.wave_count[w], P.rw);
-        for (uint32_t j = threadIdx.x; j < n; j += BLOCK) {
-            TapeRec<Real> R = P.rec[(size_t)w * P.rw + j];
-            R.id = camera_of(A, s_off, R.id);
-            int ix, iy, iz;
-            Real vx, vy, vz, r;
-            if (tape_ray(A, R, R.id, ix, iy, iz, vx, vy, vz, r)) f(R, ix, iy, iz, vx, vy, vz, r);
-        }
+    const size_t w = (size_t)P.w0 + blockIdx.x;
+    const uint32_t n = min(P.wave_count[w], P.rw);
+    for (uint32_t j = threadIdx.x; j < n; j += BLOCK) {
+        TapeRec<Real> R = P.rec[w * P.rw + j];
+        if (P.scale_gw) R.a = (Real)((R.id < (uint32_t)A.n_pix ? A.gw[R.id] : 0.0) * (double)R.a);
+        if (R.a == (Real)0) continue;
+        R.id = camera_of(A, s_off, R.id);
+        int ix, iy, iz;
+        Real vx, vy, vz, r;
+        if (tape_ray(A, R, R.id, ix, iy, iz, vx, vy, vz, r)) f(R, ix, iy, iz, vx, vy, vz, r);
     }
 }
 
@@ -905,7 +913,7 @@ __device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const i
 // Dynamic LDS: the first pixels of the cameras (bin_cams words), then one
 // counter per tile of the pass, and for the scatter two more per tile.
 template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves, int scatter) {
+__global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int scatter) {
     extern __shared__ uint32_t s_bin[];
     const Tape<Real>& P = A.tp;
     const int lo = scatter ? P.t_lo : 0, hi = scatter ? P.t_hi : P.n_tiles;
@@ -927,7 +935,7 @@ __global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int n_waves, int s
     }
     for (int i = threadIdx.x; i < n_off; i += BLOCK) s_off[i] = A.cams[i].pix_off;
     __syncthreads();
-    for_each_block_ray(A, s_off, n_waves, [&](const TapeRec<Real>& R0, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
+    for_each_block_ray(A, s_off, [&](const TapeRec<Real>& R0, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
         TapeRec<Real> R = R0;
         if (scatter) R.ab = (Real)((double)R.a / (double)A.beta[ix + A.G.nx * iy + A.G.nxy * iz]);
         for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
@@ -1015,22 +1023,25 @@ struct alignas(16) CamCentre {
 
 // Start the deposit of binned record R: a / beta(k_e) if the ray starts in
 // the tile, then the walk of the part of the ray inside the tile (false
-// when the record is empty or that part has no length).
+// when the record is empty or that part has no length).  Straight-line code
+// with selects: the lanes that start a record do so together, and branches
+// would cost more in mask handling than the arithmetic they skip.
 template <typename Real, bool CAMS_LDS>
 __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
                                               const CamCentre<Real>* s_cam, const TapeRec<Real>& R, double* s_g,
                                               DepWalk<Real>& D, double& a) {
-    if (R.a == (Real)0) return false;
     a = (double)R.a;
     const int i0x = (int)(R.vox & 2047u), i0y = (int)((R.vox >> 11) & 2047u), i0z = (int)(R.vox >> 22);
-    if (i0x >= A.G.nx || i0y >= A.G.ny || i0z >= A.G.nz || R.id >= (uint32_t)A.n_cams) return false;
+    // (bitwise operators: no short-circuit branches)
+    bool ok = (R.a != (Real)0) & (i0x < A.G.nx) & (i0y < A.G.ny) & (i0z < A.G.nz) & (R.id < (uint32_t)A.n_cams);
+    const uint32_t c = ok ? R.id : 0u;  // keeps the camera read in bounds
     // all cameras in LDS, or all read from global memory: one kind of load
     // (a choice per lane would become a generic-address load)
     CamCentre<Real> cc;
     if (CAMS_LDS) {
-        cc = s_cam[R.id];
+        cc = s_cam[c];
     } else {
-        const DevCam<Real>& cam = A.cams[R.id];
+        const DevCam<Real>& cam = A.cams[c];
         cc.ix = cam.icx;
         cc.iy = cam.icy;
         cc.iz = cam.icz;
@@ -1046,32 +1057,32 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     const Real ir = m_rcp(r);
     const Real vx = -dx * ir, vy = -dy * ir, vz = -dz * ir;
     const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
-    if ((unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz)
+    if (ok && (unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz)
         atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), (double)R.ab);
     // clip [0, r] to the tile box; o = start in tile-local voxel units,
-    // w = km per voxel along each axis (inf: no motion).  A ray in the plane
-    // of a face belongs to the tile above it.
+    // w = km per voxel along each axis.  An axis the ray does not move along
+    // (|v| <= tiny) does not clip; the ray must then lie within the tile's
+    // slab of that axis, and a ray in the plane of a face belongs to the
+    // tile above it.
     const Real tiny = sizeof(Real) == 4 ? (Real)1e-20f : (Real)1e-200;
     const Real o[3] = {(Real)jx + R.fx, (Real)jy + R.fy, (Real)jz + R.fz};
     const Real v[3] = {vx, vy, vz};
     const Real d[3] = {A.G.dx, A.G.dy, A.G.dz};
     const Real id[3] = {A.G.idx, A.G.idy, A.G.idz};
     const int e[3] = {L.nx, L.ny, L.nz};
+    const int stride[3] = {1, L.nx, L.nxy};
+    bool mov[3];
     Real w[3];
     Real t0 = (Real)0, t1 = r;
     for (int ax = 0; ax < 3; ++ax) {
-        if (v[ax] > tiny || v[ax] < -tiny) {
-            w[ax] = d[ax] * m_rcp(v[ax]);
-            const Real ta = ((Real)0 - o[ax]) * w[ax], tb = ((Real)e[ax] - o[ax]) * w[ax];
-            t0 = fmax(t0, fmin(ta, tb));
-            t1 = fmin(t1, fmax(ta, tb));
-        } else {
-            if (!(o[ax] >= (Real)0 && o[ax] < (Real)e[ax])) return false;
-            w[ax] = (Real)INFINITY;
-        }
+        mov[ax] = (v[ax] > tiny) | (v[ax] < -tiny);
+        w[ax] = d[ax] * m_rcp(mov[ax] ? v[ax] : (Real)1);
+        const Real ta = ((Real)0 - o[ax]) * w[ax], tb = ((Real)e[ax] - o[ax]) * w[ax];
+        t0 = mov[ax] ? fmax(t0, fmin(ta, tb)) : t0;
+        t1 = mov[ax] ? fmin(t1, fmax(ta, tb)) : t1;
+        ok &= mov[ax] | ((o[ax] >= (Real)0) & (o[ax] < (Real)e[ax]));
     }
-    if (!(t1 > t0)) return false;
-    const int stride[3] = {1, L.nx, L.nxy};
+    ok &= t1 > t0;
     int ks[3];
     Real tn[3], dt[3];
     D.k = 0;
@@ -1083,19 +1094,10 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
         Real fr = p - fl;
         fr = fr < (Real)0 ? (Real)0 : (fr > (Real)1 ? (Real)1 : fr);
         D.k += (int)fl * stride[ax];
-        if (w[ax] == (Real)INFINITY) {
-            ks[ax] = 0;
-            dt[ax] = (Real)INFINITY;
-            tn[ax] = (Real)INFINITY;
-        } else if (w[ax] > (Real)0) {
-            ks[ax] = stride[ax];
-            dt[ax] = w[ax];
-            tn[ax] = ((Real)1 - fr) * w[ax];
-        } else {
-            ks[ax] = -stride[ax];
-            dt[ax] = -w[ax];
-            tn[ax] = fr * -w[ax];
-        }
+        const bool up = w[ax] > (Real)0;
+        ks[ax] = mov[ax] ? (up ? stride[ax] : -stride[ax]) : 0;
+        dt[ax] = mov[ax] ? (up ? w[ax] : -w[ax]) : (Real)INFINITY;
+        tn[ax] = mov[ax] ? (up ? (Real)1 - fr : fr) * dt[ax] : (Real)INFINITY;
     }
     D.kx = ks[0];
     D.ky = ks[1];
@@ -1108,7 +1110,7 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     D.dtz = dt[2];
     D.t = (Real)0;
     D.len = (Real)(t1 - t0);
-    return true;
+    return ok;
 }
 
 // One voxel of a deposit walk.  Every lane of the wavefront runs the
@@ -1434,6 +1436,10 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
                                   : launch_r<Real, MODE_GRAD, TALLY_K32>(a, grid, s);
     }
     if (mode == MODE_TAPE) return launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
+    if (mode == MODE_RTAPE) {
+        return tally == TALLY_F64 ? launch_r<Real, MODE_RTAPE, TALLY_F64>(a, grid, s)
+                                  : launch_r<Real, MODE_RTAPE, TALLY_K32>(a, grid, s);
+    }
     hipLaunchKernelGGL(k_trace<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -1451,6 +1457,8 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
     if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
                                                      : occ_r<Real, MODE_GRAD, TALLY_K32>(a, b);
     if (mode == MODE_TAPE) return occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
+    if (mode == MODE_RTAPE) return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64>(a, b)
+                                                      : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
 
@@ -1461,13 +1469,12 @@ hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s
 }
 
 template <typename Real>
-hipError_t launch_bin(const KArgs<Real>& a, bool scatter, int n_waves, hipStream_t s) {
-    if (n_waves <= 0) return hipSuccess;
-    const int grid = n_waves;  // one wavefront slice per block
+hipError_t launch_bin(const KArgs<Real>& a, bool scatter, hipStream_t s) {
+    const int grid = a.tp.n_slices;  // one wavefront slice per block
+    if (grid <= 0) return hipSuccess;
     const size_t tiles = scatter ? (size_t)(a.tp.t_hi - a.tp.t_lo) : (size_t)a.tp.n_tiles;
     const size_t dyn = sizeof(uint32_t) * ((size_t)std::min(a.n_cams, BIN_LDS_CAMS) + (scatter ? 3 : 1) * tiles);
-    if (grid != a.tp.n_slices) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bin<Real>, dim3(grid), dim3(BLOCK), dyn, s, a, n_waves, scatter ? 1 : 0);
+    hipLaunchKernelGGL(k_bin<Real>, dim3(grid), dim3(BLOCK), dyn, s, a, scatter ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1478,8 +1485,8 @@ hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template hipError_t launch_bin<float>(const KArgs<float>&, bool, int, hipStream_t);
-template hipError_t launch_bin<double>(const KArgs<double>&, bool, int, hipStream_t);
+template hipError_t launch_bin<float>(const KArgs<float>&, bool, hipStream_t);
+template hipError_t launch_bin<double>(const KArgs<double>&, bool, hipStream_t);
 template hipError_t launch_bin_scan<float>(const KArgs<float>&, hipStream_t);
 template hipError_t launch_bin_scan<double>(const KArgs<double>&, hipStream_t);
 

@@ -7,6 +7,8 @@ is missing or no GPU is visible the calls raise; there is no CPU fallback.
 Entry points (same names as the C ABI in include/mcrt.h):
     mc_render(scene, beta, ...)      -> images (float64 tensor on the GPU), stats
     mc_grad_beta(scene, beta, dl, ...) -> dL/dbeta (float64 tensor), stats
+    mc_render_tape(scene, beta, ...) -> images, stats, Tape (or None): a render that keeps its rays
+    mc_grad_beta(..., tape=t)        -> the gradient of that render from its rays (no replay)
     mc_trace_paths(scene, beta, first_pid, count, max_rec, ...)
     MCRender: torch.autograd.Function (forward = render, backward = surrogate gradient)
 """
@@ -83,7 +85,7 @@ PATH_DTYPE = np.dtype([("n_events", "<i4"), ("fate", "<i4"), ("exit_pos", "<f8",
                        ("exit_dir", "<f8", (3,)), ("exit_w", "<f8")])
 
 EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_error_string",
-           "mc_device_count"]
+           "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory"]
 
 
 class McError(RuntimeError):
@@ -112,7 +114,14 @@ def load_library(path: str = LIB_PATH):
         L.mc_trace_paths.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
                                      C.POINTER(McParams), C.c_uint64, C.c_uint32, C.c_uint32,
                                      vp, vp, vp, vp]
-        for f in ("mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_device_count"):
+        L.mc_render_tape.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                     C.POINTER(McParams), vp, C.POINTER(McStats), vp, C.POINTER(vp)]
+        L.mc_grad_beta_tape.argtypes = [vp, C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                        C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
+        L.mc_tape_free.argtypes = [vp, vp]
+        L.mc_release_memory.argtypes = []
+        for f in ("mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_device_count",
+                  "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -218,9 +227,62 @@ def mc_render_moments(s, beta, transport="fp32", tally="f64", stats=True, stream
     return img, m2, (_stats(st) if stats else None)
 
 
+class Tape:
+    """The rays a render kept (mc_render_tape) for mc_grad_beta(..., tape=...).
+    Holds device memory of the library until free() (or garbage collection)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("the tape has been freed")
+        return self._h
+
+    def free(self, stream=None):
+        if self._h:
+            torch = _torch()
+            h, self._h = self._h, None
+            _check("mc_tape_free", load_library().mc_tape_free(C.c_void_p(h), C.c_void_p(_stream(torch, stream))))
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mc_release_memory():
+    """Return the device memory the library keeps pooled for reuse (call when idle)."""
+    _torch().cuda.synchronize()
+    _check("mc_release_memory", load_library().mc_release_memory())
+
+
+def mc_render_tape(s, beta, transport="fp32", tally="f64", stats=True, out=None, stream=None, **kw):
+    """Forward render that keeps its connection rays for the gradient.  Returns (images,
+    stats or None, Tape or None); None when the grid does not need a tape or the rays do
+    not fit (the images are rendered either way).  Waits for the stream."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    n = n_pixels(s)
+    img = out if out is not None else torch.empty(n, dtype=torch.float64, device=beta.device)
+    st = McStats() if stats else None
+    h = C.c_void_p()
+    rc = load_library().mc_render_tape(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                       make_cameras(s.cameras),
+                                       C.byref(make_params(s, transport=transport, tally=tally, **kw)),
+                                       C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
+                                       C.c_void_p(_stream(torch, stream)), C.byref(h))
+    _check("mc_render_tape", rc)
+    return img, (_stats(st) if stats else None), (Tape(h.value) if h.value else None)
+
+
 def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True, out=None,
-                 stream=None, **kw):
-    """Surrogate gradient dL/dbeta for image gradient dl_dimages (float64 [n_pix])."""
+                 stream=None, tape=None, **kw):
+    """Surrogate gradient dL/dbeta for image gradient dl_dimages (float64 [n_pix]); with
+    `tape` (from mc_render_tape with the same scene, beta and parameters), from the
+    render's rays instead of a replay of the photons."""
     torch = _torch()
     _check_beta(torch, s, beta, transport)
     dl = dl_dimages.detach().to(device=beta.device, dtype=torch.float64).contiguous().reshape(-1)
@@ -228,12 +290,15 @@ def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True,
         raise ValueError("dl_dimages has the wrong number of pixels")
     g = out if out is not None else torch.empty(s.n_vox, dtype=torch.float64, device=beta.device)
     st = McStats() if stats else None
-    rc = load_library().mc_grad_beta(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()),
-                                     len(s.cameras), make_cameras(s.cameras),
-                                     C.byref(make_params(s, transport=transport, tally=tally, **kw)),
-                                     C.c_void_p(dl.data_ptr()), C.c_void_p(g.data_ptr()),
-                                     C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
-    _check("mc_grad_beta", rc)
+    args = (C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras), make_cameras(s.cameras),
+            C.byref(make_params(s, transport=transport, tally=tally, **kw)), C.c_void_p(dl.data_ptr()),
+            C.c_void_p(g.data_ptr()), C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
+    if tape is not None:
+        rc = load_library().mc_grad_beta_tape(C.c_void_p(tape.handle), *args)
+        _check("mc_grad_beta_tape", rc)
+    else:
+        rc = load_library().mc_grad_beta(*args)
+        _check("mc_grad_beta", rc)
     return g, (_stats(st) if stats else None)
 
 
@@ -285,7 +350,13 @@ def _autograd_fn():
             @staticmethod
             def forward(ctx, beta, scene, transport, tally, grad_seed, kw):
                 b = beta_tensor(scene, transport, beta=beta, device=beta.device)
-                img, _ = mc_render(scene, b, transport=transport, tally=tally, stats=False, **kw)
+                ctx.tape = None
+                if ctx.needs_input_grad[0] and grad_seed is None:
+                    # keep the render's rays: the backward pass then needs no replay
+                    img, _, ctx.tape = mc_render_tape(scene, b, transport=transport, tally=tally, stats=False,
+                                                      **kw)
+                else:
+                    img, _ = mc_render(scene, b, transport=transport, tally=tally, stats=False, **kw)
                 ctx.save_for_backward(b)
                 ctx.scene, ctx.transport, ctx.tally, ctx.grad_seed, ctx.kw = scene, transport, tally, grad_seed, kw
                 ctx.beta_dtype = beta.dtype
@@ -298,7 +369,10 @@ def _autograd_fn():
                 if ctx.grad_seed is not None:
                     kw["seed"] = ctx.grad_seed
                 g, _ = mc_grad_beta(ctx.scene, b, g_img, transport=ctx.transport, tally=ctx.tally,
-                                    stats=False, **kw)
+                                    stats=False, tape=ctx.tape, **kw)
+                if ctx.tape is not None:
+                    ctx.tape.free()
+                    ctx.tape = None
                 return g.to(ctx.beta_dtype), None, None, None, None, None
 
         _fn = _MCRender

@@ -200,6 +200,89 @@ def test_gradient_tape_chunks(M, oracle, tape_limit):
     assert st == st_fwd
 
 
+@pytest.mark.parametrize("transport", ["fp64", "fp32"])
+def test_kept_tape_gradient(M, oracle, transport):
+    """A render that keeps its rays: the images equal the plain render's (up to
+    the order of the FP64 tally atomics), and the gradient from the kept rays
+    equals the replayed one (FP64: up to summation order, and the oracle per
+    voxel; FP32: the records round the weight in another order), also when
+    the bin space forces several binning passes."""
+    import torch
+    s = scenes.config2(n_photons=3001)
+    print(f"case kept tape c2 {transport}", flush=True)
+    dl = torch.as_tensor(np.random.default_rng(11).normal(size=sum(c.n_pix for c in s.cameras)), device="cuda")
+    beta = M.beta_tensor(s, transport)
+    img, st, tape = M.mc_render_tape(s, beta, transport=transport)
+    assert tape is not None
+    ref_img, ref_st = M.mc_render(s, beta, transport=transport)
+    img, ref_img = img.cpu().numpy(), ref_img.cpu().numpy()
+    assert st == ref_st
+    assert np.allclose(img, ref_img, rtol=1e-12, atol=1e-15 * np.abs(ref_img).max())
+    g_rep, st_rep = M.mc_grad_beta(s, beta, dl, transport=transport)
+    g_tape, st_tape = M.mc_grad_beta(s, beta, dl, transport=transport, tape=tape)
+    g_pass, _ = M.mc_grad_beta(s, beta, dl, transport=transport, tape=tape, tape_limit=5000)
+    tape.free()
+    g_rep, g_tape, g_pass = g_rep.cpu().numpy(), g_tape.cpu().numpy(), g_pass.cpu().numpy()
+    assert st_tape == st_rep and st_tape.timing["transport_ms"] == 0.0
+    scale = np.abs(g_rep).max()
+    if transport == "fp64":
+        ref, _ = oracle.grad_beta(s, dl.cpu().numpy())
+        assert np.allclose(g_tape, ref, rtol=1e-8, atol=1e-11 * np.abs(ref).max())
+        assert np.allclose(g_tape, g_rep, rtol=1e-10, atol=1e-13 * scale)
+        assert np.allclose(g_pass, g_rep, rtol=1e-10, atol=1e-13 * scale)
+    else:
+        assert np.linalg.norm(g_tape - g_rep) <= 1e-5 * np.linalg.norm(g_rep)
+        assert np.allclose(g_pass, g_tape, rtol=1e-10, atol=1e-12 * scale)
+
+
+def test_kept_tape_checks_and_small_grids(M):
+    """A tape only answers for the render that made it; a grid small enough
+    for the in-LDS gradient keeps no tape; a tiny tape budget keeps none."""
+    import torch
+    s = scenes.config2(n_photons=500)
+    print("case kept tape checks", flush=True)
+    beta = M.beta_tensor(s, "fp32")
+    dl = torch.ones(sum(c.n_pix for c in s.cameras), dtype=torch.float64, device="cuda")
+    _, _, tape = M.mc_render_tape(s, beta)
+    assert tape is not None
+    for kw in (dict(seed=s.seed + 1), dict(n_photons=499), dict(transport="fp64")):
+        b = M.beta_tensor(s, kw.get("transport", "fp32"))
+        with pytest.raises(M.McError) as e:
+            M.mc_grad_beta(s, b, dl, tape=tape, **kw)
+        assert e.value.code == M.MC_ERR_INVALID_ARG
+    tape.free()
+    with pytest.raises(ValueError):
+        M.mc_grad_beta(s, beta, dl, tape=tape)
+    small = scenes.config3_initial(n_photons=500)
+    img, _, t_small = M.mc_render_tape(small, M.beta_tensor(small, "fp32"))
+    assert t_small is None and torch.isfinite(img).all()
+    _, _, t_tiny = M.mc_render_tape(s, beta, tape_limit=1000)
+    assert t_tiny is None
+    # the pooled memory goes back to the device; later calls allocate anew
+    M.mc_release_memory()
+    again, _ = M.mc_render(s, beta)
+    first, _ = M.mc_render(s, beta)
+    assert torch.allclose(again, first, rtol=1e-12)
+
+
+def test_autograd_function_large_grid(M):
+    """The autograd wrapper on a tiled grid keeps the render's rays and its
+    gradient equals the replayed one."""
+    import torch
+    s = scenes.config2(n_photons=4000)
+    print("case autograd c2", flush=True)
+    beta = torch.tensor(s.beta, dtype=torch.float32, device="cuda", requires_grad=True)
+    img = M.MCRender.apply(beta, s)
+    meas = img.detach() * 1.1
+    ((img - meas) ** 2).sum().backward()
+    b32 = M.beta_tensor(s, "fp32")
+    ref_img, _ = M.mc_render(s, b32)
+    assert torch.allclose(img.detach(), ref_img, rtol=1e-12)
+    g, _ = M.mc_grad_beta(s, b32, 2 * (ref_img - meas))
+    err = (beta.grad.double() - g.float().double()).norm() / g.norm()
+    assert err.item() <= 1e-5
+
+
 def test_kahan_tally_matches_f64(M):
     s = scenes.config2(n_photons=20000)
     print("case kahan vs f64 render c2", flush=True)
