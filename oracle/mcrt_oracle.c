@@ -28,6 +28,13 @@
  *    For one local estimate C_e from a collision in voxel k_e,
  *    dC_e/dbeta(m) = C_e (delta(m,k_e)/beta(k_e) - l_e(m)), the per-event
  *    form of Eqs. (Jaco1, TcofJaco1, DivTc).
+ *  - Voxelised model (Sec. 3): L_c(k) takes, per collision in voxel k, the
+ *    phase function at the angle between the incoming direction and the
+ *    direction from the collision point to the camera centre; j_c = L_c /
+ *    beta (0 where beta = 0), scaled by mu0 A_top / N like the images.  The
+ *    LOS of Eq. (taoKtoc) runs from the voxel centre to the camera centre;
+ *    the sub-pixel points of Eq. (PIc) are an n x n grid of cell centres of
+ *    the pixel; rays and LOS parts outside the domain contribute nothing.
  */
 #include "mcrt_oracle.h"
 
@@ -214,7 +221,7 @@ static int64_t vox_index(const geom* G, const int i[3])
 
 /* ------------------------------------------------------------------------ */
 
-enum { MODE_RENDER = 0, MODE_FROZEN = 1, MODE_GRAD = 2, MODE_TRACE = 3 };
+enum { MODE_RENDER = 0, MODE_FROZEN = 1, MODE_GRAD = 2, MODE_TRACE = 3, MODE_VOXEL = 4 };
 
 typedef struct {
     geom G;
@@ -236,6 +243,7 @@ typedef struct {
     double* m2;
     const double* dl;
     double* grad;
+    double* Lc;             /* voxel model: [camera][voxel] scattered power */
     orc_stats st;
     /* trace */
     orc_path* path;
@@ -367,6 +375,26 @@ static void local_estimates(ctx* c, const double X[3], const int vox[3], const d
     }
 }
 
+/* Sec. 3.2, Eq. (Lcupdate): a collision at X in voxel vox with incoming
+ * direction w and intensity I_s = weight adds albedo I_s P(angle) to
+ * L_c(vox) for every camera c, the angle between w and X -> X_c. */
+static void voxel_tally(ctx* c, const double X[3], const int vox[3], const double w[3], double weight)
+{
+    const orc_params* P = c->prm;
+    int64_t k = vox_index(&c->G, vox);
+    int64_t nv = (int64_t)c->G.n[0] * c->G.n[1] * c->G.n[2];
+    for (int ci = 0; ci < c->n_cams; ++ci) {
+        const orc_camera* cam = &c->cams[ci];
+        double V[3] = {cam->pos[0] - X[0], cam->pos[1] - X[1], cam->pos[2] - X[2]};
+        double r2 = V[0] * V[0] + V[1] * V[1] + V[2] * V[2];
+        if (r2 < 1e-12) continue;
+        double r = sqrt(r2);
+        double cosang = (w[0] * V[0] + w[1] * V[1] + w[2] * V[2]) / r;
+        c->Lc[(int64_t)ci * nv + k] += P->albedo * weight * oracle_hg_phase(P->g, cosang);
+        c->st.le_jobs++;
+    }
+}
+
 /* The photon life cycle of Sec. 2.1.2, steps (i)-(vi). */
 static int trace_photon(ctx* c, uint64_t pid)
 {
@@ -413,8 +441,12 @@ static int trace_photon(ctx* c, uint64_t pid)
             e->voxel = (int32_t)vox_index(&c->G, vox);
             e->pad_ = 0;
         }
-        /* Sec. 2.1.3: local estimate with the incoming ray and I_s */
-        local_estimates(c, X, vox, w, weight);
+        /* Sec. 2.1.3: local estimate with the incoming ray and I_s (or, for
+         * the voxelised model of Sec. 3, the scattered power per voxel) */
+        if (c->mode == MODE_VOXEL)
+            voxel_tally(c, X, vox, w, weight);
+        else
+            local_estimates(c, X, vox, w, weight);
         if (s >= P->max_events) {
             c->st.capped++;
             return ORC_FATE_CAP;
@@ -665,4 +697,235 @@ double oracle_optical_depth(const orc_grid* grid, const double* beta, const doub
     double tau = connection_tau(&c, beta, X, vox, v, t1 - t0, 0.0, 1);
     if (nvox) *nvox = (int64_t)c.st.vox_conn;
     return tau;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Voxelised forward model, Sec. 3.                                         */
+
+/* The voxels of the segment p0 + t v, 0 <= t <= tmax (v unit), that lie in
+ * the domain, with the length of the segment inside each: k[i], l[i] for
+ * i < return value (at most cap).  The segment is clipped to the domain box
+ * first (slab method); the walk starts in the voxel entered along v. */
+static int segment_voxels(const geom* G, const double p0[3], const double v[3], double tmax,
+                          int64_t* ks, double* ls, int cap)
+{
+    double L[3] = {G->n[0] * G->d[0], G->n[1] * G->d[1], G->n[2] * G->d[2]};
+    double t0 = 0.0, t1 = tmax;
+    for (int a = 0; a < 3; ++a) {
+        if (v[a] == 0.0) {
+            if (p0[a] < 0.0 || p0[a] > L[a]) return 0;
+            continue;
+        }
+        double ta = (0.0 - p0[a]) / v[a], tb = (L[a] - p0[a]) / v[a];
+        if (ta > tb) { double tmp = ta; ta = tb; tb = tmp; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    if (!(t1 > t0)) return 0;
+    double X[3];
+    int vox[3];
+    for (int a = 0; a < 3; ++a) {
+        X[a] = p0[a] + t0 * v[a];
+        double f = X[a] / G->d[a];
+        int i = (int)floor(f);
+        if (v[a] < 0.0 && f == floor(f)) i -= 1;
+        if (i < 0) i = 0;
+        if (i > G->n[a] - 1) i = G->n[a] - 1;
+        vox[a] = i;
+    }
+    walker wk;
+    walker_init(&wk, G, X, v, vox);
+    double r = t1 - t0;
+    int n = 0;
+    for (;;) {
+        int a = walker_axis(&wk);
+        int last = wk.tmax[a] >= r;
+        double tn = last ? r : wk.tmax[a];
+        if (n < cap) {
+            ks[n] = vox_index(G, wk.i);
+            ls[n] = tn - wk.t;
+            ++n;
+        }
+        if (last) break;
+        if (walker_cross(&wk, G, a) != LEFT_NONE) break;
+    }
+    return n;
+}
+
+static void geom_of(const orc_grid* grid, geom* G)
+{
+    G->n[0] = grid->nx;
+    G->n[1] = grid->ny;
+    G->n[2] = grid->nz;
+    G->d[0] = grid->dx;
+    G->d[1] = grid->dy;
+    G->d[2] = grid->dz;
+}
+
+/* Eq. (Jc) from a FMC run without local estimation: the tallies L_c(k) of
+ * Eq. (Lcupdate), scaled by mu0 A_top / N, divided by beta(k). */
+int oracle_voxel_scatter(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                         const orc_params* P, double* j, orc_stats* stats)
+{
+    int err = validate(grid, beta, n_cams, cams, P);
+    if (err) return err;
+    if (!j) return ORC_ERR_INVALID_ARG;
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    ctx c;
+    ctx_setup(&c, grid, beta, beta, n_cams, cams, P, MODE_VOXEL);
+    c.Lc = j;
+    memset(j, 0, (size_t)n_cams * (size_t)nv * sizeof(double));
+    run_photons(&c);
+    uint64_t N = P->n_photons_norm ? P->n_photons_norm : P->n_photons;
+    double base = N ? cos(P->sun_zenith) * c.L[0] * c.L[1] / (double)N : 0.0;
+    for (int ci = 0; ci < n_cams; ++ci)
+        for (int64_t k = 0; k < nv; ++k) {
+            double* x = &j[(int64_t)ci * nv + k];
+            *x = beta[k] > 0.0 ? *x * base / beta[k] : 0.0;
+        }
+    if (stats) *stats = c.st;
+    ctx_free(&c);
+    return ORC_OK;
+}
+
+static void voxel_centre(const geom* G, int64_t k, double X[3])
+{
+    int64_t nxy = (int64_t)G->n[0] * G->n[1];
+    int ix = (int)(k % G->n[0]), iy = (int)((k / G->n[0]) % G->n[1]), iz = (int)(k / nxy);
+    X[0] = (ix + 0.5) * G->d[0];
+    X[1] = (iy + 0.5) * G->d[1];
+    X[2] = (iz + 0.5) * G->d[2];
+}
+
+/* Eqs. (taoKtoc, Tck): T_c(k) = exp(-tau) along the LOS from the centre of
+ * voxel k to camera c.  T: [camera][voxel]. */
+int oracle_voxel_transmittance(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                               double* T)
+{
+    if (!grid || !beta || !cams || !T || n_cams < 1) return ORC_ERR_INVALID_ARG;
+    geom G;
+    geom_of(grid, &G);
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    for (int ci = 0; ci < n_cams; ++ci)
+        for (int64_t k = 0; k < nv; ++k) {
+            double X[3];
+            voxel_centre(&G, k, X);
+            T[(int64_t)ci * nv + k] = exp(-oracle_optical_depth(grid, beta, X, cams[ci].pos, NULL));
+        }
+    return ORC_OK;
+}
+
+/* Unit direction of sub-pixel ray (a, b) of pixel (row, col), n x n per
+ * pixel (Eq. PIc): through the image point (col + (a + 1/2)/n,
+ * row + (b + 1/2)/n), back-projected from the camera centre. */
+static void subpixel_ray(const orc_camera* cam, int row, int col, int a, int b, int n, double v[3])
+{
+    double u = col + (a + 0.5) / n, w = row + (b + 0.5) / n;
+    double q[3] = {(u - cam->cx) / cam->fx, (w - cam->cy) / cam->fy, 1.0};
+    for (int i = 0; i < 3; ++i) v[i] = cam->R[i] * q[0] + cam->R[3 + i] * q[1] + cam->R[6 + i] * q[2];
+    double len = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < 3; ++i) v[i] /= len;
+}
+
+/* Eqs. (IcPJbetaT, Icpixel): i_c(p) = 1/(N_rays V) sum_rho sum_k
+ * l_rho(k) j_c(k) beta(k) T_c(k), N_rays = n^2, no direct sunlight. */
+int oracle_voxel_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                        int n, const double* j, double* images)
+{
+    if (!grid || !beta || !cams || !j || !images || n_cams < 1 || n < 1) return ORC_ERR_INVALID_ARG;
+    geom G;
+    geom_of(grid, &G);
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    double V = grid->dx * grid->dy * grid->dz;
+    double* T = (double*)malloc((size_t)n_cams * (size_t)nv * sizeof(double));
+    oracle_voxel_transmittance(grid, beta, n_cams, cams, T);
+    int cap = grid->nx + grid->ny + grid->nz + 4;
+    int64_t* ks = (int64_t*)malloc((size_t)cap * sizeof(int64_t));
+    double* ls = (double*)malloc((size_t)cap * sizeof(double));
+    int64_t off = 0;
+    for (int ci = 0; ci < n_cams; ++ci) {
+        const orc_camera* cam = &cams[ci];
+        const double* jc = j + (int64_t)ci * nv;
+        const double* Tc = T + (int64_t)ci * nv;
+        for (int row = 0; row < cam->height; ++row)
+            for (int col = 0; col < cam->width; ++col) {
+                double acc = 0.0;
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        double v[3];
+                        subpixel_ray(cam, row, col, a, b, n, v);
+                        int m = segment_voxels(&G, cam->pos, v, INFINITY, ks, ls, cap);
+                        for (int q = 0; q < m; ++q) acc += ls[q] * jc[ks[q]] * beta[ks[q]] * Tc[ks[q]];
+                    }
+                images[off + (int64_t)row * cam->width + col] = acc / ((double)n * n * V);
+            }
+        off += (int64_t)cam->width * cam->height;
+    }
+    free(ks);
+    free(ls);
+    free(T);
+    return ORC_OK;
+}
+
+/* Gradient of L(i(beta)) for dL/di = dl with j frozen, Eqs. (Jaco1,
+ * TcofJaco1, DivTc):  with B_c = Pi_c^T dl_c,
+ * grad(m) = sum_c [ T_c(m) j_c(m) B_c(m)
+ *                   - sum_k D_c(k, m) T_c(k) beta(k) j_c(k) B_c(k) ],
+ * D_c(k, m) the length of the LOS from the centre of k to camera c in m. */
+int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                      int n, const double* j, const double* dl, double* grad)
+{
+    if (!grid || !beta || !cams || !j || !dl || !grad || n_cams < 1 || n < 1) return ORC_ERR_INVALID_ARG;
+    geom G;
+    geom_of(grid, &G);
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    double V = grid->dx * grid->dy * grid->dz;
+    double* T = (double*)malloc((size_t)n_cams * (size_t)nv * sizeof(double));
+    double* B = (double*)calloc((size_t)nv, sizeof(double));
+    oracle_voxel_transmittance(grid, beta, n_cams, cams, T);
+    int cap = grid->nx + grid->ny + grid->nz + 4;
+    int64_t* ks = (int64_t*)malloc((size_t)cap * sizeof(int64_t));
+    double* ls = (double*)malloc((size_t)cap * sizeof(double));
+    memset(grad, 0, (size_t)nv * sizeof(double));
+    int64_t off = 0;
+    for (int ci = 0; ci < n_cams; ++ci) {
+        const orc_camera* cam = &cams[ci];
+        const double* jc = j + (int64_t)ci * nv;
+        const double* Tc = T + (int64_t)ci * nv;
+        /* B_c = Pi_c^T dl_c */
+        memset(B, 0, (size_t)nv * sizeof(double));
+        for (int row = 0; row < cam->height; ++row)
+            for (int col = 0; col < cam->width; ++col) {
+                double g = dl[off + (int64_t)row * cam->width + col];
+                if (g == 0.0) continue;
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        double v[3];
+                        subpixel_ray(cam, row, col, a, b, n, v);
+                        int m = segment_voxels(&G, cam->pos, v, INFINITY, ks, ls, cap);
+                        for (int q = 0; q < m; ++q) B[ks[q]] += g * ls[q] / ((double)n * n * V);
+                    }
+            }
+        for (int64_t k = 0; k < nv; ++k) {
+            if (B[k] == 0.0 || jc[k] == 0.0) continue;
+            grad[k] += Tc[k] * jc[k] * B[k];
+            double w = Tc[k] * beta[k] * jc[k] * B[k];
+            if (w == 0.0) continue;
+            /* the LOS from the centre of k towards the camera */
+            double X[3], D[3];
+            voxel_centre(&G, k, X);
+            for (int a = 0; a < 3; ++a) D[a] = cam->pos[a] - X[a];
+            double len = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+            if (!(len > 0.0)) continue;
+            for (int a = 0; a < 3; ++a) D[a] /= len;
+            int m = segment_voxels(&G, X, D, len, ks, ls, cap);
+            for (int q = 0; q < m; ++q) grad[ks[q]] -= w * ls[q];
+        }
+        off += (int64_t)cam->width * cam->height;
+    }
+    free(ks);
+    free(ls);
+    free(B);
+    free(T);
+    return ORC_OK;
 }

@@ -127,6 +127,24 @@ double oracle_optical_depth(const orc_grid* grid, const double* beta,
                             const double p0[3], const double p1[3], int64_t* nvox);
 double oracle_pixel_solid_angle(const orc_camera* cam, int row, int col);
 
+/* Voxelised forward model (Sec. 3).  Arrays [camera][voxel] hold one value
+ * per camera and voxel (voxel index fastest).
+ * oracle_voxel_scatter: FMC without local estimation; j = j_c(k) of Eq. (Jc)
+ *   (L_c of Eq. (Lcupdate) times mu0 A_top / N, over beta; 0 where beta = 0).
+ * oracle_voxel_transmittance: T = T_c(k) of Eq. (Tck), LOS from the voxel
+ *   centre to the camera centre.
+ * oracle_voxel_render: i_c(p) of Eq. (Icpixel) with n x n sub-pixel rays.
+ * oracle_voxel_grad: dL/dbeta for image gradient dl with j frozen, Eqs.
+ *   (Jaco1, TcofJaco1, DivTc). */
+int oracle_voxel_scatter(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                         const orc_params* prm, double* j, orc_stats* stats);
+int oracle_voxel_transmittance(const orc_grid* grid, const double* beta, int n_cams,
+                               const orc_camera* cams, double* T);
+int oracle_voxel_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                        int n, const double* j, double* images);
+int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                      int n, const double* j, const double* dl, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -110,6 +110,14 @@ def lib():
         L.oracle_optical_depth.restype = C.c_double
         L.oracle_pixel_solid_angle.argtypes = [C.POINTER(Cam), C.c_int, C.c_int]
         L.oracle_pixel_solid_angle.restype = C.c_double
+        L.oracle_voxel_scatter.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.POINTER(Params),
+                                           dp, C.POINTER(Stats)]
+        L.oracle_voxel_transmittance.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), dp]
+        L.oracle_voxel_render.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.c_int, dp, dp]
+        L.oracle_voxel_grad.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.c_int, dp, dp, dp]
+        for f in ("oracle_voxel_scatter", "oracle_voxel_transmittance", "oracle_voxel_render",
+                  "oracle_voxel_grad"):
+            getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
 
@@ -268,3 +276,58 @@ def normalisation(s, n_photons=None):
         om = np.array([[pixel_solid_angle(c, r, q) for q in range(c.width)] for r in range(c.height)])
         out.append((base / om).reshape(-1))
     return np.concatenate(out)
+
+
+# Voxelised forward model (Sec. 3): arrays [camera][voxel] are returned as
+# (n_cams, n_vox) numpy arrays.
+
+def voxel_scatter(s, beta=None, **kw):
+    """j_c(k) of Eq. (Jc) from a FMC run without local estimation; (j, stats)."""
+    b = _beta(s, beta)
+    j = np.zeros(len(s.cameras) * b.size)
+    st = Stats()
+    rc = lib().oracle_voxel_scatter(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
+                                    C.byref(make_params(s, **kw)), _dptr(j), C.byref(st))
+    if rc != 0:
+        raise OracleError(f"oracle_voxel_scatter failed: {rc}")
+    return j.reshape(len(s.cameras), b.size), st.as_dict()
+
+
+def voxel_transmittance(s, beta=None):
+    b = _beta(s, beta)
+    T = np.zeros(len(s.cameras) * b.size)
+    rc = lib().oracle_voxel_transmittance(C.byref(make_grid(s)), _dptr(b), len(s.cameras),
+                                          make_cams(s.cameras), _dptr(T))
+    if rc != 0:
+        raise OracleError(f"oracle_voxel_transmittance failed: {rc}")
+    return T.reshape(len(s.cameras), b.size)
+
+
+def voxel_render(s, j, n_rays_side, beta=None):
+    """Images of Eq. (Icpixel) with n x n sub-pixel rays (flat, like render)."""
+    b = _beta(s, beta)
+    jj = np.ascontiguousarray(j, dtype=np.float64).reshape(-1)
+    if jj.size != len(s.cameras) * b.size:
+        raise ValueError("j must hold one value per camera and voxel")
+    img = np.zeros(_n_pix(s.cameras))
+    rc = lib().oracle_voxel_render(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
+                                   int(n_rays_side), _dptr(jj), _dptr(img))
+    if rc != 0:
+        raise OracleError(f"oracle_voxel_render failed: {rc}")
+    return img
+
+
+def voxel_grad(s, j, dl_dimages, n_rays_side, beta=None):
+    """dL/dbeta of the voxelised images for dL/di = dl_dimages, j frozen."""
+    b = _beta(s, beta)
+    jj = np.ascontiguousarray(j, dtype=np.float64).reshape(-1)
+    dl = np.ascontiguousarray(dl_dimages, dtype=np.float64).reshape(-1)
+    if jj.size != len(s.cameras) * b.size or dl.size != _n_pix(s.cameras):
+        raise ValueError("size mismatch")
+    g = np.zeros(b.size)
+    rc = lib().oracle_voxel_grad(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
+                                 int(n_rays_side), _dptr(jj), _dptr(dl), _dptr(g))
+    if rc != 0:
+        raise OracleError(f"oracle_voxel_grad failed: {rc}")
+    return g
+
