@@ -213,6 +213,41 @@ int mc_tape_free(mc_tape* tape, void* hip_stream);
  * library used are idle. */
 int mc_release_memory(void);
 
+/* Voxelised forward model (Sec. 3) and its frozen-j gradient (Sec. 5.2).
+ * Arrays "[camera][voxel]" are device arrays of n_cams * nx*ny*nz doubles,
+ * camera-major, voxel index fastest.
+ *
+ * mc_voxel_scatter: forward Monte Carlo without local estimation (the same
+ *   photons as mc_render for the same params); every collision in voxel k
+ *   adds albedo I_s P(angle) to L_c(k) of every camera c, the angle between
+ *   the incoming direction and the direction from the collision point to
+ *   the camera centre (Eq. Lcupdate).  j is overwritten with
+ *   j_c(k) = L_c(k) mu0 A_top / (N beta(k)) (Eq. Jc; 0 where beta(k) = 0),
+ *   the in-scatter field in the units of the images.  beta is float for
+ *   MC_FP32 transport, double for MC_FP64; tally must be MC_TALLY_F64.
+ *   stats: le_jobs counts the (collision, camera) tallies.
+ * mc_voxel_render: images (same layout as mc_render's) =
+ *   i_c(p) = 1/(n^2 V) sum_rho sum_k l_rho(k) j_c(k) beta(k) T_c(k)
+ *   (Eqs. IcP, PIc, Icpixel), n = rays_per_side: the rays from the camera
+ *   centre through the n x n cell centres of the pixel; T_c(k) =
+ *   exp(-tau) along the line of sight from the centre of voxel k to the
+ *   camera centre (Eqs. taoKtoc, Tck); parts outside the domain contribute
+ *   nothing; no direct sunlight.  beta is double.  Deterministic (FP64).
+ * mc_voxel_grad: grad_beta = d/dbeta of sum_p dl_dimages(p) i(p) with j
+ *   frozen (Eqs. Jaco1, TcofJaco1, DivTc):
+ *   sum_c [T_c j_c B_c - D_c^T (T_c beta j_c B_c)], B_c = Pi_c^T dl_c.
+ * 1 <= rays_per_side <= 64.  Scratch: 8 n_cams nx ny nz bytes (render), twice
+ * that (gradient). */
+int mc_voxel_scatter(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                     const mc_params* params, double* j, mc_stats* stats, void* hip_stream);
+
+int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams,
+                    int rays_per_side, const double* j, double* images, void* hip_stream);
+
+int mc_voxel_grad(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams,
+                  int rays_per_side, const double* j, const double* dl_dimages, double* grad_beta,
+                  void* hip_stream);
+
 /* Test and diagnostics export: the first max_rec collisions of each of the
  * photons first_pid .. first_pid+count-1, for path-by-path comparison.
  * events: device array of count*max_rec mc_event (nullable if max_rec == 0);

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmcrt.so")
-SOURCES = ["mcrt_api.hip", "mcrt_kernels.hip"]
+SOURCES = ["mcrt_api.hip", "mcrt_kernels.hip", "mcrt_voxel.hip"]
 MICRO_LIB = os.path.join(PKG, "libmcrt_micro.so")
 MICRO_SOURCES = ["mcrt_micro.hip"]
 ARCH = os.environ.get("MCRT_OFFLOAD_ARCH", "gfx950")

@@ -52,8 +52,8 @@ int map_err(hipError_t e) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* cams, const mc_params* p) {
-    if (!g || !beta || !cams || !p) return MC_ERR_INVALID_ARG;
+int validate_scene(const mc_grid* g, const void* beta, int n_cams, const mc_camera* cams) {
+    if (!g || !beta || !cams) return MC_ERR_INVALID_ARG;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MC_ERR_INVALID_ARG;
     if ((int64_t)g->nx * g->ny * g->nz >= (int64_t)1 << 31) return MC_ERR_INVALID_ARG;
     // the local-estimate queue packs a voxel as 11 + 11 + 10 bits
@@ -72,6 +72,13 @@ int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* ca
         npix += (int64_t)c.width * c.height;
         if (npix >= (int64_t)1 << 31) return MC_ERR_INVALID_ARG;
     }
+    return MC_OK;
+}
+
+int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* cams, const mc_params* p) {
+    int rc = validate_scene(g, beta, n_cams, cams);
+    if (rc != MC_OK) return rc;
+    if (!p) return MC_ERR_INVALID_ARG;
     if (!(p->albedo >= 0.0 && p->albedo <= 1.0)) return MC_ERR_INVALID_ARG;
     if (!(p->g > -1.0 && p->g < 1.0)) return MC_ERR_INVALID_ARG;
     if (!(p->sun_zenith >= 0.0 && p->sun_zenith < 0.5 * PI)) return MC_ERR_INVALID_ARG;
@@ -632,7 +639,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
     const int tally = prm->tally == MC_TALLY_KAHAN32 ? TALLY_K32 : TALLY_F64;
-    const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE;
+    const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE && mode != MODE_VOXEL;
 
     // occupancy mask: one bit per run of 2^msh consecutive voxels, the
     // shortest runs whose bits fit the kernels' LDS copy
@@ -801,6 +808,10 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         } else {
             CHECK_HIP(launch_fill_f64(images, n_pix, stream));
         }
+    } else if (mode == MODE_VOXEL) {
+        // images carries j: the tallies L_c(k), turned into j_c(k) at the end
+        A.Lc = images;
+        CHECK_HIP(launch_fill_f64(images, (int64_t)n_cams * n_vox, stream));
     } else if (mode == MODE_GRAD) {
         double* gw = S.take<double>(n_pix);
         CHECK_HIP(launch_grad_weights(gw, dl, ncams, n_cams, n_pix, base_norm, stream));
@@ -907,6 +918,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         if (stats) CHECK_HIP(hipEventRecord(ev1, stream));
     }
 
+    if (mode == MODE_VOXEL)
+        CHECK_HIP(launch_voxel_finish<Real>(images, betap, n_cams, n_vox, base_norm, stream));
     if (mode == MODE_RENDER) {
         if (k32) CHECK_HIP(launch_kahan_reduce(images, A.img32, n_pix, stream));
         CHECK_HIP(launch_normalize(images, ncams, n_cams, n_pix, base_norm, 1, stream));
@@ -974,6 +987,80 @@ done:
     if (kt) tape_release(kt, stream);  // an error before the tape was handed over
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (S.base) {
+        hipError_t e = hipFreeAsync(S.base, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    return rc;
+}
+
+// Voxelised model, deterministic part: transmittances, then the images
+// (images != nullptr) or the gradient (dl, grad).
+int run_voxel(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int n_side,
+              const double* j, double* images, const double* dl, double* grad, hipStream_t stream) {
+    int rc = MC_OK;
+    const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
+    const int64_t n_cv = (int64_t)n_cams * n_vox;
+    Scratch S;
+    VoxArgs A;
+    std::memset(&A, 0, sizeof(A));
+    size_t bytes = round256(sizeof(HostCam) * n_cams) + round256(sizeof(double) * n_cv) + 256;
+    if (grad) bytes += round256(sizeof(double) * n_cv);
+    CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
+    {
+        HostCam* dcams = S.take<HostCam>(n_cams);
+        int64_t off = 0;
+        for (int first = 0; first < n_cams; first += CAM_CHUNK) {
+            CamChunk ch;
+            std::memset(&ch, 0, sizeof(ch));
+            ch.first = first;
+            ch.n = n_cams - first < CAM_CHUNK ? n_cams - first : CAM_CHUNK;
+            for (int i = 0; i < ch.n; ++i) {
+                const mc_camera& c = cams[first + i];
+                HostCam& h = ch.c[i];
+                std::memcpy(h.pos, c.pos, sizeof(h.pos));
+                std::memcpy(h.R, c.R, sizeof(h.R));
+                h.fx = c.fx;
+                h.fy = c.fy;
+                h.cx = c.cx;
+                h.cy = c.cy;
+                h.width = c.width;
+                h.height = c.height;
+                h.pix_off = off;
+                off += (int64_t)c.width * c.height;
+            }
+            CHECK_HIP(launch_vox_cams(ch, dcams, stream));
+        }
+        A.cams = dcams;
+        A.n_pix = off;
+    }
+    A.nx = grid->nx;
+    A.ny = grid->ny;
+    A.nz = grid->nz;
+    A.dx = grid->dx;
+    A.dy = grid->dy;
+    A.dz = grid->dz;
+    A.n_vox = n_vox;
+    A.beta = beta;
+    A.n_cams = n_cams;
+    A.n_side = n_side;
+    A.T = S.take<double>(n_cv);
+    A.j = j;
+    CHECK_HIP(launch_vox_transmittance(A, stream));
+    if (images) {
+        A.images = images;
+        CHECK_HIP(launch_vox_project(A, stream));
+    }
+    if (grad) {
+        A.dl = dl;
+        A.B = S.take<double>(n_cv);
+        A.grad = grad;
+        CHECK_HIP(launch_fill_f64(A.B, n_cv, stream));
+        CHECK_HIP(launch_fill_f64(grad, n_vox, stream));
+        CHECK_HIP(launch_vox_backproject(A, stream));
+        CHECK_HIP(launch_vox_los_adjoint(A, stream));
+    }
+done:
     if (S.base) {
         hipError_t e = hipFreeAsync(S.base, stream);
         if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
@@ -1095,6 +1182,44 @@ int mc_grad_beta_tape(const mc_tape* tape, const mc_grid* grid, const void* beta
                            stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, tape);
     return run<float>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta, stats,
                       0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, tape);
+}
+
+int mc_voxel_scatter(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                     const mc_params* params, double* j, mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!j || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(j)) return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_VOXEL, grid, beta, n_cams, cams, params, j, nullptr, nullptr, nullptr, stats, 0, 0,
+                           0, nullptr, nullptr, nullptr, s);
+    return run<float>(MODE_VOXEL, grid, beta, n_cams, cams, params, j, nullptr, nullptr, nullptr, stats, 0, 0, 0,
+                      nullptr, nullptr, nullptr, s);
+}
+
+int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int rays_per_side,
+                    const double* j, double* images, void* hip_stream) {
+    int rc = validate_scene(grid, beta, n_cams, cams);
+    if (rc != MC_OK) return rc;
+    if (!j || !images || rays_per_side < 1 || rays_per_side > 64) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(j) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
+    return run_voxel(grid, beta, n_cams, cams, rays_per_side, j, images, nullptr, nullptr,
+                     static_cast<hipStream_t>(hip_stream));
+}
+
+int mc_voxel_grad(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int rays_per_side,
+                  const double* j, const double* dl_dimages, double* grad_beta, void* hip_stream) {
+    int rc = validate_scene(grid, beta, n_cams, cams);
+    if (rc != MC_OK) return rc;
+    if (!j || !dl_dimages || !grad_beta || rays_per_side < 1 || rays_per_side > 64) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(j) || !is_device_ptr(dl_dimages) || !is_device_ptr(grad_beta))
+        return MC_ERR_INVALID_ARG;
+    return run_voxel(grid, beta, n_cams, cams, rays_per_side, j, nullptr, dl_dimages, grad_beta,
+                     static_cast<hipStream_t>(hip_stream));
 }
 
 int mc_release_memory(void) {

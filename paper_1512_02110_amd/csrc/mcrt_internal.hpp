@@ -12,7 +12,9 @@ namespace mcrt {
 // MODE_TAPE: gradient replay that writes rays with their gradient weight to
 // the tape; MODE_RTAPE: render (image tallies) that also writes every ray
 // with its local estimate to the tape, for a later gradient without replay.
-enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4 };
+// MODE_VOXEL: photon transport without local estimates that tallies the
+// scattered power per voxel and camera (the voxelised model).
+enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4, MODE_VOXEL = 5 };
 enum { TALLY_F64 = 0, TALLY_K32 = 1 };
 enum {
     ST_PHOTONS = 0, ST_EVENTS, ST_LE, ST_VFREE, ST_VCONN,
@@ -101,6 +103,7 @@ struct KArgs {
     float* img32;               // [2 n_pix]: sum, compensation (K32 tally)
     const double* gw;           // dL/di * normalisation per pixel (gradient)
     double* grad;               // F64 gradient
+    double* Lc;                 // voxel model: [camera][voxel] scattered power
     float* grad32;              // [2 n_vox] (K32 gradient)
     int64_t n_pix, n_vox;
     // occupancy bitmask of beta > 0: bit c covers voxels [c 2^msh, (c+1) 2^msh)
@@ -165,6 +168,32 @@ template <typename Real>
 hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s);
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s);
+template <typename Real>
+hipError_t launch_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base, hipStream_t s);
+
+// Voxelised model, deterministic part (mcrt_voxel.hip): FP64 throughout.
+// Cameras as HostCam (double), uploaded by k_vox_cams from kernel arguments.
+struct VoxArgs {
+    int nx, ny, nz;
+    double dx, dy, dz;
+    int64_t n_vox;
+    const double* beta;
+    const HostCam* cams;
+    int n_cams;
+    int n_side;                 // sub-pixel rays per side (n_side^2 per pixel)
+    int64_t n_pix;
+    double* T;                  // [camera][voxel] transmittance to the camera
+    const double* j;            // [camera][voxel]
+    double* images;
+    const double* dl;
+    double* B;                  // [camera][voxel] back-projected image gradient
+    double* grad;
+};
+hipError_t launch_vox_cams(const CamChunk& chunk, HostCam* dev, hipStream_t s);
+hipError_t launch_vox_transmittance(const VoxArgs& a, hipStream_t s);
+hipError_t launch_vox_project(const VoxArgs& a, hipStream_t s);
+hipError_t launch_vox_backproject(const VoxArgs& a, hipStream_t s);
+hipError_t launch_vox_los_adjoint(const VoxArgs& a, hipStream_t s);
 
 
 }  // namespace mcrt

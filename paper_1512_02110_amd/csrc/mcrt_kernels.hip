@@ -388,6 +388,27 @@ __device__ __forceinline__ bool le_geometry(const KArgs<Real>& A, const DevCam<R
     return true;
 }
 
+// Sec. 3.2, Eq. (Lcupdate): the collision adds albedo I_s P(angle) to
+// L_c(voxel) of every camera, the angle between the incoming direction and
+// the direction from the collision point to the camera centre.
+template <typename Real>
+__device__ __forceinline__ void voxel_tally(const KArgs<Real>& A, const Photon<Real>& ph, uint32_t& n_tally) {
+    const int64_t k = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
+    const double aw = (double)A.albedo * (double)ph.weight;
+    for (int c = 0; c < A.n_cams; ++c) {
+        const DevCam<Real>& cam = A.cams[c];
+        // X_c - X from voxel-local parts (exact integer differences)
+        const Real dx = ((Real)(cam.icx - ph.ix) + (cam.fcx - ph.fx)) * A.G.dx;
+        const Real dy = ((Real)(cam.icy - ph.iy) + (cam.fcy - ph.fy)) * A.G.dy;
+        const Real dz = ((Real)(cam.icz - ph.iz) + (cam.fcz - ph.fz)) * A.G.dz;
+        const Real r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < (Real)1e-12) continue;
+        const Real cosang = (ph.wx * dx + ph.wy * dy + ph.wz * dz) / m_sqrt(r2);
+        unsafeAtomicAdd(A.Lc + (int64_t)c * A.n_vox + k, aw * (double)hg_phase(A.g, cosang));
+        ++n_tally;
+    }
+}
+
 // Steps (v)-(vi) after collision s: returns -1 while the photon lives, else
 // its fate (capped or ended by Russian roulette).
 template <typename Real>
@@ -690,7 +711,9 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 template <typename Real, int MODE>
 struct RenderWaves {
     static constexpr int value =
-        sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE || MODE == MODE_RTAPE) ? 4 : 1;
+        sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE || MODE == MODE_RTAPE || MODE == MODE_VOXEL)
+            ? 4
+            : 1;
 };
 
 // Threads per block: 512 for the gradient, whose privatised copy of the
@@ -762,7 +785,9 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 ++n_ev;
             }
         }
-        if (__ballot(collided)) {
+        if (MODE == MODE_VOXEL) {
+            if (collided) voxel_tally(A, ph, n_le);
+        } else if (__ballot(collided)) {
             for (int c = 0; c < A.n_cams; ++c) {
                 const DevCam<Real>& cam = A.cams[c];
                 int64_t pix = 0;
@@ -1336,6 +1361,16 @@ __global__ void k_fill_f32(float* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0f;
 }
+// Eq. (Jc): j = L * base / beta, 0 where beta = 0 (base = mu0 A_top / N).
+template <typename Real>
+__global__ void k_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base) {
+    const int64_t n = (int64_t)n_cams * n_vox;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double b = (double)beta[i % n_vox];
+        j[i] = b > 0.0 ? j[i] * base / b : 0.0;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -1440,6 +1475,7 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
         return tally == TALLY_F64 ? launch_r<Real, MODE_RTAPE, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_RTAPE, TALLY_K32>(a, grid, s);
     }
+    if (mode == MODE_VOXEL) return launch_r<Real, MODE_VOXEL, TALLY_F64>(a, grid, s);
     hipLaunchKernelGGL(k_trace<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -1459,8 +1495,20 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
     if (mode == MODE_TAPE) return occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
     if (mode == MODE_RTAPE) return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64>(a, b)
                                                       : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
+    if (mode == MODE_VOXEL) return occ_r<Real, MODE_VOXEL, TALLY_F64>(a, b);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
+
+template <typename Real>
+hipError_t launch_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base, hipStream_t s) {
+    const int64_t n = (int64_t)n_cams * n_vox;
+    const int grid = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 65536);
+    if (grid > 0) hipLaunchKernelGGL(k_voxel_finish<Real>, dim3(grid), dim3(BLOCK), 0, s, j, beta, n_cams, n_vox, base);
+    return hipGetLastError();
+}
+
+template hipError_t launch_voxel_finish<float>(double*, const float*, int, int64_t, double, hipStream_t);
+template hipError_t launch_voxel_finish<double>(double*, const double*, int, int64_t, double, hipStream_t);
 
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s) {

@@ -85,7 +85,8 @@ PATH_DTYPE = np.dtype([("n_events", "<i4"), ("fate", "<i4"), ("exit_pos", "<f8",
                        ("exit_dir", "<f8", (3,)), ("exit_w", "<f8")])
 
 EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_error_string",
-           "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory"]
+           "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
+           "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad"]
 
 
 class McError(RuntimeError):
@@ -120,8 +121,14 @@ def load_library(path: str = LIB_PATH):
                                         C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
         L.mc_tape_free.argtypes = [vp, vp]
         L.mc_release_memory.argtypes = []
+        L.mc_voxel_scatter.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                       C.POINTER(McParams), vp, C.POINTER(McStats), vp]
+        L.mc_voxel_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
+        L.mc_voxel_grad.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp,
+                                    vp]
         for f in ("mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_device_count",
-                  "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory"):
+                  "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
+                  "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -300,6 +307,60 @@ def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True,
         rc = load_library().mc_grad_beta(*args)
         _check("mc_grad_beta", rc)
     return g, (_stats(st) if stats else None)
+
+
+def mc_voxel_scatter(s, beta, transport="fp32", stats=True, out=None, stream=None, **kw):
+    """Voxelised model (Sec. 3): j_c(k) of Eq. (Jc) from photons without local
+    estimation.  Returns (j: float64 [n_cams * n_vox] on the GPU, camera-major; stats)."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    j = out if out is not None else torch.empty(len(s.cameras) * s.n_vox, dtype=torch.float64,
+                                                 device=beta.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_voxel_scatter(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                         make_cameras(s.cameras),
+                                         C.byref(make_params(s, transport=transport, **kw)),
+                                         C.c_void_p(j.data_ptr()), C.byref(st) if stats else None,
+                                         C.c_void_p(_stream(torch, stream)))
+    _check("mc_voxel_scatter", rc)
+    return j, (_stats(st) if stats else None)
+
+
+def _voxel_inputs(torch, s, beta, j):
+    if not (beta.is_cuda and beta.dtype == torch.float64 and beta.is_contiguous() and beta.numel() == s.n_vox):
+        raise ValueError(f"beta must be a contiguous float64 CUDA tensor of {s.n_vox} voxels")
+    j = j.detach().to(device=beta.device, dtype=torch.float64).contiguous().reshape(-1)
+    if j.numel() != len(s.cameras) * s.n_vox:
+        raise ValueError("j must hold one value per camera and voxel")
+    return j
+
+
+def mc_voxel_render(s, beta, j, rays_per_side=2, out=None, stream=None):
+    """Images of the voxelised model, Eq. (Icpixel), for float64 beta and j."""
+    torch = _torch()
+    j = _voxel_inputs(torch, s, beta, j)
+    img = out if out is not None else torch.empty(n_pixels(s), dtype=torch.float64, device=beta.device)
+    rc = load_library().mc_voxel_render(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                        make_cameras(s.cameras), int(rays_per_side), C.c_void_p(j.data_ptr()),
+                                        C.c_void_p(img.data_ptr()), C.c_void_p(_stream(torch, stream)))
+    _check("mc_voxel_render", rc)
+    return img
+
+
+def mc_voxel_grad(s, beta, j, dl_dimages, rays_per_side=2, out=None, stream=None):
+    """dL/dbeta of the voxelised images with j frozen (Eqs. Jaco1, TcofJaco1, DivTc)."""
+    torch = _torch()
+    j = _voxel_inputs(torch, s, beta, j)
+    dl = dl_dimages.detach().to(device=beta.device, dtype=torch.float64).contiguous().reshape(-1)
+    if dl.numel() != n_pixels(s):
+        raise ValueError("dl_dimages has the wrong number of pixels")
+    g = out if out is not None else torch.empty(s.n_vox, dtype=torch.float64, device=beta.device)
+    rc = load_library().mc_voxel_grad(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                      make_cameras(s.cameras), int(rays_per_side), C.c_void_p(j.data_ptr()),
+                                      C.c_void_p(dl.data_ptr()), C.c_void_p(g.data_ptr()),
+                                      C.c_void_p(_stream(torch, stream)))
+    _check("mc_voxel_grad", rc)
+    return g
 
 
 def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pix=True,
