@@ -126,6 +126,37 @@ def adjoint_c3(M, torch, np, stream, n_photons):
             "kahan32_vs_f64_max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(a)))}
 
 
+def voxel_model(M, torch, np, stream, s, n_side=2):
+    """The paper's voxelised forward model (Sec. 3) on the same workload: the
+    scatter pass (photons without local estimates, j_c(k) per camera and
+    voxel), the images from j (n x n rays per pixel) and the frozen-j
+    gradient; warm-up, then one timed call of each."""
+    b32, b64 = M.beta_tensor(s, "fp32"), M.beta_tensor(s, "fp64")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    M.mc_voxel_scatter(s, b32, seed=7, stats=False)
+    (j, st), t_sc = timed(lambda: M.mc_voxel_scatter(s, b32, seed=7, stats=True))
+    M.mc_voxel_render(s, b64, j, n_side)
+    img, t_r = timed(lambda: M.mc_voxel_render(s, b64, j, n_side))
+    dl = torch.ones_like(img)
+    M.mc_voxel_grad(s, b64, j, dl, n_side)
+    _, t_g = timed(lambda: M.mc_voxel_grad(s, b64, j, dl, n_side))
+    k_s = st.timing["transport_ms"] / 1e3
+    return {"workload": f"same scene, {s.n_photons:.0e} photons, FP32 transport, {n_side}x{n_side} rays per pixel",
+            "scatter_ms": round(t_sc, 3), "scatter_events_per_s": st["events"] / (t_sc / 1e3),
+            "scatter_kernel_ms": round(st.timing["transport_ms"], 3),
+            "voxel_camera_tallies": st["le_jobs"],
+            "tally_atomics_per_s": st["le_jobs"] / k_s,
+            "render_ms": round(t_r, 3), "grad_ms": round(t_g, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +170,7 @@ def main():
     ap.add_argument("--cpu-photons", type=int, default=120000, help="photons per CPU process")
     ap.add_argument("--cpu-procs", type=int, default=None)
     ap.add_argument("--c3-photons", type=int, default=100_000_000)
+    ap.add_argument("--no-voxel", action="store_true", help="skip the voxelised-model section")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -299,6 +331,8 @@ def main():
                        "events_fp32_minus_fp64": int(recs[0][1]["events"] - st64["events"])}
     if not args.no_adjoint and args.config == "c2":
         out["fwd_adjoint_c3"] = adjoint_c3(M, torch, np, stream, args.c3_photons)
+    if not args.no_voxel:
+        out["voxel_model"] = voxel_model(M, torch, np, stream, s)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
