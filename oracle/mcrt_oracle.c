@@ -871,9 +871,11 @@ int oracle_voxel_render(const orc_grid* grid, const double* beta, int n_cams, co
  * TcofJaco1, DivTc):  with B_c = Pi_c^T dl_c,
  * grad(m) = sum_c [ T_c(m) j_c(m) B_c(m)
  *                   - sum_k D_c(k, m) T_c(k) beta(k) j_c(k) B_c(k) ],
- * D_c(k, m) the length of the LOS from the centre of k to camera c in m. */
+ * D_c(k, m) the length of the LOS from the centre of k to camera c in m.
+ * With q (nullable, [camera][voxel]) camera c's term at voxel m is
+ * multiplied by q_c(m): the conditioning Q_c of Eq. (divCost1). */
 int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
-                      int n, const double* j, const double* dl, double* grad)
+                      int n, const double* j, const double* dl, const double* q, double* grad)
 {
     if (!grid || !beta || !cams || !j || !dl || !grad || n_cams < 1 || n < 1) return ORC_ERR_INVALID_ARG;
     geom G;
@@ -892,6 +894,7 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
         const orc_camera* cam = &cams[ci];
         const double* jc = j + (int64_t)ci * nv;
         const double* Tc = T + (int64_t)ci * nv;
+        const double* qc = q ? q + (int64_t)ci * nv : NULL;
         /* B_c = Pi_c^T dl_c */
         memset(B, 0, (size_t)nv * sizeof(double));
         for (int row = 0; row < cam->height; ++row)
@@ -908,7 +911,7 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
             }
         for (int64_t k = 0; k < nv; ++k) {
             if (B[k] == 0.0 || jc[k] == 0.0) continue;
-            grad[k] += Tc[k] * jc[k] * B[k];
+            grad[k] += (qc ? qc[k] : 1.0) * Tc[k] * jc[k] * B[k];
             double w = Tc[k] * beta[k] * jc[k] * B[k];
             if (w == 0.0) continue;
             /* the LOS from the centre of k towards the camera */
@@ -919,7 +922,7 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
             if (!(len > 0.0)) continue;
             for (int a = 0; a < 3; ++a) D[a] /= len;
             int m = segment_voxels(&G, X, D, len, ks, ls, cap);
-            for (int q = 0; q < m; ++q) grad[ks[q]] -= w * ls[q];
+            for (int t = 0; t < m; ++t) grad[ks[t]] -= (qc ? qc[ks[t]] : 1.0) * w * ls[t];
         }
         off += (int64_t)cam->width * cam->height;
     }
@@ -927,5 +930,191 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
     free(ls);
     free(B);
     free(T);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Recovery (Secs. 5.2, 6, 7): conditioning, regularisation, the surrogate  */
+/* gradient-descent loop and the error measures.                            */
+
+/* Sec. 6: Q_c(k, k) from the number of sub-pixel rays R_{c,p}^rho that pass
+ * through voxel k (a positive length inside it).  counts: [camera][voxel].
+ * The conditioned step divides by the count (q = 1/count, 0 where no ray
+ * passes): a voxel seen by more rays gets a proportionally smaller step. */
+int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera* cams, int n,
+                              double* counts, double* q)
+{
+    if (!grid || !cams || n_cams < 1 || n < 1) return ORC_ERR_INVALID_ARG;
+    geom G;
+    geom_of(grid, &G);
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    double* cnt = (double*)calloc((size_t)n_cams * (size_t)nv, sizeof(double));
+    int cap = grid->nx + grid->ny + grid->nz + 4;
+    int64_t* ks = (int64_t*)malloc((size_t)cap * sizeof(int64_t));
+    double* ls = (double*)malloc((size_t)cap * sizeof(double));
+    for (int ci = 0; ci < n_cams; ++ci) {
+        const orc_camera* cam = &cams[ci];
+        for (int row = 0; row < cam->height; ++row)
+            for (int col = 0; col < cam->width; ++col)
+                for (int b = 0; b < n; ++b)
+                    for (int a = 0; a < n; ++a) {
+                        double v[3];
+                        subpixel_ray(cam, row, col, a, b, n, v);
+                        int m = segment_voxels(&G, cam->pos, v, INFINITY, ks, ls, cap);
+                        for (int t = 0; t < m; ++t)
+                            if (ls[t] > 0.0) cnt[(int64_t)ci * nv + ks[t]] += 1.0;
+                    }
+    }
+    for (int64_t i = 0; i < (int64_t)n_cams * nv; ++i) {
+        if (counts) counts[i] = cnt[i];
+        if (q) q[i] = cnt[i] > 0.0 ? 1.0 / cnt[i] : 0.0;
+    }
+    free(ks);
+    free(ls);
+    free(cnt);
+    return ORC_OK;
+}
+
+/* Sec. 6: Psi(beta) = || W Lap beta ||^2 with Lap the 7-point Laplacian in
+ * voxel units (a neighbour outside the domain takes the voxel's own value,
+ * i.e. no flux through the boundary) and W diagonal, w_layer[iz] for the
+ * voxels of layer iz (NULL: 1).  Returns Psi; grad (nullable) gets
+ * 2 Lap^T W^T W Lap beta. */
+static double lap_at(const geom* G, const double* f, int ix, int iy, int iz)
+{
+    int64_t k = (int64_t)ix + (int64_t)G->n[0] * ((int64_t)iy + (int64_t)G->n[1] * iz);
+    double c = f[k], sum = -6.0 * c;
+    int i[3] = {ix, iy, iz};
+    for (int a = 0; a < 3; ++a)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int jn[3] = {i[0], i[1], i[2]};
+            jn[a] += sgn;
+            if (jn[a] < 0 || jn[a] >= G->n[a]) {
+                sum += c;
+            } else {
+                sum += f[(int64_t)jn[0] + (int64_t)G->n[0] * ((int64_t)jn[1] + (int64_t)G->n[1] * jn[2])];
+            }
+        }
+    return sum;
+}
+
+double oracle_laplacian_reg(const orc_grid* grid, const double* beta, const double* w_layer, double* grad)
+{
+    geom G;
+    geom_of(grid, &G);
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    double* r = (double*)malloc((size_t)nv * sizeof(double));  /* W^2 Lap beta */
+    double psi = 0.0;
+    for (int iz = 0; iz < G.n[2]; ++iz)
+        for (int iy = 0; iy < G.n[1]; ++iy)
+            for (int ix = 0; ix < G.n[0]; ++ix) {
+                double w = w_layer ? w_layer[iz] : 1.0;
+                double l = lap_at(&G, beta, ix, iy, iz);
+                psi += (w * l) * (w * l);
+                r[(int64_t)ix + (int64_t)G.n[0] * ((int64_t)iy + (int64_t)G.n[1] * iz)] = w * w * l;
+            }
+    if (grad) {
+        /* Lap is symmetric (each boundary term folds into the diagonal), so
+         * Lap^T r = Lap r */
+        for (int iz = 0; iz < G.n[2]; ++iz)
+            for (int iy = 0; iy < G.n[1]; ++iy)
+                for (int ix = 0; ix < G.n[0]; ++ix)
+                    grad[(int64_t)ix + (int64_t)G.n[0] * ((int64_t)iy + (int64_t)G.n[1] * iz)] =
+                        2.0 * lap_at(&G, r, ix, iy, iz);
+    }
+    free(r);
+    return psi;
+}
+
+/* Eq. (noise): measured radiance to 10-bit grey levels.  scale = 2^10 over
+ * the largest masked pixel of all cameras; out = the rounded (floor(x+1/2))
+ * value of images * scale + 0.4 * normals, clipped to [0, 1024]. */
+double oracle_camera_noise(int64_t n_pix, const double* images, const double* mask, const double* normals,
+                           double* out)
+{
+    double mx = 0.0;
+    for (int64_t p = 0; p < n_pix; ++p) {
+        double v = (mask ? mask[p] : 1.0) * images[p];
+        if (v > mx) mx = v;
+    }
+    double scale = mx > 0.0 ? 1024.0 / mx : 0.0;
+    for (int64_t p = 0; p < n_pix; ++p) {
+        double x = floor(images[p] * scale + 0.4 * normals[p] + 0.5);
+        out[p] = x < 0.0 ? 0.0 : (x > 1024.0 ? 1024.0 : x);
+    }
+    return scale;
+}
+
+/* Sec. 7: delta_mass = (|b|_1 - |t|_1) / |t|_1, eps = |b - t|_1 / |t|_1. */
+void oracle_recovery_error(int64_t n, const double* beta_hat, const double* beta_true, double out[2])
+{
+    double a = 0.0, t = 0.0, d = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        a += fabs(beta_hat[k]);
+        t += fabs(beta_true[k]);
+        d += fabs(beta_hat[k] - beta_true[k]);
+    }
+    out[0] = (a - t) / t;
+    out[1] = d / t;
+}
+
+/* Sec. 5.2, Eqs. (Cost, divCost1, minobjectiveBetaQplus1, GD): n_outer
+ * surrogate iterations.  Iteration q renders j at the current beta with the
+ * photons of seed P->seed + q (Sec. 3.2), then takes n_gd gradient steps
+ * of E(beta | j) = sum_c |M_c (i_c(beta | j) - measured_c)|^2
+ *                  + eta Psi(beta),
+ * beta <- max(beta - delta * grad, 0) (the non-negative set), grad =
+ * 2 sum_c Q_c J_c^T M_c^2 (i_c - measured_c) + eta dPsi/dbeta, Q_c the
+ * conditioning (conditioned != 0) or 1.  beta (in) is the start, (out) the
+ * result; cost[q * n_gd + d] gets E before step d of iteration q. */
+int oracle_recover(const orc_grid* grid, double* beta, int n_cams, const orc_camera* cams,
+                   const orc_params* P, int n, const double* measured, const double* mask,
+                   const double* w_layer, double eta, double delta, int n_gd, int n_outer, int conditioned,
+                   double* cost)
+{
+    int err = validate(grid, beta, n_cams, cams, P);
+    if (err) return err;
+    if (!measured || n < 1 || n_gd < 1 || n_outer < 0) return ORC_ERR_INVALID_ARG;
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    int64_t npix = 0;
+    for (int ci = 0; ci < n_cams; ++ci) npix += (int64_t)cams[ci].width * cams[ci].height;
+    double* j = (double*)malloc((size_t)n_cams * (size_t)nv * sizeof(double));
+    double* q = conditioned ? (double*)malloc((size_t)n_cams * (size_t)nv * sizeof(double)) : NULL;
+    double* img = (double*)malloc((size_t)npix * sizeof(double));
+    double* dl = (double*)malloc((size_t)npix * sizeof(double));
+    double* g = (double*)malloc((size_t)nv * sizeof(double));
+    double* gr = (double*)malloc((size_t)nv * sizeof(double));
+    if (q) oracle_voxel_conditioning(grid, n_cams, cams, n, NULL, q);
+    for (int it = 0; it < n_outer; ++it) {
+        orc_params Pq = *P;
+        Pq.seed = P->seed + (uint64_t)it;
+        oracle_voxel_scatter(grid, beta, n_cams, cams, &Pq, j, NULL);
+        for (int d = 0; d < n_gd; ++d) {
+            oracle_voxel_render(grid, beta, n_cams, cams, n, j, img);
+            double E = 0.0;
+            for (int64_t p = 0; p < npix; ++p) {
+                double m = mask ? mask[p] : 1.0;
+                double r = m * (img[p] - measured[p]);
+                E += r * r;
+                dl[p] = 2.0 * m * r;
+            }
+            oracle_voxel_grad(grid, beta, n_cams, cams, n, j, dl, q, g);
+            if (eta != 0.0) {
+                E += eta * oracle_laplacian_reg(grid, beta, w_layer, gr);
+                for (int64_t k = 0; k < nv; ++k) g[k] += eta * gr[k];
+            }
+            if (cost) cost[(int64_t)it * n_gd + d] = E;
+            for (int64_t k = 0; k < nv; ++k) {
+                double b = beta[k] - delta * g[k];
+                beta[k] = b > 0.0 ? b : 0.0;
+            }
+        }
+    }
+    free(j);
+    free(q);
+    free(img);
+    free(dl);
+    free(g);
+    free(gr);
     return ORC_OK;
 }

@@ -143,7 +143,28 @@ int oracle_voxel_transmittance(const orc_grid* grid, const double* beta, int n_c
 int oracle_voxel_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
                         int n, const double* j, double* images);
 int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
-                      int n, const double* j, const double* dl, double* grad);
+                      int n, const double* j, const double* dl, const double* q, double* grad);
+
+/* Recovery (Secs. 5.2, 6, 7).
+ * oracle_voxel_conditioning: counts[c][k] = sub-pixel rays of camera c that
+ *   cross voxel k; q = 1/counts (0 where none); either output nullable.
+ * oracle_laplacian_reg: Psi = |W Lap beta|^2 (7-point Laplacian in voxel
+ *   units, no flux through the boundary, W = w_layer[iz] or 1); grad
+ *   (nullable) = 2 Lap^T W^2 Lap beta.
+ * oracle_camera_noise: Eq. (noise) with the caller's N(0,1) draws; returns
+ *   the grey-level scale.
+ * oracle_recovery_error: out = {delta_mass, eps} of Sec. 7.
+ * oracle_recover: the surrogate gradient-descent loop (see the source). */
+int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera* cams, int n,
+                              double* counts, double* q);
+double oracle_laplacian_reg(const orc_grid* grid, const double* beta, const double* w_layer, double* grad);
+double oracle_camera_noise(int64_t n_pix, const double* images, const double* mask, const double* normals,
+                           double* out);
+void oracle_recovery_error(int64_t n, const double* beta_hat, const double* beta_true, double out[2]);
+int oracle_recover(const orc_grid* grid, double* beta, int n_cams, const orc_camera* cams,
+                   const orc_params* prm, int n, const double* measured, const double* mask,
+                   const double* w_layer, double eta, double delta, int n_gd, int n_outer, int conditioned,
+                   double* cost);
 
 #ifdef __cplusplus
 }

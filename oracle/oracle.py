@@ -114,7 +114,18 @@ def lib():
                                            dp, C.POINTER(Stats)]
         L.oracle_voxel_transmittance.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), dp]
         L.oracle_voxel_render.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.c_int, dp, dp]
-        L.oracle_voxel_grad.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.c_int, dp, dp, dp]
+        L.oracle_voxel_grad.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.c_int, dp, dp, dp, dp]
+        L.oracle_voxel_conditioning.argtypes = [C.POINTER(Grid), C.c_int, C.POINTER(Cam), C.c_int, dp, dp]
+        L.oracle_voxel_conditioning.restype = C.c_int
+        L.oracle_laplacian_reg.argtypes = [C.POINTER(Grid), dp, dp, dp]
+        L.oracle_laplacian_reg.restype = C.c_double
+        L.oracle_camera_noise.argtypes = [C.c_int64, dp, dp, dp, dp]
+        L.oracle_camera_noise.restype = C.c_double
+        L.oracle_recovery_error.argtypes = [C.c_int64, dp, dp, dp]
+        L.oracle_recovery_error.restype = None
+        L.oracle_recover.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.POINTER(Params), C.c_int,
+                                     dp, dp, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, dp]
+        L.oracle_recover.restype = C.c_int
         for f in ("oracle_voxel_scatter", "oracle_voxel_transmittance", "oracle_voxel_render",
                   "oracle_voxel_grad"):
             getattr(L, f).restype = C.c_int
@@ -317,17 +328,82 @@ def voxel_render(s, j, n_rays_side, beta=None):
     return img
 
 
-def voxel_grad(s, j, dl_dimages, n_rays_side, beta=None):
-    """dL/dbeta of the voxelised images for dL/di = dl_dimages, j frozen."""
+def voxel_grad(s, j, dl_dimages, n_rays_side, beta=None, q=None):
+    """dL/dbeta of the voxelised images for dL/di = dl_dimages, j frozen;
+    with q ([camera][voxel]) each camera's term is weighted (conditioning)."""
     b = _beta(s, beta)
     jj = np.ascontiguousarray(j, dtype=np.float64).reshape(-1)
     dl = np.ascontiguousarray(dl_dimages, dtype=np.float64).reshape(-1)
     if jj.size != len(s.cameras) * b.size or dl.size != _n_pix(s.cameras):
         raise ValueError("size mismatch")
+    qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
     g = np.zeros(b.size)
     rc = lib().oracle_voxel_grad(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
-                                 int(n_rays_side), _dptr(jj), _dptr(dl), _dptr(g))
+                                 int(n_rays_side), _dptr(jj), _dptr(dl), _dptr(qq) if qq is not None else None,
+                                 _dptr(g))
     if rc != 0:
         raise OracleError(f"oracle_voxel_grad failed: {rc}")
     return g
+
+
+# Recovery (Secs. 5.2, 6, 7).
+
+def voxel_conditioning(s, n_rays_side):
+    """(counts, q): sub-pixel rays per camera and voxel, and q = 1/counts (0 where none)."""
+    n = len(s.cameras) * s.nx * s.ny * s.nz
+    counts, q = np.zeros(n), np.zeros(n)
+    rc = lib().oracle_voxel_conditioning(C.byref(make_grid(s)), len(s.cameras), make_cams(s.cameras),
+                                         int(n_rays_side), _dptr(counts), _dptr(q))
+    if rc != 0:
+        raise OracleError(f"oracle_voxel_conditioning failed: {rc}")
+    shape = (len(s.cameras), s.nx * s.ny * s.nz)
+    return counts.reshape(shape), q.reshape(shape)
+
+
+def laplacian_reg(s, beta=None, w_layer=None):
+    """(Psi, dPsi/dbeta) of the Laplacian regulariser."""
+    b = _beta(s, beta)
+    w = None if w_layer is None else np.ascontiguousarray(w_layer, dtype=np.float64)
+    g = np.zeros(b.size)
+    psi = lib().oracle_laplacian_reg(C.byref(make_grid(s)), _dptr(b), _dptr(w) if w is not None else None,
+                                     _dptr(g))
+    return psi, g
+
+
+def camera_noise(images, normals, mask=None):
+    """Eq. (noise): (grey levels, scale)."""
+    im = np.ascontiguousarray(images, dtype=np.float64).reshape(-1)
+    nz = np.ascontiguousarray(normals, dtype=np.float64).reshape(-1)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.float64).reshape(-1)
+    out = np.zeros(im.size)
+    scale = lib().oracle_camera_noise(im.size, _dptr(im), _dptr(m) if m is not None else None, _dptr(nz),
+                                      _dptr(out))
+    return out, scale
+
+
+def recovery_error(beta_hat, beta_true):
+    """(delta_mass, eps) of Sec. 7."""
+    a = np.ascontiguousarray(beta_hat, dtype=np.float64).reshape(-1)
+    t = np.ascontiguousarray(beta_true, dtype=np.float64).reshape(-1)
+    out = np.zeros(2)
+    lib().oracle_recovery_error(a.size, _dptr(a), _dptr(t), _dptr(out))
+    return float(out[0]), float(out[1])
+
+
+def recover(s, beta0, measured, n_rays_side, delta, n_gd, n_outer, eta=0.0, w_layer=None, mask=None,
+            conditioned=True, **kw):
+    """The surrogate gradient-descent loop; returns (beta, cost[n_outer * n_gd])."""
+    b = np.array(beta0, dtype=np.float64).reshape(-1).copy()
+    meas = np.ascontiguousarray(measured, dtype=np.float64).reshape(-1)
+    m = None if mask is None else np.ascontiguousarray(mask, dtype=np.float64).reshape(-1)
+    w = None if w_layer is None else np.ascontiguousarray(w_layer, dtype=np.float64)
+    cost = np.zeros(max(1, n_outer * n_gd))
+    rc = lib().oracle_recover(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
+                              C.byref(make_params(s, **kw)), int(n_rays_side), _dptr(meas),
+                              _dptr(m) if m is not None else None, _dptr(w) if w is not None else None,
+                              float(eta), float(delta), int(n_gd), int(n_outer), int(bool(conditioned)),
+                              _dptr(cost))
+    if rc != 0:
+        raise OracleError(f"oracle_recover failed: {rc}")
+    return b, cost[:n_outer * n_gd]
 
