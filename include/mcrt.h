@@ -245,8 +245,62 @@ int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const m
                     int rays_per_side, const double* j, double* images, void* hip_stream);
 
 int mc_voxel_grad(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams,
-                  int rays_per_side, const double* j, const double* dl_dimages, double* grad_beta,
-                  void* hip_stream);
+                  int rays_per_side, const double* j, const double* dl_dimages, const double* cam_weights,
+                  double* grad_beta, void* hip_stream);
+
+/* Recovery (Secs. 5.2, 6, 7).  All arrays are device arrays of doubles.
+ * mc_voxel_conditioning: counts[c][k] = the sub-pixel rays (rays_per_side^2
+ *   per pixel) of camera c whose length in voxel k exceeds 1e-9 of the
+ *   shortest voxel edge (grazing rays are not counted); q[c][k] =
+ *   1/counts (0 where no ray passes), the diagonal of the conditioning Q_c
+ *   of Sec. 6 read as a normalisation by the number of rays (the reading
+ *   that makes a voxel seen by many rays take a smaller step).  Either
+ *   output may be NULL, not both.  Passed as cam_weights to mc_voxel_grad,
+ *   q weights every camera's term of the gradient, Eq. (divCost1).
+ * mc_regularizer: Psi = |W Lap beta|^2 (Sec. 6), Lap the 7-point Laplacian
+ *   in voxel units with no flux through the domain boundary, W the diagonal
+ *   of per-layer weights w_layer[iz] (NULL: 1).  value (nullable, one
+ *   double) is overwritten with Psi; grad_beta (nullable) gets
+ *   eta * 2 Lap^T W^T W Lap beta ADDED to it.
+ * mc_image_residual: with r = mask (images - measured) (mask NULL: 1),
+ *   dl_dimages = 2 mask r and *loss (nullable) = sum r^2: the data term of
+ *   Eq. (Cost) and its image gradient.
+ * mc_gd_step: beta = max(beta - delta grad, 0), Eq. (GD) on the
+ *   non-negative set.
+ * mc_camera_noise: Eq. (noise): scale = 2^10 / max(mask . images) over all
+ *   cameras; out = floor(images scale + 0.4 normals + 1/2) clipped to
+ *   [0, 1024]; normals are the caller's N(0,1) draws; *scale (nullable).
+ * mc_recovery_error: out (HOST, two doubles) = delta_mass, eps of Sec. 7;
+ *   waits for the stream.
+ * mc_recover: n_outer surrogate iterations on beta (in/out): iteration q
+ *   computes j with mc_voxel_scatter at the current beta and seed
+ *   params->seed + q, then n_gd steps beta = max(beta - delta grad, 0) of
+ *   E = sum |mask (i(beta | j) - measured)|^2 + eta Psi(beta), grad =
+ *   2 sum_c Q_c J_c^T mask^2 (i - measured) + eta dPsi, Q_c from
+ *   mc_voxel_conditioning when conditioned != 0 (else 1).  cost (HOST,
+ *   nullable, n_outer n_gd doubles) gets E before every step (one wait for
+ *   the stream per step).  tally must be MC_TALLY_F64. */
+int mc_voxel_conditioning(const mc_grid* grid, int n_cams, const mc_camera* cams, int rays_per_side,
+                          double* counts, double* q, void* hip_stream);
+
+int mc_regularizer(const mc_grid* grid, const double* beta, const double* w_layer, double eta,
+                   double* grad_beta, double* value, void* hip_stream);
+
+int mc_image_residual(int64_t n_pix, const double* images, const double* measured, const double* mask,
+                      double* dl_dimages, double* loss, void* hip_stream);
+
+int mc_gd_step(int64_t n, double* beta, const double* grad, double delta, void* hip_stream);
+
+int mc_camera_noise(int64_t n_pix, const double* images, const double* mask, const double* normals,
+                    double* out, double* scale, void* hip_stream);
+
+int mc_recovery_error(int64_t n, const double* beta_hat, const double* beta_true, double* out,
+                      void* hip_stream);
+
+int mc_recover(const mc_grid* grid, double* beta, int n_cams, const mc_camera* cams, const mc_params* params,
+               int rays_per_side, const double* measured, const double* mask, const double* w_layer,
+               double eta, double delta, int n_gd, int n_outer, int conditioned, double* cost,
+               void* hip_stream);
 
 /* Test and diagnostics export: the first max_rec collisions of each of the
  * photons first_pid .. first_pid+count-1, for path-by-path comparison.

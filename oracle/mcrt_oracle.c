@@ -938,7 +938,8 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
 /* gradient-descent loop and the error measures.                            */
 
 /* Sec. 6: Q_c(k, k) from the number of sub-pixel rays R_{c,p}^rho that pass
- * through voxel k (a positive length inside it).  counts: [camera][voxel].
+ * through voxel k (a length inside it above 1e-9 of the shortest voxel
+ * edge, so that rounding does not decide whether a grazing ray counts).  counts: [camera][voxel].
  * The conditioned step divides by the count (q = 1/count, 0 where no ray
  * passes): a voxel seen by more rays gets a proportionally smaller step. */
 int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera* cams, int n,
@@ -952,6 +953,8 @@ int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera
     int cap = grid->nx + grid->ny + grid->nz + 4;
     int64_t* ks = (int64_t*)malloc((size_t)cap * sizeof(int64_t));
     double* ls = (double*)malloc((size_t)cap * sizeof(double));
+    /* a ray that only grazes a voxel (an edge or corner) is not counted */
+    double eps = 1e-9 * fmin(grid->dx, fmin(grid->dy, grid->dz));
     for (int ci = 0; ci < n_cams; ++ci) {
         const orc_camera* cam = &cams[ci];
         for (int row = 0; row < cam->height; ++row)
@@ -962,7 +965,7 @@ int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera
                         subpixel_ray(cam, row, col, a, b, n, v);
                         int m = segment_voxels(&G, cam->pos, v, INFINITY, ks, ls, cap);
                         for (int t = 0; t < m; ++t)
-                            if (ls[t] > 0.0) cnt[(int64_t)ci * nv + ks[t]] += 1.0;
+                            if (ls[t] > eps) cnt[(int64_t)ci * nv + ks[t]] += 1.0;
                     }
     }
     for (int64_t i = 0; i < (int64_t)n_cams * nv; ++i) {

@@ -997,7 +997,8 @@ done:
 // Voxelised model, deterministic part: transmittances, then the images
 // (images != nullptr) or the gradient (dl, grad).
 int run_voxel(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int n_side,
-              const double* j, double* images, const double* dl, double* grad, hipStream_t stream) {
+              const double* j, double* images, const double* dl, double* grad, hipStream_t stream,
+              const double* q = nullptr, double* counts = nullptr) {
     int rc = MC_OK;
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
     const int64_t n_cv = (int64_t)n_cams * n_vox;
@@ -1046,6 +1047,13 @@ int run_voxel(const mc_grid* grid, const double* beta, int n_cams, const mc_came
     A.n_side = n_side;
     A.T = S.take<double>(n_cv);
     A.j = j;
+    A.q = q;
+    if (counts) {
+        // ray counts only (the conditioning)
+        CHECK_HIP(launch_fill_f64(counts, n_cv, stream));
+        CHECK_HIP(launch_vox_ray_counts(A, counts, stream));
+        goto done;
+    }
     CHECK_HIP(launch_vox_transmittance(A, stream));
     if (images) {
         A.images = images;
@@ -1211,15 +1219,209 @@ int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const m
 }
 
 int mc_voxel_grad(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int rays_per_side,
-                  const double* j, const double* dl_dimages, double* grad_beta, void* hip_stream) {
+                  const double* j, const double* dl_dimages, const double* cam_weights, double* grad_beta,
+                  void* hip_stream) {
     int rc = validate_scene(grid, beta, n_cams, cams);
     if (rc != MC_OK) return rc;
     if (!j || !dl_dimages || !grad_beta || rays_per_side < 1 || rays_per_side > 64) return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
     if (!is_device_ptr(beta) || !is_device_ptr(j) || !is_device_ptr(dl_dimages) || !is_device_ptr(grad_beta))
         return MC_ERR_INVALID_ARG;
+    if (cam_weights && !is_device_ptr(cam_weights)) return MC_ERR_INVALID_ARG;
     return run_voxel(grid, beta, n_cams, cams, rays_per_side, j, nullptr, dl_dimages, grad_beta,
-                     static_cast<hipStream_t>(hip_stream));
+                     static_cast<hipStream_t>(hip_stream), cam_weights);
+}
+
+int mc_voxel_conditioning(const mc_grid* grid, int n_cams, const mc_camera* cams, int rays_per_side, double* counts,
+                          double* q, void* hip_stream) {
+    double one = 1.0;
+    int rc = validate_scene(grid, &one, n_cams, cams);
+    if (rc != MC_OK) return rc;
+    if ((!counts && !q) || rays_per_side < 1 || rays_per_side > 64) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if ((counts && !is_device_ptr(counts)) || (q && !is_device_ptr(q))) return MC_ERR_INVALID_ARG;
+    const int64_t n = (int64_t)n_cams * grid->nx * grid->ny * grid->nz;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    double* c = counts ? counts : q;
+    rc = run_voxel(grid, nullptr, n_cams, cams, rays_per_side, nullptr, nullptr, nullptr, nullptr, s, nullptr, c);
+    if (rc != MC_OK) return rc;
+    if (q) {
+        if (counts) {
+            hipError_t e = hipMemcpyAsync(q, counts, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return map_err(e);
+        }
+        return map_err(launch_vox_invert(q, n, s));
+    }
+    return MC_OK;
+}
+
+int mc_regularizer(const mc_grid* grid, const double* beta, const double* w_layer, double eta, double* grad_beta,
+                   double* value, void* hip_stream) {
+    if (!grid || !beta || grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return MC_ERR_INVALID_ARG;
+    if ((int64_t)grid->nx * grid->ny * grid->nz >= (int64_t)1 << 31) return MC_ERR_INVALID_ARG;
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    if (!is_device_ptr(beta) || (w_layer && !is_device_ptr(w_layer)) || (grad_beta && !is_device_ptr(grad_beta)) ||
+        (value && !is_device_ptr(value)))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    double* r = nullptr;
+    CHECK_HIP(lib_alloc((void**)&r, sizeof(double) * n, stream));
+    if (value) CHECK_HIP(launch_fill_f64(value, 1, stream));
+    CHECK_HIP(launch_reg(grid->nx, grid->ny, grid->nz, beta, w_layer, eta, r, grad_beta, value, stream));
+done:
+    if (r) {
+        hipError_t e = hipFreeAsync(r, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    return rc;
+}
+
+int mc_image_residual(int64_t n_pix, const double* images, const double* measured, const double* mask,
+                      double* dl_dimages, double* loss, void* hip_stream) {
+    if (n_pix < 0 || !images || !measured || !dl_dimages) return MC_ERR_INVALID_ARG;
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    if (!is_device_ptr(images) || !is_device_ptr(measured) || !is_device_ptr(dl_dimages) ||
+        (mask && !is_device_ptr(mask)) || (loss && !is_device_ptr(loss)))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (loss) CHECK_HIP(launch_fill_f64(loss, 1, stream));
+    CHECK_HIP(launch_image_residual(n_pix, images, measured, mask, dl_dimages, loss, stream));
+done:
+    return rc;
+}
+
+int mc_gd_step(int64_t n, double* beta, const double* grad, double delta, void* hip_stream) {
+    if (n < 0 || !beta || !grad || !std::isfinite(delta)) return MC_ERR_INVALID_ARG;
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(grad)) return MC_ERR_INVALID_ARG;
+    return map_err(launch_gd_step(n, beta, grad, delta, static_cast<hipStream_t>(hip_stream)));
+}
+
+int mc_camera_noise(int64_t n_pix, const double* images, const double* mask, const double* normals, double* out,
+                    double* scale, void* hip_stream) {
+    if (n_pix < 0 || !images || !normals || !out) return MC_ERR_INVALID_ARG;
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    if (!is_device_ptr(images) || !is_device_ptr(normals) || !is_device_ptr(out) || (mask && !is_device_ptr(mask)) ||
+        (scale && !is_device_ptr(scale)))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    unsigned long long* mx = nullptr;
+    CHECK_HIP(lib_alloc((void**)&mx, sizeof(unsigned long long), stream));
+    CHECK_HIP(launch_fill_u64(mx, 1, stream));
+    CHECK_HIP(launch_camera_noise(n_pix, images, mask, normals, mx, out, scale, stream));
+done:
+    if (mx) {
+        hipError_t e = hipFreeAsync(mx, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    return rc;
+}
+
+int mc_recovery_error(int64_t n, const double* beta_hat, const double* beta_true, double* out, void* hip_stream) {
+    if (n < 1 || !beta_hat || !beta_true || !out) return MC_ERR_INVALID_ARG;
+    int rc = precheck_device();
+    if (rc != MC_OK) return rc;
+    if (!is_device_ptr(beta_hat) || !is_device_ptr(beta_true)) return MC_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    double* acc = nullptr;
+    double h[3] = {0.0, 0.0, 0.0};
+    CHECK_HIP(lib_alloc((void**)&acc, sizeof(double) * 3, stream));
+    CHECK_HIP(launch_fill_f64(acc, 3, stream));
+    CHECK_HIP(launch_recovery_sums(n, beta_hat, beta_true, acc, stream));
+    CHECK_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, stream));
+    CHECK_HIP(hipStreamSynchronize(stream));
+    out[0] = (h[0] - h[1]) / h[1];
+    out[1] = h[2] / h[1];
+done:
+    if (acc) {
+        hipError_t e = hipFreeAsync(acc, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    return rc;
+}
+
+int mc_recover(const mc_grid* grid, double* beta, int n_cams, const mc_camera* cams, const mc_params* params,
+               int rays_per_side, const double* measured, const double* mask, const double* w_layer, double eta,
+               double delta, int n_gd, int n_outer, int conditioned, double* cost, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!measured || params->tally != MC_TALLY_F64 || rays_per_side < 1 || rays_per_side > 64 || n_gd < 1 ||
+        n_outer < 0 || !std::isfinite(eta) || !std::isfinite(delta))
+        return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(measured) || (mask && !is_device_ptr(mask)) ||
+        (w_layer && !is_device_ptr(w_layer)))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
+    const int64_t n_cv = (int64_t)n_cams * n_vox;
+    const int64_t n_pix = pixel_count(n_cams, cams);
+    const bool fp32 = params->transport == MC_FP32;
+    // j, q: [camera][voxel]; img, dl: pixels; g, r: voxels; two scalars
+    const size_t bytes = round256(sizeof(double) * n_cv) * (conditioned ? 2 : 1) +
+                         round256(sizeof(double) * n_pix) * 2 + round256(sizeof(double) * n_vox) * 2 +
+                         round256(sizeof(float) * n_vox) + 256 + 256;
+    Scratch S;
+    double *j = nullptr, *q = nullptr, *img = nullptr, *dl = nullptr, *g = nullptr, *r = nullptr, *scal = nullptr;
+    float* bf = nullptr;
+    double h[2] = {0.0, 0.0};
+    CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
+    j = S.take<double>(n_cv);
+    if (conditioned) q = S.take<double>(n_cv);
+    img = S.take<double>(n_pix);
+    dl = S.take<double>(n_pix);
+    g = S.take<double>(n_vox);
+    r = S.take<double>(n_vox);
+    bf = S.take<float>(n_vox);
+    scal = S.take<double>(2);
+    if (q) {
+        rc = run_voxel(grid, nullptr, n_cams, cams, rays_per_side, nullptr, nullptr, nullptr, nullptr, stream,
+                       nullptr, q);
+        if (rc != MC_OK) goto done;
+        CHECK_HIP(launch_vox_invert(q, n_cv, stream));
+    }
+    for (int it = 0; it < n_outer; ++it) {
+        // j at the current beta, with the photons of seed + it
+        mc_params P = *params;
+        P.seed = params->seed + (uint64_t)it;
+        if (fp32) {
+            CHECK_HIP(launch_d2f(n_vox, beta, bf, stream));
+            rc = run<float>(MODE_VOXEL, grid, bf, n_cams, cams, &P, j, nullptr, nullptr, nullptr, nullptr, 0, 0, 0,
+                            nullptr, nullptr, nullptr, stream);
+        } else {
+            rc = run<double>(MODE_VOXEL, grid, beta, n_cams, cams, &P, j, nullptr, nullptr, nullptr, nullptr, 0, 0, 0,
+                             nullptr, nullptr, nullptr, stream);
+        }
+        if (rc != MC_OK) goto done;
+        for (int d = 0; d < n_gd; ++d) {
+            rc = run_voxel(grid, beta, n_cams, cams, rays_per_side, j, img, nullptr, nullptr, stream);
+            if (rc != MC_OK) goto done;
+            CHECK_HIP(launch_fill_f64(scal, 2, stream));
+            CHECK_HIP(launch_image_residual(n_pix, img, measured, mask, dl, scal, stream));
+            rc = run_voxel(grid, beta, n_cams, cams, rays_per_side, j, nullptr, dl, g, stream, q);
+            if (rc != MC_OK) goto done;
+            if (eta != 0.0)
+                CHECK_HIP(launch_reg(grid->nx, grid->ny, grid->nz, beta, w_layer, eta, r, g, scal + 1, stream));
+            if (cost) {
+                CHECK_HIP(hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, stream));
+                CHECK_HIP(hipStreamSynchronize(stream));
+                cost[(int64_t)it * n_gd + d] = h[0] + eta * h[1];
+            }
+            CHECK_HIP(launch_gd_step(n_vox, beta, g, delta, stream));
+        }
+    }
+done:
+    if (S.base) {
+        hipError_t e = hipFreeAsync(S.base, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    (void)hipStreamSynchronize(stream);  // h was a copy target
+    return rc;
 }
 
 int mc_release_memory(void) {

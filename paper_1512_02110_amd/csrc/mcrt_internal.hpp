@@ -187,6 +187,7 @@ struct VoxArgs {
     double* images;
     const double* dl;
     double* B;                  // [camera][voxel] back-projected image gradient
+    const double* q;            // [camera][voxel] weights of the camera terms (nullable)
     double* grad;
 };
 hipError_t launch_vox_cams(const CamChunk& chunk, HostCam* dev, hipStream_t s);
@@ -194,6 +195,17 @@ hipError_t launch_vox_transmittance(const VoxArgs& a, hipStream_t s);
 hipError_t launch_vox_project(const VoxArgs& a, hipStream_t s);
 hipError_t launch_vox_backproject(const VoxArgs& a, hipStream_t s);
 hipError_t launch_vox_los_adjoint(const VoxArgs& a, hipStream_t s);
+hipError_t launch_vox_ray_counts(const VoxArgs& a, double* counts, hipStream_t s);
+hipError_t launch_vox_invert(double* x, int64_t n, hipStream_t s);
+hipError_t launch_reg(int nx, int ny, int nz, const double* beta, const double* w_layer, double eta, double* r,
+                      double* grad, double* value, hipStream_t s);
+hipError_t launch_image_residual(int64_t n, const double* img, const double* meas, const double* mask, double* dl,
+                                 double* loss, hipStream_t s);
+hipError_t launch_gd_step(int64_t n, double* beta, const double* g, double delta, hipStream_t s);
+hipError_t launch_camera_noise(int64_t n, const double* img, const double* mask, const double* normals,
+                               unsigned long long* mx, double* out, double* scale_out, hipStream_t s);
+hipError_t launch_recovery_sums(int64_t n, const double* b, const double* t, double* acc, hipStream_t s);
+hipError_t launch_d2f(int64_t n, const double* in, float* out, hipStream_t s);
 
 
 }  // namespace mcrt

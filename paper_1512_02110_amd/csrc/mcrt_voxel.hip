@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(VOX_BLOCK) k_vox_los_adjoint(VoxArgs A) {
         const int c = (int)(i / A.n_vox);
         const int64_t k = i % A.n_vox;
         const double T = A.T[i];
-        unsafeAtomicAdd(A.grad + k, T * bj);
+        const double* qc = A.q ? A.q + (int64_t)c * A.n_vox : nullptr;
+        unsafeAtomicAdd(A.grad + k, (qc ? qc[k] : 1.0) * T * bj);
         const double w = T * A.beta[k] * bj;
         if (w == 0.0) continue;
         double x, y, z;
@@ -198,8 +199,167 @@ __global__ void __launch_bounds__(VOX_BLOCK) k_vox_los_adjoint(VoxArgs A) {
         const double len = sqrt(Dx * Dx + Dy * Dy + Dz * Dz);
         if (!(len > 0.0)) continue;
         seg_walk(A, x, y, z, Dx / len, Dy / len, Dz / len, len,
-                 [&](int64_t m, double l) { unsafeAtomicAdd(A.grad + m, -w * l); });
+                 [&](int64_t m, double l) { unsafeAtomicAdd(A.grad + m, -(qc ? qc[m] : 1.0) * w * l); });
     }
+}
+
+// Sec. 6: counts[c][k] += 1 for every sub-pixel ray of camera c whose length
+// in voxel k exceeds 1e-9 of the shortest voxel edge (a ray that only grazes
+// an edge or a corner is not counted, whatever the rounding).
+__global__ void __launch_bounds__(VOX_BLOCK) k_vox_ray_counts(VoxArgs A, double* counts) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < A.n_pix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int c = camera_of_pixel(A, p);
+        const HostCam& cam = A.cams[c];
+        const int64_t lp = p - cam.pix_off;
+        const int row = (int)(lp / cam.width), col = (int)(lp % cam.width);
+        double* Cc = counts + (int64_t)c * A.n_vox;
+        const double eps = 1e-9 * fmin(A.dx, fmin(A.dy, A.dz));
+        for (int b = 0; b < A.n_side; ++b)
+            for (int a = 0; a < A.n_side; ++a) {
+                double vx, vy, vz;
+                subpixel_dir(cam, row, col, a, b, A.n_side, vx, vy, vz);
+                seg_walk(A, cam.pos[0], cam.pos[1], cam.pos[2], vx, vy, vz, INFINITY, [&](int64_t k, double l) {
+                    if (l > eps) unsafeAtomicAdd(Cc + k, 1.0);
+                });
+            }
+    }
+}
+
+// q = 1 / count where a ray passes, else 0 (in place).
+__global__ void k_vox_invert(double* x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = x[i] > 0.0 ? 1.0 / x[i] : 0.0;
+}
+
+// Block sum of v into *out (one device atomic per block).
+__device__ void block_sum_add(double v, double* s_red, double* out) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_red[w];
+        unsafeAtomicAdd(out, t);
+    }
+}
+
+// 7-point Laplacian in voxel units at (ix, iy, iz); a neighbour outside the
+// domain takes the centre's value (no flux through the boundary).
+__device__ double lap_at(const double* f, int nx, int ny, int nz, int ix, int iy, int iz) {
+    const int64_t nxy = (int64_t)nx * ny;
+    const int64_t k = ix + (int64_t)nx * iy + nxy * iz;
+    const double c = f[k];
+    double s = -6.0 * c;
+    s += ix > 0 ? f[k - 1] : c;
+    s += ix < nx - 1 ? f[k + 1] : c;
+    s += iy > 0 ? f[k - nx] : c;
+    s += iy < ny - 1 ? f[k + nx] : c;
+    s += iz > 0 ? f[k - nxy] : c;
+    s += iz < nz - 1 ? f[k + nxy] : c;
+    return s;
+}
+
+// Sec. 6, Psi = |W Lap beta|^2: r = W^2 Lap beta (scratch), *value += Psi.
+__global__ void __launch_bounds__(VOX_BLOCK) k_reg_residual(int nx, int ny, int nz, const double* beta,
+                                                            const double* w_layer, double* r, double* value) {
+    __shared__ double s_red[VOX_BLOCK / 64];
+    const int64_t n = (int64_t)nx * ny * nz, nxy = (int64_t)nx * ny;
+    double acc = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(k % nx), iy = (int)((k / nx) % ny), iz = (int)(k / nxy);
+        const double w = w_layer ? w_layer[iz] : 1.0;
+        const double l = lap_at(beta, nx, ny, nz, ix, iy, iz);
+        acc += (w * l) * (w * l);
+        r[k] = w * w * l;
+    }
+    if (value) block_sum_add(acc, s_red, value);
+}
+
+// grad += eta * 2 Lap r (Lap is symmetric).
+__global__ void __launch_bounds__(VOX_BLOCK) k_reg_grad(int nx, int ny, int nz, const double* r, double eta,
+                                                        double* grad) {
+    const int64_t n = (int64_t)nx * ny * nz, nxy = (int64_t)nx * ny;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(k % nx), iy = (int)((k / nx) % ny), iz = (int)(k / nxy);
+        grad[k] += eta * 2.0 * lap_at(r, nx, ny, nz, ix, iy, iz);
+    }
+}
+
+// Eq. (Cost) data term: r = M (i - measured); dl = 2 M r; *loss += sum r^2.
+__global__ void __launch_bounds__(VOX_BLOCK) k_image_residual(int64_t n, const double* img, const double* meas,
+                                                              const double* mask, double* dl, double* loss) {
+    __shared__ double s_red[VOX_BLOCK / 64];
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const double m = mask ? mask[p] : 1.0;
+        const double r = m * (img[p] - meas[p]);
+        acc += r * r;
+        dl[p] = 2.0 * m * r;
+    }
+    if (loss) block_sum_add(acc, s_red, loss);
+}
+
+// Eq. (GD) projected on the non-negative set: beta = max(beta - delta g, 0).
+__global__ void k_gd_step(int64_t n, double* beta, const double* g, double delta) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const double b = beta[k] - delta * g[k];
+        beta[k] = b > 0.0 ? b : 0.0;
+    }
+}
+
+// Largest masked pixel (values are >= 0: the bit pattern orders like the
+// value, so an integer max does).
+__global__ void __launch_bounds__(VOX_BLOCK) k_masked_max(int64_t n, const double* img, const double* mask,
+                                                          unsigned long long* mx) {
+    unsigned long long best = 0ull;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (mask ? mask[p] : 1.0) * img[p];
+        if (v > 0.0) {
+            const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+            best = u > best ? u : best;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_down(best, o);
+        best = t > best ? t : best;
+    }
+    if ((threadIdx.x & 63) == 0 && best) atomicMax(mx, best);
+}
+
+// Eq. (noise) with the caller's N(0,1) draws.
+__global__ void k_camera_noise(int64_t n, const double* img, const double* normals,
+                               const unsigned long long* mx, double* out, double* scale_out) {
+    const double m = __longlong_as_double((long long)*mx);
+    const double scale = m > 0.0 ? 1024.0 / m : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && scale_out) *scale_out = scale;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const double x = floor(img[p] * scale + 0.4 * normals[p] + 0.5);
+        out[p] = x < 0.0 ? 0.0 : (x > 1024.0 ? 1024.0 : x);
+    }
+}
+
+// Sec. 7: sums |b|, |t|, |b - t| into acc[0..2].
+__global__ void __launch_bounds__(VOX_BLOCK) k_recovery_sums(int64_t n, const double* b, const double* t,
+                                                             double* acc) {
+    __shared__ double s_red[VOX_BLOCK / 64];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        a0 += fabs(b[k]);
+        a1 += fabs(t[k]);
+        a2 += fabs(b[k] - t[k]);
+    }
+    block_sum_add(a0, s_red, acc);
+    __syncthreads();
+    block_sum_add(a1, s_red, acc + 1);
+    __syncthreads();
+    block_sum_add(a2, s_red, acc + 2);
+}
+
+__global__ void k_d2f(int64_t n, const double* in, float* out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
 }
 
 int grid_for(int64_t n) { return (int)((n + VOX_BLOCK - 1) / VOX_BLOCK < 65536 ? (n + VOX_BLOCK - 1) / VOX_BLOCK : 65536); }
@@ -224,6 +384,53 @@ hipError_t launch_vox_project(const VoxArgs& a, hipStream_t s) {
 
 hipError_t launch_vox_backproject(const VoxArgs& a, hipStream_t s) {
     if (a.n_pix > 0) hipLaunchKernelGGL(k_vox_backproject, dim3(grid_for(a.n_pix)), dim3(VOX_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_vox_ray_counts(const VoxArgs& a, double* counts, hipStream_t s) {
+    if (a.n_pix > 0) hipLaunchKernelGGL(k_vox_ray_counts, dim3(grid_for(a.n_pix)), dim3(VOX_BLOCK), 0, s, a, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_vox_invert(double* x, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_vox_invert, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reg(int nx, int ny, int nz, const double* beta, const double* w_layer, double eta, double* r,
+                      double* grad, double* value, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_reg_residual, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, nx, ny, nz, beta, w_layer, r, value);
+    if (grad) hipLaunchKernelGGL(k_reg_grad, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, nx, ny, nz, r, eta, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_residual(int64_t n, const double* img, const double* meas, const double* mask, double* dl,
+                                 double* loss, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_image_residual, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, img, meas, mask, dl, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_gd_step(int64_t n, double* beta, const double* g, double delta, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gd_step, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, beta, g, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_camera_noise(int64_t n, const double* img, const double* mask, const double* normals,
+                               unsigned long long* mx, double* out, double* scale_out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_masked_max, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, img, mask, mx);
+    hipLaunchKernelGGL(k_camera_noise, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, img, normals, mx, out, scale_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_d2f(int64_t n, const double* in, float* out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_d2f, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_recovery_sums(int64_t n, const double* b, const double* t, double* acc, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_recovery_sums, dim3(grid_for(n)), dim3(VOX_BLOCK), 0, s, n, b, t, acc);
     return hipGetLastError();
 }
 

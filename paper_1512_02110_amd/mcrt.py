@@ -86,7 +86,8 @@ PATH_DTYPE = np.dtype([("n_events", "<i4"), ("fate", "<i4"), ("exit_pos", "<f8",
 
 EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_error_string",
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
-           "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad"]
+           "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
+           "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover"]
 
 
 class McError(RuntimeError):
@@ -125,10 +126,20 @@ def load_library(path: str = LIB_PATH):
                                        C.POINTER(McParams), vp, C.POINTER(McStats), vp]
         L.mc_voxel_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
         L.mc_voxel_grad.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp,
-                                    vp]
+                                    vp, vp]
+        L.mc_voxel_conditioning.argtypes = [C.POINTER(McGrid), C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
+        L.mc_regularizer.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, vp, vp, vp]
+        L.mc_image_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.mc_gd_step.argtypes = [C.c_int64, vp, vp, C.c_double, vp]
+        L.mc_camera_noise.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
+        L.mc_recovery_error.argtypes = [C.c_int64, vp, vp, dp, vp]
+        L.mc_recover.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.POINTER(McParams), C.c_int,
+                                 vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, dp, vp]
         for f in ("mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_device_count",
                   "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
-                  "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad"):
+                  "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning",
+                  "mc_regularizer", "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error",
+                  "mc_recover"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -347,20 +358,125 @@ def mc_voxel_render(s, beta, j, rays_per_side=2, out=None, stream=None):
     return img
 
 
-def mc_voxel_grad(s, beta, j, dl_dimages, rays_per_side=2, out=None, stream=None):
-    """dL/dbeta of the voxelised images with j frozen (Eqs. Jaco1, TcofJaco1, DivTc)."""
+def _dev64(torch, x, device, n=None, name="array"):
+    t = x.detach().to(device=device, dtype=torch.float64).contiguous().reshape(-1)
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must hold {n} values")
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def mc_voxel_grad(s, beta, j, dl_dimages, rays_per_side=2, cam_weights=None, out=None, stream=None):
+    """dL/dbeta of the voxelised images with j frozen (Eqs. Jaco1, TcofJaco1, DivTc); with
+    cam_weights ([camera][voxel], e.g. mc_voxel_conditioning's q) every camera's term is weighted."""
     torch = _torch()
     j = _voxel_inputs(torch, s, beta, j)
-    dl = dl_dimages.detach().to(device=beta.device, dtype=torch.float64).contiguous().reshape(-1)
-    if dl.numel() != n_pixels(s):
-        raise ValueError("dl_dimages has the wrong number of pixels")
+    dl = _dev64(torch, dl_dimages, beta.device, n_pixels(s), "dl_dimages")
+    q = None if cam_weights is None else _dev64(torch, cam_weights, beta.device, j.numel(), "cam_weights")
     g = out if out is not None else torch.empty(s.n_vox, dtype=torch.float64, device=beta.device)
     rc = load_library().mc_voxel_grad(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
                                       make_cameras(s.cameras), int(rays_per_side), C.c_void_p(j.data_ptr()),
-                                      C.c_void_p(dl.data_ptr()), C.c_void_p(g.data_ptr()),
+                                      C.c_void_p(dl.data_ptr()), _ptr(q), C.c_void_p(g.data_ptr()),
                                       C.c_void_p(_stream(torch, stream)))
     _check("mc_voxel_grad", rc)
     return g
+
+
+def mc_voxel_conditioning(s, rays_per_side=2, stream=None):
+    """(counts, q) [n_cams * n_vox]: sub-pixel rays per camera and voxel, and q = 1/counts."""
+    torch = _torch()
+    n = len(s.cameras) * s.n_vox
+    counts = torch.empty(n, dtype=torch.float64, device="cuda")
+    q = torch.empty(n, dtype=torch.float64, device="cuda")
+    rc = load_library().mc_voxel_conditioning(C.byref(make_grid(s)), len(s.cameras), make_cameras(s.cameras),
+                                              int(rays_per_side), _ptr(counts), _ptr(q),
+                                              C.c_void_p(_stream(torch, stream)))
+    _check("mc_voxel_conditioning", rc)
+    return counts, q
+
+
+def mc_regularizer(s, beta, w_layer=None, eta=1.0, grad=None, stream=None):
+    """(Psi as a 1-element tensor, grad with eta dPsi/dbeta added) of the Laplacian regulariser."""
+    torch = _torch()
+    b = _dev64(torch, beta, "cuda", s.n_vox, "beta")
+    w = None if w_layer is None else _dev64(torch, w_layer, "cuda", s.nz, "w_layer")
+    g = grad if grad is not None else torch.zeros(s.n_vox, dtype=torch.float64, device="cuda")
+    val = torch.empty(1, dtype=torch.float64, device="cuda")
+    rc = load_library().mc_regularizer(C.byref(make_grid(s)), _ptr(b), _ptr(w), float(eta), _ptr(g), _ptr(val),
+                                       C.c_void_p(_stream(torch, stream)))
+    _check("mc_regularizer", rc)
+    return val, g
+
+
+def mc_image_residual(images, measured, mask=None, stream=None):
+    """(dl = 2 mask^2 (images - measured), loss = |mask (images - measured)|^2)."""
+    torch = _torch()
+    i = _dev64(torch, images, "cuda")
+    m = _dev64(torch, measured, "cuda", i.numel(), "measured")
+    k = None if mask is None else _dev64(torch, mask, "cuda", i.numel(), "mask")
+    dl = torch.empty_like(i)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    rc = load_library().mc_image_residual(i.numel(), _ptr(i), _ptr(m), _ptr(k), _ptr(dl), _ptr(loss),
+                                          C.c_void_p(_stream(torch, stream)))
+    _check("mc_image_residual", rc)
+    return dl, loss
+
+
+def mc_gd_step(beta, grad, delta, stream=None):
+    """In place: beta = max(beta - delta grad, 0) (beta: contiguous float64 CUDA tensor)."""
+    torch = _torch()
+    if not (beta.is_cuda and beta.dtype == torch.float64 and beta.is_contiguous()):
+        raise ValueError("beta must be a contiguous float64 CUDA tensor")
+    g = _dev64(torch, grad, beta.device, beta.numel(), "grad")
+    _check("mc_gd_step", load_library().mc_gd_step(beta.numel(), _ptr(beta), _ptr(g), float(delta),
+                                                   C.c_void_p(_stream(torch, stream))))
+    return beta
+
+
+def mc_camera_noise(images, normals, mask=None, stream=None):
+    """Eq. (noise): (grey levels, scale as a 1-element tensor)."""
+    torch = _torch()
+    i = _dev64(torch, images, "cuda")
+    z = _dev64(torch, normals, "cuda", i.numel(), "normals")
+    k = None if mask is None else _dev64(torch, mask, "cuda", i.numel(), "mask")
+    out = torch.empty_like(i)
+    scale = torch.empty(1, dtype=torch.float64, device="cuda")
+    rc = load_library().mc_camera_noise(i.numel(), _ptr(i), _ptr(k), _ptr(z), _ptr(out), _ptr(scale),
+                                        C.c_void_p(_stream(torch, stream)))
+    _check("mc_camera_noise", rc)
+    return out, scale
+
+
+def mc_recovery_error(beta_hat, beta_true, stream=None):
+    """(delta_mass, eps) of Sec. 7."""
+    torch = _torch()
+    b = _dev64(torch, beta_hat, "cuda")
+    t = _dev64(torch, beta_true, "cuda", b.numel(), "beta_true")
+    out = (C.c_double * 2)()
+    _check("mc_recovery_error", load_library().mc_recovery_error(b.numel(), _ptr(b), _ptr(t), out,
+                                                                 C.c_void_p(_stream(torch, stream))))
+    return float(out[0]), float(out[1])
+
+
+def mc_recover(s, beta0, measured, delta, n_gd, n_outer, rays_per_side=2, eta=0.0, w_layer=None, mask=None,
+               conditioned=True, transport="fp32", stream=None, **kw):
+    """The surrogate gradient-descent loop of Sec. 5.2 on the voxelised model.
+    Returns (beta float64 tensor, cost numpy array [n_outer * n_gd])."""
+    torch = _torch()
+    b = _dev64(torch, beta0, "cuda", s.n_vox, "beta0").clone()
+    m = _dev64(torch, measured, "cuda", n_pixels(s), "measured")
+    k = None if mask is None else _dev64(torch, mask, "cuda", n_pixels(s), "mask")
+    w = None if w_layer is None else _dev64(torch, w_layer, "cuda", s.nz, "w_layer")
+    cost = (C.c_double * max(1, n_outer * n_gd))()
+    rc = load_library().mc_recover(C.byref(make_grid(s)), _ptr(b), len(s.cameras), make_cameras(s.cameras),
+                                   C.byref(make_params(s, transport=transport, **kw)), int(rays_per_side),
+                                   _ptr(m), _ptr(k), _ptr(w), float(eta), float(delta), int(n_gd), int(n_outer),
+                                   int(bool(conditioned)), cost, C.c_void_p(_stream(torch, stream)))
+    _check("mc_recover", rc)
+    return b, np.array(cost[:n_outer * n_gd])
 
 
 def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pix=True,
