@@ -1121,3 +1121,148 @@ int oracle_recover(const orc_grid* grid, double* beta, int n_cams, const orc_cam
     free(gr);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Backward Monte Carlo (Sec. 2.1.4): per pixel, photon packets back-traced  */
+/* from the camera, with the local estimate towards the sun, Eq. (ble).     */
+
+/* Optical depth from X (in voxel vox) along unit v to the domain exit, and
+ * the face it leaves through. */
+static double tau_to_exit(ctx* c, const double X[3], const int vox[3], const double v[3], int* face)
+{
+    walker wk;
+    walker_init(&wk, &c->G, X, v, vox);
+    double tau = 0.0;
+    for (;;) {
+        int a = walker_axis(&wk);
+        tau += c->beta_t[vox_index(&c->G, wk.i)] * (wk.tmax[a] - wk.t);
+        int left = walker_cross(&wk, &c->G, a);
+        if (left != LEFT_NONE) {
+            *face = left;
+            return tau;
+        }
+    }
+}
+
+/* Image of every camera by BMC with n_pp packets per pixel.  Packet i of
+ * global pixel p has photon id p * n_pp + i: leg 0 gives the point of the
+ * pixel (two uniforms) and the first free path; leg s >= 1 follows
+ * collision s as in the forward method (polar, azimuth, roulette, free
+ * path).  Steps: (i) start at the camera centre along the back-projected
+ * direction through that point, entering the domain where the ray does;
+ * (ii)-(iii) free flight, the packet ends when it leaves (a packet reaching
+ * the sun directly has zero measure for a pinhole and is not counted);
+ * at every collision the local estimate albedo I_s P(angle between the ray
+ * and the direction to the sun) t(X -> sun), with t = 0 when the path to
+ * the sun leaves through a side face (light enters through the top face
+ * only, as in the forward method); (v) albedo and roulette, (vi) HG
+ * scattering about the ray.  pixel = mean of the packets' sums: radiance
+ * per unit solar irradiance, the units of the forward images; images_m2
+ * (nullable) = mean of the squared packet sums. */
+int oracle_bmc_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                      const orc_params* P, uint32_t n_pp, double* images, double* images_m2, orc_stats* stats)
+{
+    int err = validate(grid, beta, n_cams, cams, P);
+    if (err) return err;
+    if (!images || n_pp < 1) return ORC_ERR_INVALID_ARG;
+    ctx c;
+    ctx_setup(&c, grid, beta, beta, n_cams, cams, P, MODE_RENDER);
+    double to_sun[3] = {-c.w_sun[0], -c.w_sun[1], -c.w_sun[2]};
+    int64_t gp = 0;
+    for (int ci = 0; ci < n_cams; ++ci) {
+        const orc_camera* cam = &cams[ci];
+        for (int row = 0; row < cam->height; ++row)
+            for (int col = 0; col < cam->width; ++col, ++gp) {
+                double sum = 0.0, sum2 = 0.0;
+                for (uint32_t i = 0; i < n_pp; ++i) {
+                    uint64_t pid = (uint64_t)gp * n_pp + i;
+                    double packet = 0.0;
+                    double u[4];
+                    draw(P->seed, pid, 0u, u);
+                    c.st.photons++;
+                    /* (i) the ray through the point (col + u0, row + u1) */
+                    double q[3] = {(col + u[0] - cam->cx) / cam->fx, (row + u[1] - cam->cy) / cam->fy, 1.0};
+                    double d[3];
+                    for (int a = 0; a < 3; ++a)
+                        d[a] = cam->R[a] * q[0] + cam->R[3 + a] * q[1] + cam->R[6 + a] * q[2];
+                    double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    for (int a = 0; a < 3; ++a) d[a] /= len;
+                    double t0 = 0.0, t1 = INFINITY;
+                    for (int a = 0; a < 3; ++a) {
+                        if (d[a] == 0.0) {
+                            if (cam->pos[a] < 0.0 || cam->pos[a] > c.L[a]) t1 = -1.0;
+                            continue;
+                        }
+                        double ta = (0.0 - cam->pos[a]) / d[a], tb = (c.L[a] - cam->pos[a]) / d[a];
+                        if (ta > tb) { double tmp = ta; ta = tb; tb = tmp; }
+                        if (ta > t0) t0 = ta;
+                        if (tb < t1) t1 = tb;
+                    }
+                    if (!(t1 > t0)) {
+                        c.st.esc_side++;
+                        continue;
+                    }
+                    double X[3];
+                    int vox[3];
+                    for (int a = 0; a < 3; ++a) {
+                        X[a] = cam->pos[a] + t0 * d[a];
+                        double f = X[a] / c.G.d[a];
+                        int k = (int)floor(f);
+                        if (d[a] < 0.0 && f == floor(f)) k -= 1;
+                        if (k < 0) k = 0;
+                        if (k > c.G.n[a] - 1) k = c.G.n[a] - 1;
+                        vox[a] = k;
+                    }
+                    double weight = 1.0, tau_star = -log(1.0 - u[2]);
+                    uint32_t s = 0;
+                    for (;;) {
+                        int left = free_flight(&c, X, vox, d, tau_star);
+                        if (left != LEFT_NONE) {
+                            if (left == ORC_FATE_TOP) c.st.esc_top++;
+                            else if (left == ORC_FATE_BOTTOM) c.st.esc_bottom++;
+                            else c.st.esc_side++;
+                            break;
+                        }
+                        ++s;
+                        c.st.events++;
+                        /* Eq. (ble) */
+                        int face = 0;
+                        double tau = tau_to_exit(&c, X, vox, to_sun, &face);
+                        c.st.le_jobs++;
+                        if (face == ORC_FATE_TOP) {
+                            double cosang = d[0] * to_sun[0] + d[1] * to_sun[1] + d[2] * to_sun[2];
+                            packet += P->albedo * weight * oracle_hg_phase(P->g, cosang) * exp(-tau);
+                        }
+                        if (s >= P->max_events) {
+                            c.st.capped++;
+                            break;
+                        }
+                        draw(P->seed, pid, s, u);
+                        weight *= P->albedo;
+                        if (weight < P->rr_weight) {
+                            if (u[2] < weight / P->rr_weight) {
+                                weight = P->rr_weight;
+                            } else {
+                                c.st.rr_killed++;
+                                break;
+                            }
+                        }
+                        double mu = oracle_hg_sample(P->g, u[0]);
+                        double wn[3];
+                        oracle_scatter_direction(d, mu, 2.0 * ORC_PI * u[1], wn);
+                        d[0] = wn[0];
+                        d[1] = wn[1];
+                        d[2] = wn[2];
+                        tau_star = -log(1.0 - u[3]);
+                    }
+                    sum += packet;
+                    sum2 += packet * packet;
+                }
+                images[gp] = sum / (double)n_pp;
+                if (images_m2) images_m2[gp] = sum2 / (double)n_pp;
+            }
+    }
+    if (stats) *stats = c.st;
+    ctx_free(&c);
+    return ORC_OK;
+}

@@ -155,6 +155,13 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
  *   the grey-level scale.
  * oracle_recovery_error: out = {delta_mass, eps} of Sec. 7.
  * oracle_recover: the surrogate gradient-descent loop (see the source). */
+/* Backward Monte Carlo (Sec. 2.1.4, Eq. ble): n_pp packets per pixel;
+ * images in the units of oracle_render's (see the source for the steps and
+ * the photon ids).  prm->n_photons and photon_offset are not used. */
+int oracle_bmc_render(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,
+                      const orc_params* prm, uint32_t n_pp, double* images, double* images_m2,
+                      orc_stats* stats);
+
 int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera* cams, int n,
                               double* counts, double* q);
 double oracle_laplacian_reg(const orc_grid* grid, const double* beta, const double* w_layer, double* grad);

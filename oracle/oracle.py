@@ -126,6 +126,9 @@ def lib():
         L.oracle_recover.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.POINTER(Params), C.c_int,
                                      dp, dp, dp, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, dp]
         L.oracle_recover.restype = C.c_int
+        L.oracle_bmc_render.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.POINTER(Params),
+                                        C.c_uint32, dp, dp, C.POINTER(Stats)]
+        L.oracle_bmc_render.restype = C.c_int
         for f in ("oracle_voxel_scatter", "oracle_voxel_transmittance", "oracle_voxel_render",
                   "oracle_voxel_grad"):
             getattr(L, f).restype = C.c_int
@@ -406,4 +409,19 @@ def recover(s, beta0, measured, n_rays_side, delta, n_gd, n_outer, eta=0.0, w_la
     if rc != 0:
         raise OracleError(f"oracle_recover failed: {rc}")
     return b, cost[:n_outer * n_gd]
+
+
+def bmc_render(s, n_per_pixel, beta=None, with_m2=False, **kw):
+    """Backward Monte Carlo images (Sec. 2.1.4, Eq. ble): (images_flat, stats[, m2_flat]),
+    m2 = mean squared packet sum per pixel."""
+    b = _beta(s, beta)
+    img = np.zeros(_n_pix(s.cameras))
+    m2 = np.zeros_like(img) if with_m2 else None
+    st = Stats()
+    rc = lib().oracle_bmc_render(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
+                                 C.byref(make_params(s, **kw)), int(n_per_pixel), _dptr(img),
+                                 _dptr(m2) if with_m2 else None, C.byref(st))
+    if rc != 0:
+        raise OracleError(f"oracle_bmc_render failed: {rc}")
+    return (img, st.as_dict(), m2) if with_m2 else (img, st.as_dict())
 

@@ -112,7 +112,7 @@ def _break_planes(s, to_sun):
     return planes
 
 
-def single_scatter_image(s, cam, n_sub=16, n_gl=4):
+def single_scatter_image(s, cam, n_sub=16, n_gl=4, uniform=False):
     """Pixel-averaged single-scatter radiance per unit solar irradiance,
     Eq. (IRTE) with J = albedo P exp(-tau_sun) (Eq. (JEq) for the direct
     beam), by quadrature: sub-pixel directions, then along each line of sight
@@ -128,6 +128,8 @@ def single_scatter_image(s, cam, n_sub=16, n_gl=4):
     for row in range(cam.height):
         for col in range(cam.width):
             dirs, wts = pixel_grid(cam, row, col, n_sub)
+            if uniform:  # average over the image plane instead of the solid angle
+                wts = np.ones_like(wts)
             acc = 0.0
             for dvec, wt in zip(dirs, wts):
                 t0, t1 = 0.0, np.inf
