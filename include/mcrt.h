@@ -213,6 +213,24 @@ int mc_tape_free(mc_tape* tape, void* hip_stream);
  * library used are idle. */
 int mc_release_memory(void);
 
+/* Backward Monte Carlo (Sec. 2.1.4, Eq. ble): n_per_pixel packets per
+ * pixel traced from the camera centre through a uniform point of the pixel,
+ * with the forward method's free flights, albedo, roulette, HG scattering
+ * and max_events; at every collision the local estimate
+ * albedo I_s P(angle between the ray and the direction to the sun)
+ * exp(-tau to the top face) (0 when the path to the sun leaves through a
+ * side face: light enters through the top face only, as in mc_render).
+ * Packet i of global pixel p has photon id p n_per_pixel + i: Philox leg 0
+ * gives the point of the pixel (first two uniforms) and the first free path
+ * (third); legs s >= 1 as in mc_render.  params->n_photons and
+ * photon_offset are not used.  images (same layout and units as mc_render's)
+ * = mean over the pixel's packets of their sums; images_m2 (nullable) = mean
+ * of the squared sums (Var(image) = (images_m2 - images^2) / n_per_pixel).
+ * tally must be MC_TALLY_F64; stats.photons = packets, le_jobs = events. */
+int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                  const mc_params* params, uint32_t n_per_pixel, double* images, double* images_m2,
+                  mc_stats* stats, void* hip_stream);
+
 /* Voxelised forward model (Sec. 3) and its frozen-j gradient (Sec. 5.2).
  * Arrays "[camera][voxel]" are device arrays of n_cams * nx*ny*nz doubles,
  * camera-major, voxel index fastest.

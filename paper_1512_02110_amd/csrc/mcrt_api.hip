@@ -634,7 +634,8 @@ template <typename Real>
 int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
-        mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr) {
+        mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr,
+        uint32_t n_pp = 0) {
     int rc = MC_OK;
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -655,6 +656,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     if (mode == MODE_GRAD) bytes += round256(sizeof(double) * n_pix);
     if (k32 && mode == MODE_RENDER) bytes += round256(sizeof(float) * 2 * n_pix);
     if (k32 && mode == MODE_GRAD) bytes += round256(sizeof(float) * 2 * n_vox);
+    if (mode == MODE_BMC) bytes += round256(sizeof(HostCam) * n_cams);
     bytes += 256;
 
     Scratch S;
@@ -668,7 +670,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     double base_norm = 0.0;
     int dev = 0, n_cu = 0, per_cu = 0, grid_blocks = 1;
     const uint64_t n_norm = prm->n_photons_norm ? prm->n_photons_norm : prm->n_photons;
-    const int64_t need_blocks = (int64_t)((prm->n_photons + BLOCK - 1) / BLOCK);
+    // packets of the backward method: n_pp per pixel
+    const uint64_t n_work = mode == MODE_BMC ? (uint64_t)n_pix * n_pp : prm->n_photons;
+    const int64_t need_blocks = (int64_t)((n_work + BLOCK - 1) / BLOCK);
     bool tape_counts = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the transport launch (stats only)
     double t_transport = 0.0, t_tape = 0.0;
@@ -808,6 +812,36 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         } else {
             CHECK_HIP(launch_fill_f64(images, n_pix, stream));
         }
+    } else if (mode == MODE_BMC) {
+        A.img = images;
+        A.img_m2 = images_m2;
+        A.n_pp = n_pp;
+        CHECK_HIP(launch_fill_f64(images, n_pix, stream));
+        if (images_m2) CHECK_HIP(launch_fill_f64(images_m2, n_pix, stream));
+        HostCam* hc = S.take<HostCam>(n_cams);
+        int64_t off = 0;
+        for (int first = 0; first < n_cams; first += CAM_CHUNK) {
+            CamChunk ch;
+            std::memset(&ch, 0, sizeof(ch));
+            ch.first = first;
+            ch.n = n_cams - first < CAM_CHUNK ? n_cams - first : CAM_CHUNK;
+            for (int i = 0; i < ch.n; ++i) {
+                const mc_camera& c = cams[first + i];
+                HostCam& h = ch.c[i];
+                std::memcpy(h.pos, c.pos, sizeof(h.pos));
+                std::memcpy(h.R, c.R, sizeof(h.R));
+                h.fx = c.fx;
+                h.fy = c.fy;
+                h.cx = c.cx;
+                h.cy = c.cy;
+                h.width = c.width;
+                h.height = c.height;
+                h.pix_off = off;
+                off += (int64_t)c.width * c.height;
+            }
+            CHECK_HIP(launch_vox_cams(ch, hc, stream));
+        }
+        A.hcams = hc;
     } else if (mode == MODE_VOXEL) {
         // images carries j: the tallies L_c(k), turned into j_c(k) at the end
         A.Lc = images;
@@ -908,7 +942,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         } else {
             tape_counts = true;
         }
-    } else if (grid_blocks > 0 && (mode == MODE_TRACE || prm->n_photons > 0)) {
+    } else if (grid_blocks > 0 && (mode == MODE_TRACE || n_work > 0)) {
         if (stats) {
             CHECK_HIP(hipEventCreate(&ev0));
             CHECK_HIP(hipEventCreate(&ev1));
@@ -963,7 +997,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         }
         CHECK_HIP(hipStreamSynchronize(stream));
         if (stats) {
-            stats->photons = mode == MODE_TRACE ? trace_count : prm->n_photons;
+            stats->photons = mode == MODE_TRACE ? trace_count : n_work;
             stats->events = host_counters[1 + ST_EVENTS];
             stats->le_jobs = host_counters[1 + ST_LE];
             stats->vox_free = host_counters[1 + ST_VFREE];
@@ -1205,6 +1239,23 @@ int mc_voxel_scatter(const mc_grid* grid, const void* beta, int n_cams, const mc
                            0, nullptr, nullptr, nullptr, s);
     return run<float>(MODE_VOXEL, grid, beta, n_cams, cams, params, j, nullptr, nullptr, nullptr, stats, 0, 0, 0,
                       nullptr, nullptr, nullptr, s);
+}
+
+int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams, const mc_params* params,
+                  uint32_t n_per_pixel, double* images, double* images_m2, mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!images || n_per_pixel < 1 || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
+    if ((uint64_t)pixel_count(n_cams, cams) * n_per_pixel >= ((uint64_t)1 << 62)) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(images) || (images_m2 && !is_device_ptr(images_m2)))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_BMC, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0,
+                           0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
+    return run<float>(MODE_BMC, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0, 0,
+                      0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
 }
 
 int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int rays_per_side,

@@ -14,7 +14,9 @@ namespace mcrt {
 // with its local estimate to the tape, for a later gradient without replay.
 // MODE_VOXEL: photon transport without local estimates that tallies the
 // scattered power per voxel and camera (the voxelised model).
-enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4, MODE_VOXEL = 5 };
+// MODE_BMC: backward Monte Carlo, packets traced from the camera pixels with
+// the local estimate towards the sun.
+enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4, MODE_VOXEL = 5, MODE_BMC = 6 };
 enum { TALLY_F64 = 0, TALLY_K32 = 1 };
 enum {
     ST_PHOTONS = 0, ST_EVENTS, ST_LE, ST_VFREE, ST_VCONN,
@@ -104,6 +106,8 @@ struct KArgs {
     const double* gw;           // dL/di * normalisation per pixel (gradient)
     double* grad;               // F64 gradient
     double* Lc;                 // voxel model: [camera][voxel] scattered power
+    const HostCam* hcams;       // backward MC: cameras in double, absolute positions
+    uint32_t n_pp;              // backward MC: packets per pixel
     float* grad32;              // [2 n_vox] (K32 gradient)
     int64_t n_pix, n_vox;
     // occupancy bitmask of beta > 0: bit c covers voxels [c 2^msh, (c+1) 2^msh)

@@ -1310,6 +1310,145 @@ __global__ void __launch_bounds__(BLOCK) k_trace(KArgs<Real> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Backward Monte Carlo (Sec. 2.1.4): one packet per lane.
+
+// Transmittance from the collision towards the sun, Eq. (ble): exp(-tau) to
+// the top face, 0 when the path leaves through a side face (light enters
+// through the top face only, as in the forward method).
+template <typename Real>
+__device__ __forceinline__ double sun_transmittance(const KArgs<Real>& A, const Photon<Real>& ph) {
+    const Real sx = -A.wsx, sy = -A.wsy, sz = -A.wsz;
+    const double x = absolute(ph.ix, ph.fx, A.G.dx), y = absolute(ph.iy, ph.fy, A.G.dy);
+    const double z = absolute(ph.iz, ph.fz, A.G.dz);
+    const double lx = (double)A.G.nx * (double)A.G.dx, ly = (double)A.G.ny * (double)A.G.dy;
+    const double tz = ((double)A.G.nz * (double)A.G.dz - z) / (double)sz;
+    const double xe = x + tz * (double)sx, ye = y + tz * (double)sy;
+    if (!(xe >= 0.0 && xe <= lx && ye >= 0.0 && ye <= ly)) return 0.0;
+    ConnWalk<Real> W;
+    const Real texit = conn_begin(W, A.G, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, sx, sy, sz);
+    if (texit < (Real)0) return 0.0;
+    double tau = 0.0;
+    for (;;) {
+        bool cx, cy, cz;
+        const Real tn = conn_next(W, cx, cy, cz);
+        const bool last = tn >= texit;
+        tau += (double)A.beta[W.k] * (double)((last ? texit : tn) - W.t);
+        if (last) break;
+        conn_cross(W, tn, cx, cy, cz);
+        if ((uint32_t)W.k >= (uint32_t)A.n_vox) break;
+    }
+    return exp(-tau);
+}
+
+// Packet id p * n_pp + i of global pixel p: leg 0 gives the point of the
+// pixel and the first free path; the camera centre and the back-projected
+// direction are in double; the packet enters the domain where its ray does.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_bmc(KArgs<Real> A) {
+    __shared__ unsigned long long s_st[ST_N];
+    if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
+    __syncthreads();
+    uint32_t n_ev = 0;
+    uint64_t vfree = 0;
+    const Real sx = -A.wsx, sy = -A.wsy, sz = -A.wsz;
+    const uint64_t total = (uint64_t)A.n_pix * A.n_pp;
+    const double L[3] = {(double)A.G.nx * (double)A.G.dx, (double)A.G.ny * (double)A.G.dy,
+                         (double)A.G.nz * (double)A.G.dz};
+    const double dv[3] = {(double)A.G.dx, (double)A.G.dy, (double)A.G.dz};
+    const int nv[3] = {A.G.nx, A.G.ny, A.G.nz};
+    for (uint64_t id = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total;
+         id += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t gp = (int64_t)(id / A.n_pp);
+        int lo = 0, hi = A.n_cams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (A.hcams[mid].pix_off <= gp) lo = mid;
+            else hi = mid - 1;
+        }
+        const HostCam& cam = A.hcams[lo];
+        const int64_t lp = gp - cam.pix_off;
+        const int row = (int)(lp / cam.width), col = (int)(lp % cam.width);
+        const uint4 r = draw(A.seed, id, 0u);
+        const double qx = ((double)col + (double)uniform01<Real>(r.x) - cam.cx) / cam.fx;
+        const double qy = ((double)row + (double)uniform01<Real>(r.y) - cam.cy) / cam.fy;
+        double d[3];
+        for (int a = 0; a < 3; ++a) d[a] = cam.R[a] * qx + cam.R[3 + a] * qy + cam.R[6 + a];
+        const double il = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double t0 = 0.0, t1 = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            d[a] *= il;
+            if (d[a] == 0.0) {
+                if (cam.pos[a] < 0.0 || cam.pos[a] > L[a]) t1 = -1.0;
+                continue;
+            }
+            const double ta = (0.0 - cam.pos[a]) / d[a], tb = (L[a] - cam.pos[a]) / d[a];
+            t0 = fmax(t0, fmin(ta, tb));
+            t1 = fmin(t1, fmax(ta, tb));
+        }
+        if (!(t1 > t0)) {
+            atomicAdd(&s_st[ST_SIDE], 1ull);
+            continue;
+        }
+        Photon<Real> ph;
+        int iv[3];
+        Real fv[3];
+        for (int a = 0; a < 3; ++a) {
+            const double f = (cam.pos[a] + t0 * d[a]) / dv[a];
+            int i = (int)floor(f);
+            if (d[a] < 0.0 && f == floor(f)) i -= 1;
+            i = i < 0 ? 0 : (i > nv[a] - 1 ? nv[a] - 1 : i);
+            iv[a] = i;
+            fv[a] = (Real)(f - (double)i);
+        }
+        ph.ix = iv[0];
+        ph.iy = iv[1];
+        ph.iz = iv[2];
+        ph.fx = fv[0];
+        ph.fy = fv[1];
+        ph.fz = fv[2];
+        ph.wx = (Real)d[0];
+        ph.wy = (Real)d[1];
+        ph.wz = (Real)d[2];
+        ph.weight = (Real)1;
+        ph.taustar = -m_log((Real)1 - uniform01<Real>(r.z));
+        ph.t_exit = (Real)0;
+        ph.s = 0;
+        ph.pid = id;
+        double packet = 0.0;
+        for (;;) {
+            const int left = free_flight(A, (const uint32_t*)nullptr, ph, vfree, 0xffffffffu);
+            if (left) {
+                atomicAdd(&s_st[ST_TOP + left - 1], 1ull);
+                break;
+            }
+            ph.s += 1;
+            ++n_ev;
+            const double t = sun_transmittance(A, ph);
+            if (t > 0.0) {
+                const Real cosang = ph.wx * sx + ph.wy * sy + ph.wz * sz;
+                packet += (double)A.albedo * (double)ph.weight * (double)hg_phase(A.g, cosang) * t;
+            }
+            const int fate = after_collision(A, ph);
+            if (fate >= 0) {
+                atomicAdd(&s_st[fate == MC_FATE_CAP ? ST_CAP : ST_RR], 1ull);
+                break;
+            }
+        }
+        if (packet != 0.0) {
+            unsafeAtomicAdd(A.img + gp, packet / (double)A.n_pp);
+            if (A.img_m2) unsafeAtomicAdd(A.img_m2 + gp, packet * packet / (double)A.n_pp);
+        }
+    }
+    if (n_ev) {
+        atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
+        atomicAdd(&s_st[ST_LE], (unsigned long long)n_ev);
+    }
+    if (vfree) atomicAdd(&s_st[ST_VFREE], (unsigned long long)vfree);
+    __syncthreads();
+    if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 
 template <typename Real>
@@ -1476,6 +1615,10 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
                                   : launch_r<Real, MODE_RTAPE, TALLY_K32>(a, grid, s);
     }
     if (mode == MODE_VOXEL) return launch_r<Real, MODE_VOXEL, TALLY_F64>(a, grid, s);
+    if (mode == MODE_BMC) {
+        hipLaunchKernelGGL(k_bmc<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_trace<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -1496,6 +1639,7 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
     if (mode == MODE_RTAPE) return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64>(a, b)
                                                       : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
     if (mode == MODE_VOXEL) return occ_r<Real, MODE_VOXEL, TALLY_F64>(a, b);
+    if (mode == MODE_BMC) return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_bmc<Real>, BLOCK, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
 

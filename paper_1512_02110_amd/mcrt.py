@@ -87,7 +87,8 @@ PATH_DTYPE = np.dtype([("n_events", "<i4"), ("fate", "<i4"), ("exit_pos", "<f8",
 EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "mc_error_string",
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
            "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
-           "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover"]
+           "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover",
+           "mc_bmc_render"]
 
 
 class McError(RuntimeError):
@@ -127,6 +128,8 @@ def load_library(path: str = LIB_PATH):
         L.mc_voxel_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
         L.mc_voxel_grad.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp,
                                     vp, vp]
+        L.mc_bmc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.POINTER(McParams),
+                                    C.c_uint32, vp, vp, C.POINTER(McStats), vp]
         L.mc_voxel_conditioning.argtypes = [C.POINTER(McGrid), C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
         L.mc_regularizer.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, vp, vp, vp]
         L.mc_image_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -139,7 +142,7 @@ def load_library(path: str = LIB_PATH):
                   "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
                   "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning",
                   "mc_regularizer", "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error",
-                  "mc_recover"):
+                  "mc_recover", "mc_bmc_render"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -318,6 +321,23 @@ def mc_grad_beta(s, beta, dl_dimages, transport="fp32", tally="f64", stats=True,
         rc = load_library().mc_grad_beta(*args)
         _check("mc_grad_beta", rc)
     return g, (_stats(st) if stats else None)
+
+
+def mc_bmc_render(s, beta, n_per_pixel, transport="fp32", with_m2=False, stats=True, stream=None, **kw):
+    """Backward Monte Carlo images (Sec. 2.1.4, Eq. ble).  Returns (images, stats[, m2])."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    n = n_pixels(s)
+    img = torch.empty(n, dtype=torch.float64, device=beta.device)
+    m2 = torch.empty(n, dtype=torch.float64, device=beta.device) if with_m2 else None
+    st = McStats() if stats else None
+    rc = load_library().mc_bmc_render(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                      make_cameras(s.cameras), C.byref(make_params(s, transport=transport, **kw)),
+                                      int(n_per_pixel), C.c_void_p(img.data_ptr()), _ptr(m2),
+                                      C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
+    _check("mc_bmc_render", rc)
+    out = (img, _stats(st) if stats else None)
+    return out + (m2,) if with_m2 else out
 
 
 def mc_voxel_scatter(s, beta, transport="fp32", stats=True, out=None, stream=None, **kw):
