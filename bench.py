@@ -157,6 +157,23 @@ def voxel_model(M, torch, np, stream, s, n_side=2):
             "render_ms": round(t_r, 3), "grad_ms": round(t_g, 3)}
 
 
+def bmc(M, torch, np, stream, s, n_per_pixel=64):
+    """Backward Monte Carlo (Sec. 2.1.4) on the same scene: n_per_pixel
+    packets per pixel, FP32 transport; warm-up, then one timed call."""
+    b32 = M.beta_tensor(s, "fp32")
+    M.mc_bmc_render(s, b32, 4, seed=3, stats=False)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    img, st = M.mc_bmc_render(s, b32, n_per_pixel, seed=3, stats=True)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b)
+    return {"workload": f"same scene, {n_per_pixel} packets per pixel ({st['photons']:.3e} packets), FP32 transport",
+            "ms": round(t, 3), "kernel_ms": round(st.timing["transport_ms"], 3),
+            "events_per_s": st["events"] / (t / 1e3), "events": st["events"],
+            "vox_free_per_s": st["vox_free"] / (t / 1e3)}
+
+
 def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=3, n_gd=5, n_side=2):
     """The surrogate recovery loop (Secs. 5.2, 6, 7) on the same grid and
     cameras: measured images of the truth from the voxelised model (seed 99,
@@ -392,6 +409,7 @@ def main():
     if not args.no_voxel:
         out["voxel_model"] = voxel_model(M, torch, np, stream, s)
         out["recovery"] = recovery(M, torch, np, stream, s)
+        out["bmc"] = bmc(M, torch, np, stream, s)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
