@@ -53,16 +53,19 @@ template <int KIND>
 __global__ void k_atomic(void* data, uint32_t n, uint32_t ops) {
     __shared__ double lds[8192];
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (KIND >= 5) {
+    if (KIND == 5 || KIND == 6) {
         for (uint32_t i = threadIdx.x; i < 8192; i += blockDim.x) lds[i] = 0.0;
         __syncthreads();
     }
-    uint32_t h = mix32(tid * 0x9E3779B9u + 7u);
+    // KIND 7 and 8: groups of 8 and 16 consecutive lanes add to consecutive
+    // doubles of one hashed line (64 and 128 bytes)
+    constexpr uint32_t G = KIND == 7 ? 8u : (KIND == 8 ? 16u : 1u);
+    uint32_t h = mix32((G > 1 ? tid / G : tid) * 0x9E3779B9u + 7u);
     float keep = 0.f;
     for (uint32_t j = 0; j < ops; ++j) {
         h = mix32(h + j);
-        const uint32_t i = h % n;
-        if (KIND == 0) {
+        const uint32_t i = G > 1 ? (h % (n / G)) * G + (tid % G) : h % n;
+        if (KIND == 0 || KIND == 7 || KIND == 8) {
             unsafeAtomicAdd((double*)data + i, 1.0);
         } else if (KIND == 1) {
             __hip_atomic_fetch_add((double*)data + i, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -78,7 +81,7 @@ __global__ void k_atomic(void* data, uint32_t n, uint32_t ops) {
             atomicAdd(((float*)lds) + (i & 16383u), 1.0f);
         }
     }
-    if (KIND >= 5) {
+    if (KIND == 5 || KIND == 6) {
         __syncthreads();
         if (threadIdx.x == 0 && lds[0] == -1.0) ((double*)data)[0] = lds[1];
     }
@@ -141,7 +144,8 @@ int mc_micro_gather(const float* data, uint32_t n, uint32_t blocks, uint32_t loa
 // Atomic adds at hashed addresses in [0, n) of `data` (n elements of the
 // kind's type; LDS kinds use min(n, LDS size) and data only as a sink).
 int mc_micro_atomic(void* data, uint32_t n, uint32_t blocks, uint32_t ops, int kind, void* stream) {
-    if (!data || n == 0 || kind < 0 || kind > 6) return (int)hipErrorInvalidValue;
+    if (!data || n == 0 || kind < 0 || kind > 8) return (int)hipErrorInvalidValue;
+    if ((kind == 7 && n < 8) || (kind == 8 && n < 16)) return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
     switch (kind) {
         case 0: hipLaunchKernelGGL(k_atomic<0>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
@@ -150,7 +154,9 @@ int mc_micro_atomic(void* data, uint32_t n, uint32_t blocks, uint32_t ops, int k
         case 3: hipLaunchKernelGGL(k_atomic<3>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
         case 4: hipLaunchKernelGGL(k_atomic<4>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
         case 5: hipLaunchKernelGGL(k_atomic<5>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
-        default: hipLaunchKernelGGL(k_atomic<6>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 6: hipLaunchKernelGGL(k_atomic<6>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        case 7: hipLaunchKernelGGL(k_atomic<7>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
+        default: hipLaunchKernelGGL(k_atomic<8>, dim3(blocks), dim3(256), 0, s, data, n, ops); break;
     }
     return (int)hipGetLastError();
 }

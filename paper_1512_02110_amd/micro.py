@@ -72,14 +72,17 @@ def main(quick=False):
               flush=True)
     ops = 32 if quick else 128
     kinds = {0: "f64 device", 1: "f64 workgroup", 2: "f32 device", 3: "f32 device returning",
-             4: "u64 device", 5: "f64 LDS", 6: "f32 LDS"}
+             4: "u64 device", 5: "f64 LDS", 6: "f32 LDS", 7: "f64 device, 8 lanes per 64-B line",
+             8: "f64 device, 16 lanes per 128-B line"}
     for nbytes in (64, 1 << 20, 16 << 20, 64 << 20):
         n = nbytes // 8
         data = torch.zeros(n, dtype=torch.float64, device=dev)
         for kind, name in kinds.items():
             if kind >= 5 and nbytes != 64 and nbytes != (1 << 20):
                 continue
-            nn = n if kind in (0, 1, 4) else (2 * n if kind in (2, 3) else min(n, 8192 if kind == 5 else 16384))
+            if kind == 8 and n < 16:
+                continue
+            nn = n if kind in (0, 1, 4, 7, 8) else (2 * n if kind in (2, 3) else min(n, 8192 if kind == 5 else 16384))
 
             def run():
                 rc = L.mc_micro_atomic(C.c_void_p(data.data_ptr()), nn, blocks, ops, kind, st)
