@@ -657,6 +657,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     if (k32 && mode == MODE_RENDER) bytes += round256(sizeof(float) * 2 * n_pix);
     if (k32 && mode == MODE_GRAD) bytes += round256(sizeof(float) * 2 * n_vox);
     if (mode == MODE_BMC) bytes += round256(sizeof(HostCam) * n_cams);
+    // voxel model: the tally L, [voxel][cameras rounded up to a multiple of 8]
+    const int lc_pitch = (n_cams + 7) & ~7;
+    if (mode == MODE_VOXEL) bytes += round256(sizeof(double) * n_vox * lc_pitch);
     bytes += 256;
 
     Scratch S;
@@ -843,9 +846,10 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         }
         A.hcams = hc;
     } else if (mode == MODE_VOXEL) {
-        // images carries j: the tallies L_c(k), turned into j_c(k) at the end
-        A.Lc = images;
-        CHECK_HIP(launch_fill_f64(images, (int64_t)n_cams * n_vox, stream));
+        // the tallies L_c(k), turned into j_c(k) (images) at the end
+        A.Lc = S.take<double>(n_vox * lc_pitch);
+        A.lc_pitch = lc_pitch;
+        CHECK_HIP(launch_fill_f64(A.Lc, n_vox * lc_pitch, stream));
     } else if (mode == MODE_GRAD) {
         double* gw = S.take<double>(n_pix);
         CHECK_HIP(launch_grad_weights(gw, dl, ncams, n_cams, n_pix, base_norm, stream));
@@ -953,7 +957,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     }
 
     if (mode == MODE_VOXEL)
-        CHECK_HIP(launch_voxel_finish<Real>(images, betap, n_cams, n_vox, base_norm, stream));
+        CHECK_HIP(launch_voxel_finish<Real>(images, A.Lc, lc_pitch, betap, n_cams, n_vox, base_norm, stream));
     if (mode == MODE_RENDER) {
         if (k32) CHECK_HIP(launch_kahan_reduce(images, A.img32, n_pix, stream));
         CHECK_HIP(launch_normalize(images, ncams, n_cams, n_pix, base_norm, 1, stream));

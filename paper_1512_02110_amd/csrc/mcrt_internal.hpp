@@ -105,7 +105,8 @@ struct KArgs {
     float* img32;               // [2 n_pix]: sum, compensation (K32 tally)
     const double* gw;           // dL/di * normalisation per pixel (gradient)
     double* grad;               // F64 gradient
-    double* Lc;                 // voxel model: [camera][voxel] scattered power
+    double* Lc;                 // voxel model: [voxel][lc_pitch] scattered power per camera
+    int lc_pitch;               // cameras rounded up to a multiple of 8
     const HostCam* hcams;       // backward MC: cameras in double, absolute positions
     uint32_t n_pp;              // backward MC: packets per pixel
     float* grad32;              // [2 n_vox] (K32 gradient)
@@ -173,7 +174,8 @@ hipError_t launch_bin_scan(const KArgs<Real>& a, hipStream_t s);
 template <typename Real>
 hipError_t launch_deposit(const KArgs<Real>& a, int tally, const DepositItem* items, int n_items, hipStream_t s);
 template <typename Real>
-hipError_t launch_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base, hipStream_t s);
+hipError_t launch_voxel_finish(double* j, const double* L, int pitch, const Real* beta, int n_cams, int64_t n_vox,
+                               double base, hipStream_t s);
 
 // Voxelised model, deterministic part (mcrt_voxel.hip): FP64 throughout.
 // Cameras as HostCam (double), uploaded by k_vox_cams from kernel arguments.

@@ -388,27 +388,6 @@ __device__ __forceinline__ bool le_geometry(const KArgs<Real>& A, const DevCam<R
     return true;
 }
 
-// Sec. 3.2, Eq. (Lcupdate): the collision adds albedo I_s P(angle) to
-// L_c(voxel) of every camera, the angle between the incoming direction and
-// the direction from the collision point to the camera centre.
-template <typename Real>
-__device__ __forceinline__ void voxel_tally(const KArgs<Real>& A, const Photon<Real>& ph, uint32_t& n_tally) {
-    const int64_t k = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
-    const double aw = (double)A.albedo * (double)ph.weight;
-    for (int c = 0; c < A.n_cams; ++c) {
-        const DevCam<Real>& cam = A.cams[c];
-        // X_c - X from voxel-local parts (exact integer differences)
-        const Real dx = ((Real)(cam.icx - ph.ix) + (cam.fcx - ph.fx)) * A.G.dx;
-        const Real dy = ((Real)(cam.icy - ph.iy) + (cam.fcy - ph.fy)) * A.G.dy;
-        const Real dz = ((Real)(cam.icz - ph.iz) + (cam.fcz - ph.fz)) * A.G.dz;
-        const Real r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < (Real)1e-12) continue;
-        const Real cosang = (ph.wx * dx + ph.wy * dy + ph.wz * dz) / m_sqrt(r2);
-        unsafeAtomicAdd(A.Lc + (int64_t)c * A.n_vox + k, aw * (double)hg_phase(A.g, cosang));
-        ++n_tally;
-    }
-}
-
 // Steps (v)-(vi) after collision s: returns -1 while the photon lives, else
 // its fate (capped or ended by Russian roulette).
 template <typename Real>
@@ -441,6 +420,61 @@ struct JobQueue {
     Real r[QCAP], pre[QCAP];
     int32_t pix[QCAP];
 };
+
+// Sec. 3.2, Eq. (Lcupdate): a collision adds albedo I_s P(angle) to L_c of
+// its voxel for every camera c, the angle between the incoming direction and
+// the direction from the collision point to the camera centre.
+//
+// The wave's collisions (mask cm) are staged in its LDS queue and the
+// (collision, camera) pairs are dealt to the lanes camera-fastest; lane l
+// starts at pair l, i.e. at collision e0 = l / n_cams, camera c0 = l % n_cams,
+// and steps by 64 pairs (e_step, c_step).  With L laid out [voxel][camera,
+// padded to a multiple of 8] the atomics of one instruction fall on a few
+// cache lines instead of 64, which the memory side combines.
+template <typename Real, int MODE>
+__device__ __forceinline__ void voxel_tally(const KArgs<Real>& A, JobQueue<Real, MODE>& Q, const Photon<Real>& ph,
+                                            bool collided, unsigned long long cm, uint32_t e0, uint32_t c0,
+                                            uint32_t e_step, uint32_t c_step, uint32_t& n_tally) {
+    if (collided) {
+        const uint32_t slot = lanes_below(cm);
+        Q.vox[slot] = (uint32_t)ph.ix | ((uint32_t)ph.iy << 11) | ((uint32_t)ph.iz << 22);
+        Q.fx[slot] = ph.fx;
+        Q.fy[slot] = ph.fy;
+        Q.fz[slot] = ph.fz;
+        Q.vx[slot] = ph.wx;
+        Q.vy[slot] = ph.wy;
+        Q.vz[slot] = ph.wz;
+        Q.pre[slot] = ph.weight;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n_e = (uint32_t)__popcll(cm);
+    const uint32_t n_c = (uint32_t)A.n_cams;
+    for (uint32_t e = e0, c = c0; e < n_e;) {
+        const uint32_t v = Q.vox[e];
+        const int ix = (int)(v & 2047u), iy = (int)((v >> 11) & 2047u), iz = (int)(v >> 22);
+        const DevCam<Real>& cam = A.cams[c];
+        // X_c - X from voxel-local parts (exact integer differences)
+        const Real dx = ((Real)(cam.icx - ix) + (cam.fcx - Q.fx[e])) * A.G.dx;
+        const Real dy = ((Real)(cam.icy - iy) + (cam.fcy - Q.fy[e])) * A.G.dy;
+        const Real dz = ((Real)(cam.icz - iz) + (cam.fcz - Q.fz[e])) * A.G.dz;
+        const Real r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 >= (Real)1e-12) {
+            const Real cosang = (Q.vx[e] * dx + Q.vy[e] * dy + Q.vz[e] * dz) / m_sqrt(r2);
+            const int64_t k = (int64_t)ix + (int64_t)A.G.nx * iy + (int64_t)A.G.nxy * iz;
+            const double aw = (double)A.albedo * (double)Q.pre[e];
+            unsafeAtomicAdd(A.Lc + k * A.lc_pitch + c, aw * (double)hg_phase(A.g, cosang));
+            ++n_tally;
+        }
+        e += e_step;
+        c += c_step;
+        if (c >= n_c) {
+            c -= n_c;
+            ++e;
+        }
+    }
+    // the next staging must not overtake this pass's reads
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Walk of a connection ray.  Its length is clipped at job start to where
 // the ray leaves the domain, so that the walk ends at its length and keeps
@@ -756,6 +790,10 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
     const uint32_t w_first = MODE == MODE_TAPE || MODE == MODE_RTAPE ? wave_id * A.tp.rw : 0u;
     uint32_t w_used = 0;
+    // voxel tally: this lane's first (collision, camera) pair and the step
+    const uint32_t n_c = A.n_cams > 0 ? (uint32_t)A.n_cams : 1u;
+    const uint32_t v_e0 = __lane_id() / n_c, v_c0 = __lane_id() % n_c;
+    const uint32_t v_estep = (uint32_t)WAVE / n_c, v_cstep = (uint32_t)WAVE % n_c;
 
     for (;;) {
         const unsigned long long need = __ballot(!alive && !exhausted);
@@ -786,7 +824,8 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
             }
         }
         if (MODE == MODE_VOXEL) {
-            if (collided) voxel_tally(A, ph, n_le);
+            const unsigned long long cm = __ballot(collided);
+            if (cm && A.n_cams > 0) voxel_tally<Real, MODE>(A, Q, ph, collided, cm, v_e0, v_c0, v_estep, v_cstep, n_le);
         } else if (__ballot(collided)) {
             for (int c = 0; c < A.n_cams; ++c) {
                 const DevCam<Real>& cam = A.cams[c];
@@ -1500,13 +1539,15 @@ __global__ void k_fill_f32(float* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.0f;
 }
-// Eq. (Jc): j = L * base / beta, 0 where beta = 0 (base = mu0 A_top / N).
+// Eq. (Jc): j = L * base / beta, 0 where beta = 0 (base = mu0 A_top / N);
+// L is laid out [voxel][pitch], j [camera][voxel].
 template <typename Real>
-__global__ void k_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base) {
-    const int64_t n = (int64_t)n_cams * n_vox;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double b = (double)beta[i % n_vox];
-        j[i] = b > 0.0 ? j[i] * base / b : 0.0;
+__global__ void k_voxel_finish(double* j, const double* L, int pitch, const Real* beta, int n_cams, int64_t n_vox,
+                               double base) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_vox; k += (int64_t)gridDim.x * blockDim.x) {
+        const double b = (double)beta[k];
+        const double* Lk = L + k * pitch;
+        for (int c = 0; c < n_cams; ++c) j[(int64_t)c * n_vox + k] = b > 0.0 ? Lk[c] * base / b : 0.0;
     }
 }
 
@@ -1644,15 +1685,18 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
 }
 
 template <typename Real>
-hipError_t launch_voxel_finish(double* j, const Real* beta, int n_cams, int64_t n_vox, double base, hipStream_t s) {
-    const int64_t n = (int64_t)n_cams * n_vox;
-    const int grid = (int)std::min<int64_t>((n + BLOCK - 1) / BLOCK, 65536);
-    if (grid > 0) hipLaunchKernelGGL(k_voxel_finish<Real>, dim3(grid), dim3(BLOCK), 0, s, j, beta, n_cams, n_vox, base);
+hipError_t launch_voxel_finish(double* j, const double* L, int pitch, const Real* beta, int n_cams, int64_t n_vox,
+                               double base, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>((n_vox + BLOCK - 1) / BLOCK, 65536);
+    if (grid > 0)
+        hipLaunchKernelGGL(k_voxel_finish<Real>, dim3(grid), dim3(BLOCK), 0, s, j, L, pitch, beta, n_cams, n_vox, base);
     return hipGetLastError();
 }
 
-template hipError_t launch_voxel_finish<float>(double*, const float*, int, int64_t, double, hipStream_t);
-template hipError_t launch_voxel_finish<double>(double*, const double*, int, int64_t, double, hipStream_t);
+template hipError_t launch_voxel_finish<float>(double*, const double*, int, const float*, int, int64_t, double,
+                                               hipStream_t);
+template hipError_t launch_voxel_finish<double>(double*, const double*, int, const double*, int, int64_t, double,
+                                                hipStream_t);
 
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s) {
