@@ -358,7 +358,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     const int nt = A.tp.n_tiles;
     const size_t rec = sizeof(TapeRec<Real>);
     const int wpb = BLOCK / 64;  // wavefronts per block
-    size_t free_b = 0, total_b = 0;
+    size_t free_b = 0;
     char* pool = nullptr;
     // tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
     uint32_t* meta = nullptr;
@@ -527,7 +527,7 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     float ms = 0.f;
     const int nt = A.tp.n_tiles;
     const size_t rec = sizeof(TapeRec<Real>);
-    size_t free_b = 0, total_b = 0;
+    size_t free_b = 0;
     char* pool = nullptr;
     uint32_t* meta = nullptr;  // tile_count[nt], bin_start[nt], tile_end[nt], slice[nt][nw]
     DepositItem* ditems = nullptr;

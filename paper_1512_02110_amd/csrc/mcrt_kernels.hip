@@ -539,18 +539,24 @@ __device__ __forceinline__ void conn_cross(ConnWalk<Real>& C, Real tn, bool cx, 
 }
 
 // One lane's connection ray in flight.  The optical depth of a voxel is
-// added one step after the walk left it, so that the fetch of its extinction
-// has a whole step to arrive.  The walk runs in pairs of steps with b0 and b1
-// trading roles (job_step<PH>): in step PH, b[PH] is the current voxel's
-// extinction (in flight) and b[1-PH] the previous voxel's, whose term
-// b[1-PH] * lp is added and whose register then receives the fetch for the
-// next voxel.  With fixed roles and no register copies, the wait for a fetch
-// falls one step after it was issued.
+// added some steps after the walk left it, so that the fetch of its
+// extinction has time to arrive, with fixed register roles (no copies):
+//  * the walks without a second phase (render, tape) run in triples of steps
+//    (job_step3<PH>) over a ring of three slots (b0, L0), (b1, L1), (b2, L2):
+//    voxel m's extinction and length sit in slot m mod 3; step n adds the
+//    term of voxel n - 2 and refills that slot with the length of voxel n
+//    and the fetch for voxel n + 1, which is waited for two steps later;
+//  * the gradient walk runs in pairs (job_step<PH>): in step PH, b[PH] is
+//    the current voxel's extinction (in flight) and b[1-PH] the previous
+//    voxel's, whose term b[1-PH] * lp is added and whose register then
+//    receives the fetch for the next voxel, waited for one step later.
 template <typename Real>
 struct Job {
     ConnWalk<Real> W;
     Real r;        // length to the camera, then clipped to the domain
-    Real b0, b1, lp;
+    Real b0, b1, b2;
+    Real L0, L1, L2;  // lengths of the ring (triples)
+    Real lp;          // length of the previous voxel (pairs)
     Real pre;      // albedo * I_s * P / r^2
     double tau;    // optical depth so far (FP64)
     double a;      // gradient weight of the second walk
@@ -563,6 +569,35 @@ struct Job {
     Real f0x, f0y, f0z, vx, vy, vz;
 };
 
+// Step n (n mod 3 = PH) of a walk without a second phase; returns true when
+// the ray is done.  The whole wavefront steps together (no branch around
+// the step, so that the compiler can count the fetches in flight and wait
+// for the oldest only): a lane whose ray is done (act false) keeps stepping
+// with its end clipped to where it stopped, i.e. with zero lengths and
+// fetches of the shared zero word, which adds its two pending terms in
+// order and nothing else.
+template <typename Real, int PH>
+__device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J, bool act) {
+    Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
+    Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
+    Real& Ln = PH == 0 ? J.L0 : (PH == 1 ? J.L1 : J.L2);  // slot n
+    bool cx, cy, cz;
+    const Real tn = conn_next(J.W, cx, cy, cz);
+    const bool last = tn >= J.r;
+    const Real tend = last ? J.r : tn;
+    J.tau += (double)bo * (double)Lo;
+    Ln = tend - J.W.t;
+    J.steps += act ? 1u : 0u;
+    conn_cross(J.W, tend, cx, cy, cz);
+    const bool done = last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
+    J.r = done ? tend : J.r;
+    // branch free: voxel 0 is a valid index to test when the ray is done
+    const int kk = done ? 0 : J.W.k;
+    const bool none = (int)done | (int)!occupied(A, mask, kk);
+    bo = A.beta[none ? (uint32_t)A.n_vox : (uint32_t)kk];
+    return done;
+}
+
 template <typename Real>
 __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J) {
     const Real texit = conn_begin(J.W, A.G, J.i0x, J.i0y, J.i0z, J.f0x, J.f0y, J.f0z, J.vx, J.vy, J.vz);
@@ -574,14 +609,14 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
         J.r = fmin(J.r, texit);
     }
     J.b0 = J.phase == 2 ? (Real)0 : beta_load(A, mask, J.W.k);
-    J.b1 = (Real)0;
-    J.lp = (Real)0;
+    J.b1 = J.b2 = (Real)0;
+    J.L0 = J.L1 = J.L2 = J.lp = (Real)0;
     J.tau = 0.0;
     J.steps = 0;
 }
 
-// One voxel of the connection ray (step PH of a pair); returns true when the
-// ray is done.
+// One voxel of the gradient's connection ray (step PH of a pair); returns
+// true when the ray is done.
 template <typename Real, int MODE, int TALLY, int PH>
 __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J) {
     Real& prev = PH == 0 ? J.b1 : J.b0;
@@ -622,7 +657,22 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
                                            uint64_t& vconn, bool& rec) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     vconn += J.steps;
-    J.tau += ((double)J.b0 + (double)J.b1) * (double)J.lp;  // the last voxel
+    if (MODE == MODE_GRAD) {
+        J.tau += ((double)J.b0 + (double)J.b1) * (double)J.lp;  // the last voxel
+    } else {
+        // the voxels still pending when the walk ended in step n = steps - 1:
+        // n - 1 and n, in this order (a slot added since holds a zero fetch
+        // or a zero length)
+        const uint32_t n = J.steps + 2u;  // n + 3, kept non-negative
+        const uint32_t s1 = (n - 1u) % 3u, s2 = n % 3u;
+        const Real b0 = J.b0, b1 = J.b1, b2 = J.b2, L0 = J.L0, L1 = J.L1, L2 = J.L2;
+        const Real bs1 = s1 == 0u ? b0 : (s1 == 1u ? b1 : b2);
+        const Real Ls1 = s1 == 0u ? L0 : (s1 == 1u ? L1 : L2);
+        const Real bs2 = s2 == 0u ? b0 : (s2 == 1u ? b1 : b2);
+        const Real Ls2 = s2 == 0u ? L0 : (s2 == 1u ? L1 : L2);
+        J.tau += (double)bs1 * (double)Ls1;
+        J.tau += (double)bs2 * (double)Ls2;
+    }
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
     if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
         tally_f64<TALLY>(A.img, A.img32, J.pix, C);
@@ -721,18 +771,33 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
             qhead += take;
         }
         // walk until a quarter of the lanes are idle (all, if nothing is
-        // queued), in pairs of steps (a job always starts with step 0)
+        // queued), in pairs (gradient) or triples of steps (a job always
+        // starts with step 0)
         const uint32_t keep = (qtail - qhead) > 0 ? (uint32_t)WAVE - REFILL_IDLE : 0u;
-        while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-            if (busy) {
-                const bool d = job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J);
-                busy = !d;
-                fin = d;
+        if (MODE == MODE_GRAD) {
+            while ((uint32_t)__popcll(__ballot(busy)) > keep) {
+                if (busy) {
+                    const bool d = job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J);
+                    busy = !d;
+                    fin = d;
+                }
+                if (busy) {
+                    const bool d = job_step<Real, MODE, TALLY, 1>(A, mask, lds_grad, J);
+                    busy = !d;
+                    fin = d;
+                }
             }
-            if (busy) {
-                const bool d = job_step<Real, MODE, TALLY, 1>(A, mask, lds_grad, J);
-                busy = !d;
-                fin = d;
+        } else {
+            while ((uint32_t)__popcll(__ballot(busy)) > keep) {
+                const bool d0 = job_step3<Real, 0>(A, mask, J, busy);
+                fin = fin || (busy && d0);
+                busy = busy && !d0;
+                const bool d1 = job_step3<Real, 1>(A, mask, J, busy);
+                fin = fin || (busy && d1);
+                busy = busy && !d1;
+                const bool d2 = job_step3<Real, 2>(A, mask, J, busy);
+                fin = fin || (busy && d2);
+                busy = busy && !d2;
             }
         }
     }
@@ -781,7 +846,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     JobQueue<Real, MODE>& Q = s_q[threadIdx.x / WAVE];
 
     Photon<Real> ph;
-    Job<Real> J;
+    Job<Real> J{};
     bool alive = false, exhausted = false, busy = false, fin = false;
     uint64_t pool_next = 0, pool_end = 0;
     uint32_t qhead = 0, qtail = 0;
