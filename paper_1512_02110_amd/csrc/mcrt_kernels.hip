@@ -572,29 +572,40 @@ struct Job {
 // Step n (n mod 3 = PH) of a walk without a second phase; returns true when
 // the ray is done.  The whole wavefront steps together (no branch around
 // the step, so that the compiler can count the fetches in flight and wait
-// for the oldest only): a lane whose ray is done (act false) keeps stepping
-// with its end clipped to where it stopped, i.e. with zero lengths and
-// fetches of the shared zero word, which adds its two pending terms in
-// order and nothing else.
+// for the oldest only): a lane whose ray is done keeps stepping with its end
+// clipped to where it stopped, i.e. with zero lengths and fetches of the
+// shared zero word, which adds its two pending terms and nothing else.
+// Exactly one axis crosses, so the index moves by one of kx, ky, kz; the
+// occupancy bit of run c = k >> msh is bit c mod 32 of word k >> (msh + 5)
+// (the bit-field extract reads the low 5 bits of its offset).
 template <typename Real, int PH>
-__device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J, bool act) {
+__device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* mask, uint32_t msh5, Job<Real>& J) {
     Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
     Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
     Real& Ln = PH == 0 ? J.L0 : (PH == 1 ? J.L1 : J.L2);  // slot n
-    bool cx, cy, cz;
-    const Real tn = conn_next(J.W, cx, cy, cz);
+    ConnWalk<Real>& W = J.W;
+    const bool cx = (W.tx <= W.ty) && (W.tx <= W.tz);
+    const bool cy = !cx && (W.ty <= W.tz);
+    const Real tn = fmin(W.tx, fmin(W.ty, W.tz));
     const bool last = tn >= J.r;
     const Real tend = last ? J.r : tn;
     J.tau += (double)bo * (double)Lo;
-    Ln = tend - J.W.t;
-    J.steps += act ? 1u : 0u;
-    conn_cross(J.W, tend, cx, cy, cz);
-    const bool done = last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
+    Ln = tend - W.t;
+    W.t = tend;
+    const int kx = W.kx, ky = W.ky, kz = W.kz;  // values: a select of fields would select addresses
+    W.k += cx ? kx : (cy ? ky : kz);
+    W.rx += cx ? W.sfx : (Real)0;
+    W.ry += cy ? W.sfy : (Real)0;
+    W.rz += (!cx && !cy) ? W.sfz : (Real)0;
+    W.tx = W.rx * W.gx;
+    W.ty = W.ry * W.gy;
+    W.tz = W.rz * W.gz;
+    const bool done = last || (uint32_t)W.k >= (uint32_t)A.n_vox;
     J.r = done ? tend : J.r;
     // branch free: voxel 0 is a valid index to test when the ray is done
-    const int kk = done ? 0 : J.W.k;
-    const bool none = (int)done | (int)!occupied(A, mask, kk);
-    bo = A.beta[none ? (uint32_t)A.n_vox : (uint32_t)kk];
+    const uint32_t kk = done ? 0u : (uint32_t)W.k;
+    const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> A.msh, 1u) != 0u;
+    bo = A.beta[(done || !occ) ? (uint32_t)A.n_vox : kk];
     return done;
 }
 
@@ -656,22 +667,15 @@ template <typename Real, int MODE, int TALLY>
 __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J,
                                            uint64_t& vconn, bool& rec) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
-    vconn += J.steps;
     if (MODE == MODE_GRAD) {
+        vconn += J.steps;
         J.tau += ((double)J.b0 + (double)J.b1) * (double)J.lp;  // the last voxel
     } else {
-        // the voxels still pending when the walk ended in step n = steps - 1:
-        // n - 1 and n, in this order (a slot added since holds a zero fetch
-        // or a zero length)
-        const uint32_t n = J.steps + 2u;  // n + 3, kept non-negative
-        const uint32_t s1 = (n - 1u) % 3u, s2 = n % 3u;
-        const Real b0 = J.b0, b1 = J.b1, b2 = J.b2, L0 = J.L0, L1 = J.L1, L2 = J.L2;
-        const Real bs1 = s1 == 0u ? b0 : (s1 == 1u ? b1 : b2);
-        const Real Ls1 = s1 == 0u ? L0 : (s1 == 1u ? L1 : L2);
-        const Real bs2 = s2 == 0u ? b0 : (s2 == 1u ? b1 : b2);
-        const Real Ls2 = s2 == 0u ? L0 : (s2 == 1u ? L1 : L2);
-        J.tau += (double)bs1 * (double)Ls1;
-        J.tau += (double)bs2 * (double)Ls2;
+        // the two voxels still pending (the other slots hold a zero fetch or
+        // a zero length)
+        J.tau += (double)J.b0 * (double)J.L0;
+        J.tau += (double)J.b1 * (double)J.L1;
+        J.tau += (double)J.b2 * (double)J.L2;
     }
     const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
     if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
@@ -730,8 +734,8 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>
 template <typename Real, int MODE, int TALLY>
 __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
                                       JobQueue<Real, MODE>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
-                                      bool& fin, bool final_pass, uint64_t& vconn, uint32_t& w_used,
-                                      uint32_t w_first) {
+                                      bool& fin, bool final_pass, uint64_t& vconn, uint64_t& vconn_w,
+                                      uint32_t& w_used, uint32_t w_first) {
     for (;;) {
         bool rec = false;
         if (fin) {
@@ -788,17 +792,27 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
                 }
             }
         } else {
-            while ((uint32_t)__popcll(__ballot(busy)) > keep) {
-                const bool d0 = job_step3<Real, 0>(A, mask, J, busy);
-                fin = fin || (busy && d0);
-                busy = busy && !d0;
-                const bool d1 = job_step3<Real, 1>(A, mask, J, busy);
-                fin = fin || (busy && d1);
-                busy = busy && !d1;
-                const bool d2 = job_step3<Real, 2>(A, mask, J, busy);
-                fin = fin || (busy && d2);
-                busy = busy && !d2;
+            // voxel steps are counted per wavefront: the busy lanes of each step
+            const uint32_t msh5 = (uint32_t)A.msh + 5u;
+            bool b = busy, f = fin;  // (local copies stay lane masks)
+            for (;;) {
+                const uint32_t n0 = (uint32_t)__popcll(__ballot(b));
+                if (n0 <= keep) break;
+                const bool d0 = job_step3<Real, 0>(A, mask, msh5, J);
+                f = f || (b && d0);
+                b = b && !d0;
+                const uint32_t n1 = (uint32_t)__popcll(__ballot(b));
+                const bool d1 = job_step3<Real, 1>(A, mask, msh5, J);
+                f = f || (b && d1);
+                b = b && !d1;
+                const uint32_t n2 = (uint32_t)__popcll(__ballot(b));
+                const bool d2 = job_step3<Real, 2>(A, mask, msh5, J);
+                f = f || (b && d2);
+                b = b && !d2;
+                vconn_w += n0 + n1 + n2;
             }
+            busy = b;
+            fin = f;
         }
     }
 }
@@ -852,6 +866,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     uint32_t qhead = 0, qtail = 0;
     uint32_t n_ev = 0, n_le = 0;
     uint64_t vfree = 0, vconn = 0;
+    uint64_t vconn_w = 0;  // counted per wavefront (the same in every lane)
     const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
     const uint32_t w_first = MODE == MODE_TAPE || MODE == MODE_RTAPE ? wave_id * A.tp.rw : 0u;
     uint32_t w_used = 0;
@@ -916,7 +931,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, w_used, w_first);
+                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
             }
         }
         if (collided) {
@@ -926,9 +941,9 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, w_used, w_first);
+        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
     }
-    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, w_used, w_first);
+    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used, w_first);
 
     if ((MODE == MODE_TAPE || MODE == MODE_RTAPE) && __lane_id() == 0) {
         A.tp.wave_count[wave_id] = w_used;
@@ -937,6 +952,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
     if (n_le) atomicAdd(&s_st[ST_LE], (unsigned long long)n_le);
     if (vfree) atomicAdd(&s_st[ST_VFREE], (unsigned long long)vfree);
+    if (__lane_id() == 0) vconn += vconn_w;
     if (vconn) atomicAdd(&s_st[ST_VCONN], (unsigned long long)vconn);
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
