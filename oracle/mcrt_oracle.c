@@ -116,6 +116,37 @@ double oracle_hg_sample(double g, double u)
     return mu;
 }
 
+/* Rayleigh phase function, Eq. (Pray), and the inverse-transform sampling of
+ * its polar cosine, Eq. (thetaREY): mu = gamma^(1/3) - gamma^(-1/3) with
+ * gamma = 4u - 2 + sqrt((4u - 2)^2 + 1), the real root of the CDF
+ * (mu^3 + 3 mu + 4) / 8 = u. */
+double oracle_rayleigh_phase(double c)
+{
+    return 3.0 / (16.0 * ORC_PI) * (1.0 + c * c);
+}
+
+double oracle_rayleigh_sample(double u)
+{
+    double a = 4.0 * u - 2.0;
+    double gam = a + sqrt(a * a + 1.0);
+    double cg = cbrt(gam);
+    double mu = cg - 1.0 / cg;
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    return mu;
+}
+
+/* Particle-type draw at collision s of photon pid (air + aerosol mixture,
+ * step iv): first word of counter (pid_lo, pid_hi, s, 1). */
+static double draw_type(uint64_t seed, uint64_t pid, uint32_t s)
+{
+    uint32_t ctr[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), s, 1u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    oracle_philox4x32_10(ctr, key, r);
+    return oracle_uniform(r[0]);
+}
+
 /* New direction at polar cosine mu and azimuth phi about w_in (step vi). */
 void oracle_scatter_direction(const double w[3], double mu, double phi, double out[3])
 {
@@ -244,6 +275,16 @@ typedef struct {
     const double* dl;
     double* grad;
     double* Lc;             /* voxel model: [camera][voxel] scattered power */
+    /* air + aerosol mixture (beta_t = beta_le = beta_air + beta_aer) */
+    const double* beta_air; /* NULL: one constituent (aerosol) */
+    const double* beta_aer; /* sigma * the aerosol field of the reference channel */
+    double sig;             /* sigma: d beta_aer / d (reference aerosol field) */
+    int air;                /* particle of the current collision: 1 air, 0 aerosol */
+    int full;               /* full gradient: 1 summing replay, 2 depositing replay */
+    double asum;            /* summing replay: sum of a over the photon's estimates */
+    int any_a;              /* summing replay: some a != 0 */
+    double ev_a;            /* depositing replay: sum of a over the current collision */
+    double ff_dep;          /* depositing replay: free-flight deposit weight */
     orc_stats st;
     /* trace */
     orc_path* path;
@@ -265,18 +306,21 @@ static int free_flight(ctx* c, double X[3], int vox[3], const double w[3], doubl
     walker_init(&wk, &c->G, X, w, vox);
     double tau = 0.0;
     for (;;) {
-        double b = c->beta_t[vox_index(&c->G, wk.i)];
+        int64_t k = vox_index(&c->G, wk.i);
+        double b = c->beta_t[k];
         c->st.vox_free++;
         int a = walker_axis(&wk);
         double seg = wk.tmax[a] - wk.t;
         if (b > 0.0 && tau + b * seg >= tau_star) {
             double tc = wk.t + (tau_star - tau) / b;
+            if (c->ff_dep != 0.0) c->grad[k] -= c->ff_dep * (tc - wk.t);
             for (int q = 0; q < 3; ++q) {
                 X[q] = wk.o[q] + tc * wk.w[q];
                 vox[q] = wk.i[q];
             }
             return LEFT_NONE;
         }
+        if (c->ff_dep != 0.0) c->grad[k] -= c->ff_dep * seg;
         tau += b * seg;
         int left = walker_cross(&wk, &c->G, a);
         if (left != LEFT_NONE) {
@@ -361,13 +405,27 @@ static void local_estimates(ctx* c, const double X[3], const int vox[3], const d
             continue;
         }
         double tau = connection_tau(c, c->beta_le, X, vox, vh, r, 0.0, 1);
-        double C = P->albedo * weight * oracle_hg_phase(P->g, cosang) * exp(-tau) / r2;
+        /* Eq. (fle) with the albedo and phase function of the particle */
+        double C = c->air ? weight * oracle_rayleigh_phase(cosang) * exp(-tau) / r2
+                          : P->albedo * weight * oracle_hg_phase(P->g, cosang) * exp(-tau) / r2;
         if (c->mode == MODE_FROZEN) C *= c->beta_le[ke] / c->beta_t[ke];
-        if (c->mode == MODE_GRAD) {
+        if (c->mode == MODE_GRAD && c->full == 1) {
+            double a = c->dl[p] * c->norm[p] * C;
+            c->asum += a;
+            if (a != 0.0) c->any_a = 1;
+        } else if (c->mode == MODE_GRAD && c->full == 2) {
+            double a = c->dl[p] * c->norm[p] * C;
+            c->ev_a += a;
+            if (a != 0.0) connection_tau(c, c->beta_le, X, vox, vh, r, c->sig * a, 0);
+        } else if (c->mode == MODE_GRAD) {
             double a = c->dl[p] * c->norm[p] * C;
             if (a != 0.0) {
-                c->grad[ke] += a / c->beta_t[ke];
-                connection_tau(c, c->beta_le, X, vox, vh, r, a, 0);
+                if (!c->beta_air) {
+                    c->grad[ke] += a / c->beta_t[ke];
+                } else if (!c->air) {
+                    c->grad[ke] += c->sig * a / c->beta_aer[ke];
+                }
+                connection_tau(c, c->beta_le, X, vox, vh, r, c->beta_air ? c->sig * a : a, 0);
             }
         } else {
             tally(c, p, C);
@@ -441,19 +499,31 @@ static int trace_photon(ctx* c, uint64_t pid)
             e->voxel = (int32_t)vox_index(&c->G, vox);
             e->pad_ = 0;
         }
+        /* (iv) the particle: air with probability beta_air / beta in the
+         * collision voxel (mixture only) */
+        int64_t kc = vox_index(&c->G, vox);
+        c->air = c->beta_air ? draw_type(P->seed, pid, s) < c->beta_air[kc] / c->beta_t[kc] : 0;
         /* Sec. 2.1.3: local estimate with the incoming ray and I_s (or, for
          * the voxelised model of Sec. 3, the scattered power per voxel) */
+        c->ev_a = 0.0;
         if (c->mode == MODE_VOXEL)
             voxel_tally(c, X, vox, w, weight);
         else
             local_estimates(c, X, vox, w, weight);
+        if (c->full == 2) {
+            /* score of collision s: the estimates of this and every later
+             * collision (ff_dep / sig), over the aerosol extinction of an
+             * aerosol collision; then the later ones only */
+            if (!c->air && c->ff_dep != 0.0) c->grad[kc] += c->ff_dep / c->beta_aer[kc];
+            c->ff_dep -= c->sig * c->ev_a;
+        }
         if (s >= P->max_events) {
             c->st.capped++;
             return ORC_FATE_CAP;
         }
         draw(P->seed, pid, s, u);
-        /* (v) albedo and Russian roulette */
-        weight *= P->albedo;
+        /* (v) albedo (1 for air) and Russian roulette */
+        if (!c->air) weight *= P->albedo;
         if (weight < P->rr_weight) {
             if (u[2] < weight / P->rr_weight) {
                 weight = P->rr_weight;
@@ -462,8 +532,8 @@ static int trace_photon(ctx* c, uint64_t pid)
                 return ORC_FATE_RR;
             }
         }
-        /* (vi) scattering angle, Eq. (thetaHG), and uniform azimuth */
-        double mu = oracle_hg_sample(P->g, u[0]);
+        /* (vi) scattering angle, Eq. (thetaHG) or (thetaREY), and uniform azimuth */
+        double mu = c->air ? oracle_rayleigh_sample(u[0]) : oracle_hg_sample(P->g, u[0]);
         double phi = 2.0 * ORC_PI * u[1];
         double wn[3];
         oracle_scatter_direction(w, mu, phi, wn);
@@ -622,6 +692,128 @@ int oracle_grad_beta(const orc_grid* grid, const double* beta, int n_cams, const
     if (stats) *stats = c.st;
     ctx_free(&c);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Air + aerosol mixture (step iv, Eqs. Pray, thetaREY, channelBeta).       */
+/* Channel extinction beta = beta_air + sigma * beta_aer_ref, sigma the     */
+/* aerosol cross-section of the channel over that of the reference channel. */
+
+typedef struct {
+    double* aer;  /* sigma * beta_aer_ref */
+    double* tot;  /* beta_air + aer */
+} mix_fields;
+
+static int mix_setup(const orc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                     mix_fields* F)
+{
+    F->aer = F->tot = NULL;
+    if (!grid || !beta_air || !beta_aer || !(sigma > 0.0) || !isfinite(sigma)) return ORC_ERR_INVALID_ARG;
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return ORC_ERR_INVALID_ARG;
+    int64_t nv = (int64_t)grid->nx * grid->ny * grid->nz;
+    F->aer = (double*)malloc((size_t)nv * sizeof(double));
+    F->tot = (double*)malloc((size_t)nv * sizeof(double));
+    for (int64_t k = 0; k < nv; ++k) {
+        if (!(beta_air[k] >= 0.0) || !isfinite(beta_air[k]) || !(beta_aer[k] >= 0.0) || !isfinite(beta_aer[k])) {
+            free(F->aer);
+            free(F->tot);
+            F->aer = F->tot = NULL;
+            return ORC_ERR_INVALID_ARG;
+        }
+        F->aer[k] = sigma * beta_aer[k];
+        F->tot[k] = beta_air[k] + F->aer[k];
+    }
+    return ORC_OK;
+}
+
+int oracle_render_mix(const orc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                      int n_cams, const orc_camera* cams, const orc_params* P, double* images,
+                      double* images_m2, orc_stats* stats)
+{
+    mix_fields F;
+    int err = mix_setup(grid, beta_air, beta_aer, sigma, &F);
+    if (err) return err;
+    err = validate(grid, F.tot, n_cams, cams, P);
+    if (!err && !images) err = ORC_ERR_INVALID_ARG;
+    if (!err) {
+        ctx c;
+        ctx_setup(&c, grid, F.tot, F.tot, n_cams, cams, P, MODE_RENDER);
+        c.beta_air = beta_air;
+        c.beta_aer = F.aer;
+        c.sig = sigma;
+        c.raw = images;
+        memset(images, 0, (size_t)c.n_pix * sizeof(double));
+        if (images_m2) {
+            c.m2 = images_m2;
+            memset(images_m2, 0, (size_t)c.n_pix * sizeof(double));
+            c.acc = (double*)calloc((size_t)c.n_pix, sizeof(double));
+        }
+        run_photons(&c);
+        for (int64_t p = 0; p < c.n_pix; ++p) images[p] *= c.norm[p];
+        if (stats) *stats = c.st;
+        ctx_free(&c);
+    }
+    free(F.aer);
+    free(F.tot);
+    return err;
+}
+
+/* Gradient of the loss with respect to the reference aerosol field, added
+ * to grad.  For a local estimate C_e = a_e / (dl norm) from collision e of a
+ * photon whose collisions are s = 1..n (free-flight legs l_s, particles t_s):
+ *  - surrogate (full = 0), Sec. 5.2 with the in-scatter field frozen:
+ *      a_e (delta(m,k_e) [t_e aerosol] / beta_aer(k_e) - l_e^conn(m));
+ *  - full (full = 1): the derivative of the expected image, the path
+ *    probability differentiated as well (score of every collision):
+ *      sum_s A_s ([t_s aerosol] delta(m,k_s) / beta_aer(k_s) - l_s(m))
+ *        - sum_e a_e l_e^conn(m),   A_s = sum over collisions e >= s of a_e,
+ *    computed by replaying each photon twice: once for the sum of its a,
+ *    once depositing with A_s = that sum minus the estimates before s.
+ * Both are times sigma (chain rule to the reference field). */
+int oracle_grad_mix(const orc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                    int n_cams, const orc_camera* cams, const orc_params* P, const double* dl, int full,
+                    double* grad, orc_stats* stats)
+{
+    mix_fields F;
+    int err = mix_setup(grid, beta_air, beta_aer, sigma, &F);
+    if (err) return err;
+    err = validate(grid, F.tot, n_cams, cams, P);
+    if (!err && (!dl || !grad)) err = ORC_ERR_INVALID_ARG;
+    if (!err) {
+        ctx c;
+        ctx_setup(&c, grid, F.tot, F.tot, n_cams, cams, P, MODE_GRAD);
+        c.beta_air = beta_air;
+        c.beta_aer = F.aer;
+        c.sig = sigma;
+        c.dl = dl;
+        c.grad = grad;
+        for (uint64_t n = 0; n < P->n_photons; ++n) {
+            uint64_t pid = P->photon_offset + n;
+            if (!full) {
+                trace_photon(&c, pid);
+            } else {
+                c.full = 1;
+                c.asum = 0.0;
+                c.any_a = 0;
+                c.ff_dep = 0.0;
+                trace_photon(&c, pid);
+                if (c.any_a) {
+                    orc_stats keep = c.st;
+                    c.full = 2;
+                    c.ff_dep = sigma * c.asum;
+                    trace_photon(&c, pid);
+                    c.st = keep;
+                    c.ff_dep = 0.0;
+                }
+            }
+            c.st.photons++;
+        }
+        if (stats) *stats = c.st;
+        ctx_free(&c);
+    }
+    free(F.aer);
+    free(F.tot);
+    return err;
 }
 
 int oracle_trace_paths(const orc_grid* grid, const double* beta, int n_cams, const orc_camera* cams,

@@ -162,6 +162,28 @@ int oracle_bmc_render(const orc_grid* grid, const double* beta, int n_cams, cons
                       const orc_params* prm, uint32_t n_pp, double* images, double* images_m2,
                       orc_stats* stats);
 
+/* Air + aerosol mixture (step iv; Eqs. Pray, thetaREY, channelBeta).  The
+ * channel's extinction is beta_air + sigma * beta_aer (beta_aer: aerosol
+ * field of the reference channel, sigma > 0 the ratio of the channel's
+ * aerosol cross-section to the reference one); prm->albedo and prm->g are
+ * the aerosol's, air scatters with albedo 1 and the Rayleigh phase function.
+ * At each collision the particle is air with probability beta_air / beta in
+ * the voxel (first word of Philox counter (pid_lo, pid_hi, s, 1)); the local
+ * estimate and the scattering use that particle.  With beta_air = 0 this is
+ * oracle_render on sigma * beta_aer.
+ * oracle_grad_mix ADDS dL/d beta_aer (reference field) to grad: the
+ * surrogate with the in-scatter field frozen (full = 0) or the full
+ * derivative of the expected images, path probabilities included (full = 1);
+ * see the source. */
+int oracle_render_mix(const orc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                      int n_cams, const orc_camera* cams, const orc_params* prm, double* images,
+                      double* images_m2, orc_stats* stats);
+int oracle_grad_mix(const orc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                    int n_cams, const orc_camera* cams, const orc_params* prm, const double* dl_dimages,
+                    int full, double* grad, orc_stats* stats);
+double oracle_rayleigh_phase(double cos_angle);
+double oracle_rayleigh_sample(double u);
+
 int oracle_voxel_conditioning(const orc_grid* grid, int n_cams, const orc_camera* cams, int n,
                               double* counts, double* q);
 double oracle_laplacian_reg(const orc_grid* grid, const double* beta, const double* w_layer, double* grad);

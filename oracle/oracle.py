@@ -129,6 +129,16 @@ def lib():
         L.oracle_bmc_render.argtypes = [C.POINTER(Grid), dp, C.c_int, C.POINTER(Cam), C.POINTER(Params),
                                         C.c_uint32, dp, dp, C.POINTER(Stats)]
         L.oracle_bmc_render.restype = C.c_int
+        L.oracle_render_mix.argtypes = [C.POINTER(Grid), dp, dp, C.c_double, C.c_int, C.POINTER(Cam),
+                                        C.POINTER(Params), dp, dp, C.POINTER(Stats)]
+        L.oracle_render_mix.restype = C.c_int
+        L.oracle_grad_mix.argtypes = [C.POINTER(Grid), dp, dp, C.c_double, C.c_int, C.POINTER(Cam),
+                                      C.POINTER(Params), dp, C.c_int, dp, C.POINTER(Stats)]
+        L.oracle_grad_mix.restype = C.c_int
+        L.oracle_rayleigh_phase.argtypes = [C.c_double]
+        L.oracle_rayleigh_phase.restype = C.c_double
+        L.oracle_rayleigh_sample.argtypes = [C.c_double]
+        L.oracle_rayleigh_sample.restype = C.c_double
         for f in ("oracle_voxel_scatter", "oracle_voxel_transmittance", "oracle_voxel_render",
                   "oracle_voxel_grad"):
             getattr(L, f).restype = C.c_int
@@ -222,6 +232,47 @@ def grad_beta(s, dl_dimages, beta=None, **kw):
     if rc != 0:
         raise OracleError(f"oracle_grad_beta failed: {rc}")
     return grad, st.as_dict()
+
+
+def render_mix(s, beta_air, beta_aer, sigma=1.0, with_m2=False, **kw):
+    """Air + aerosol mixture render of one channel: extinction beta_air +
+    sigma * beta_aer, the scene's albedo and g for the aerosol.  Returns
+    (images_flat, stats_dict[, m2_flat])."""
+    ba, bs = _beta(s, beta_air), _beta(s, beta_aer)
+    img = np.zeros(_n_pix(s.cameras))
+    m2 = np.zeros_like(img) if with_m2 else None
+    st = Stats()
+    rc = lib().oracle_render_mix(C.byref(make_grid(s)), _dptr(ba), _dptr(bs), float(sigma), len(s.cameras),
+                                 make_cams(s.cameras), C.byref(make_params(s, **kw)), _dptr(img),
+                                 _dptr(m2) if with_m2 else None, C.byref(st))
+    if rc != 0:
+        raise OracleError(f"oracle_render_mix failed: {rc}")
+    return (img, st.as_dict(), m2) if with_m2 else (img, st.as_dict())
+
+
+def grad_mix(s, dl_dimages, beta_air, beta_aer, sigma=1.0, full=False, grad=None, **kw):
+    """dL/d beta_aer of the mixture (surrogate, or full with path scores),
+    added to grad (a new zero array when None).  Returns (grad, stats)."""
+    ba, bs = _beta(s, beta_air), _beta(s, beta_aer)
+    dl = np.ascontiguousarray(dl_dimages, dtype=np.float64).reshape(-1)
+    if dl.size != _n_pix(s.cameras):
+        raise ValueError("dl_dimages size mismatch")
+    g = np.zeros(ba.size) if grad is None else grad
+    st = Stats()
+    rc = lib().oracle_grad_mix(C.byref(make_grid(s)), _dptr(ba), _dptr(bs), float(sigma), len(s.cameras),
+                               make_cams(s.cameras), C.byref(make_params(s, **kw)), _dptr(dl), int(bool(full)),
+                               _dptr(g), C.byref(st))
+    if rc != 0:
+        raise OracleError(f"oracle_grad_mix failed: {rc}")
+    return g, st.as_dict()
+
+
+def rayleigh_phase(cos_angle):
+    return lib().oracle_rayleigh_phase(float(cos_angle))
+
+
+def rayleigh_sample(u):
+    return lib().oracle_rayleigh_sample(float(u))
 
 
 def trace_paths(s, first_pid, count, max_rec, beta=None, with_pix=True, **kw):

@@ -112,12 +112,20 @@ def _break_planes(s, to_sun):
     return planes
 
 
-def single_scatter_image(s, cam, n_sub=16, n_gl=4, uniform=False):
+def rayleigh(c):
+    """Eq. (Pray)."""
+    return 3.0 / (16.0 * math.pi) * (1.0 + c * c)
+
+
+def single_scatter_image(s, cam, n_sub=16, n_gl=4, uniform=False, mix=None):
     """Pixel-averaged single-scatter radiance per unit solar irradiance,
     Eq. (IRTE) with J = albedo P exp(-tau_sun) (Eq. (JEq) for the direct
     beam), by quadrature: sub-pixel directions, then along each line of sight
     Gauss-Legendre on pieces where the integrand is smooth.  Points whose sun
-    path leaves through a side face are unlit (light enters at the top)."""
+    path leaves through a side face are unlit (light enters at the top).
+    mix = (beta_air, beta_aer), flat fields summing to s.beta: the source per
+    unit length is then beta_air P_Ray + albedo beta_aer P_HG (air scatters
+    with albedo 1)."""
     L = np.array([s.nx * s.dx, s.ny * s.dy, s.nz * s.dz])
     w_sun = sun_direction(s)
     to_sun = -w_sun
@@ -163,8 +171,16 @@ def single_scatter_image(s, cam, n_sub=16, n_gl=4, uniform=False):
                 flat = X.reshape(-1, 3)
                 tau_sun, ex = _exact_tau_along(s, flat, to_sun)
                 lit = np.abs(ex[:, 2] - L[2]) < 1e-9
-                f = (bseg[:, None] * np.exp(-tau_cam)
+                cs = float(w_sun @ -dvec)
+                if mix is None:
+                    src = bseg * s.albedo * hg(s.g, cs)
+                else:
+                    mid = (pos + 0.5 * (a_ + b_)[:, None] * dvec)[:, None, :]
+                    b_air = beta_lookup(s.with_beta(mix[0]), mid)[:, 0]
+                    b_aer = beta_lookup(s.with_beta(mix[1]), mid)[:, 0]
+                    src = b_air * rayleigh(cs) + s.albedo * b_aer * hg(s.g, cs)
+                f = (src[:, None] * np.exp(-tau_cam)
                      * (np.exp(-tau_sun) * lit).reshape(tn.shape))
-                acc += wt * s.albedo * hg(s.g, float(w_sun @ -dvec)) * (f * wn).sum()
+                acc += wt * (f * wn).sum()
             out[row * cam.width + col] = acc / wts.sum()
     return out
