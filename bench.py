@@ -174,6 +174,51 @@ def bmc(M, torch, np, stream, s, n_per_pixel=64):
             "vox_free_per_s": st["vox_free"] / (t / 1e3)}
 
 
+# Air + aerosol channels (synthetic): Rayleigh extinction at the floor
+# ~ lambda^-4 (650, 550, 450 nm; km^-1), an air scale height of 8 km, and
+# aerosol cross-sections relative to green with an Angstrom exponent of 1.3.
+RGB_AIR_KM = (0.0059, 0.0116, 0.0259)
+RGB_SIGMA = (0.80, 1.0, 1.30)
+
+
+def mixture(M, torch, np, stream, s, n_grad=1_000_000):
+    """Air + aerosol mixture (step iv; Eqs. Pray, thetaREY, channelBeta) on the
+    same grid and cameras: the cloud is the green aerosol field, air falls off
+    with height; one RGB render (FP32 transport, the workload's photons per
+    channel) and the full and surrogate gradients of one channel at n_grad
+    photons; warm-up, then one timed call of each."""
+    z = (np.arange(s.nz) + 0.5) * s.dz
+    airs = [torch.as_tensor(np.ascontiguousarray(np.broadcast_to(
+        (b * np.exp(-z / 8.0))[:, None, None], (s.nz, s.ny, s.nx)).reshape(-1)), dtype=torch.float64,
+        device="cuda") for b in RGB_AIR_KM]
+    aer = torch.as_tensor(s.beta, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    M.mc_render_mixture(s, airs[1], aer, 1.0, n_photons=min(s.n_photons, 1_000_000), stats=False)
+    rgb, t_rgb = timed(lambda: M.mc_render_rgb(s, airs, aer, RGB_SIGMA))
+    events = sum(st["events"] for _, st in rgb)
+    dl = torch.ones(M.n_pixels(s), dtype=torch.float64, device="cuda")
+    out = {"workload": f"same grid and cameras, RGB: air {RGB_AIR_KM} km^-1 at the floor, aerosol ratios "
+                       f"{RGB_SIGMA}; {s.n_photons:.0e} photons per channel, FP32 transport",
+           "rgb_render_ms": round(t_rgb, 3), "events_per_s": events / (t_rgb / 1e3),
+           "events": events}
+    for full in (True, False):
+        M.mc_grad_mixture(s, airs[1], aer, dl, 1.0, full=full, n_photons=n_grad // 10, stats=False)
+        (g, st), t_g = timed(lambda: M.mc_grad_mixture(s, airs[1], aer, dl, 1.0, full=full, n_photons=n_grad))
+        key = "grad_full" if full else "grad_surrogate"
+        out[key + "_ms"] = round(t_g, 3)
+        out[key + "_photons"] = n_grad
+        out[key + "_events_per_s"] = st["events"] / (t_g / 1e3)
+    return out
+
+
 def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=3, n_gd=5, n_side=2):
     """The surrogate recovery loop (Secs. 5.2, 6, 7) on the same grid and
     cameras: measured images of the truth from the voxelised model (seed 99,
@@ -410,6 +455,7 @@ def main():
         out["voxel_model"] = voxel_model(M, torch, np, stream, s)
         out["recovery"] = recovery(M, torch, np, stream, s)
         out["bmc"] = bmc(M, torch, np, stream, s)
+        out["mixture"] = mixture(M, torch, np, stream, s)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

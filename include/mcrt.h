@@ -231,6 +231,50 @@ int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                   const mc_params* params, uint32_t n_per_pixel, double* images, double* images_m2,
                   mc_stats* stats, void* hip_stream);
 
+/* Air + aerosol mixture, one colour channel (Sec. 2.1.2 step iv; Eqs.
+ * (Pray), (thetaREY), (channelBeta)).  The channel's extinction is
+ * beta = beta_air + sigma * beta_aer: beta_air (the known air field of the
+ * channel) and beta_aer (the aerosol field of the reference channel) are
+ * device FP64 arrays of nx*ny*nz values, x fastest, >= 0 (not checked);
+ * sigma > 0 is the ratio of the channel's aerosol cross-section to the
+ * reference one.  params->albedo and params->g describe the aerosol; air
+ * scatters with albedo 1 and the Rayleigh phase function.  At collision s
+ * of photon pid the particle is air when the first uniform of Philox
+ * counter (pid_lo, pid_hi, s, 1) is below beta_air / beta in the collision
+ * voxel (compared in FP64 for either transport precision); the local
+ * estimate (albedo and phase function), the weight update and the sampled
+ * scattering angle (Eq. thetaHG or thetaREY) are those of that particle.
+ * With beta_air = 0 this is mc_render on sigma * beta_aer.  images,
+ * images_m2 (nullable), stats as in mc_render_moments.  An RGB image is three
+ * calls, one per channel (its beta_air and sigma). */
+int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                      int n_cams, const mc_camera* cams, const mc_params* params, double* images, double* images_m2,
+                      mc_stats* stats, void* hip_stream);
+
+/* Gradient of a loss with respect to the reference aerosol field beta_aer
+ * for the render mc_render_mixture makes with the same arguments,
+ * given dL/d images (device FP64, the images' layout), ADDED to
+ * grad_beta_aer (device FP64, nx*ny*nz; zero it first; summing the calls of
+ * the three channels gives the RGB gradient of Eq. (divCost1) for the
+ * image term).  With a_e = dL/di(p) * mu0 A_top / (N Omega_p) * C_e for the
+ * local estimate C_e of collision e (voxel k_e, particle t_e) and its
+ * connection lengths l_e(m):
+ *  full = 0: the surrogate with the in-scatter field frozen (Sec. 5.2):
+ *      sigma * sum_e a_e ([t_e aerosol] delta(m,k_e) / beta_aer,ch(k_e) - l_e(m));
+ *  full = 1: the derivative of the expected images, the probability of
+ *      every photon path differentiated too: per photon, with free-flight
+ *      lengths l_s(m) of the leg ending at collision s and A_s the sum of a
+ *      over its collisions s and later,
+ *      sigma * [sum_s A_s ([t_s aerosol] delta(m,k_s) / beta_aer,ch(k_s) - l_s(m))
+ *               - sum_e a_e l_e(m)],
+ *      by replaying each photon twice (once for the sum of its a).
+ * (beta_aer,ch = sigma * beta_aer.)  One photon per lane with FP64 device
+ * atomics; params->tally is ignored.  stats count the photons' first
+ * replay. */
+int mc_grad_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma, int n_cams,
+                    const mc_camera* cams, const mc_params* params, const double* dl_dimages, int full,
+                    double* grad_beta_aer, mc_stats* stats, void* hip_stream);
+
 /* Voxelised forward model (Sec. 3) and its frozen-j gradient (Sec. 5.2).
  * Arrays "[camera][voxel]" are device arrays of n_cams * nx*ny*nz doubles,
  * camera-major, voxel index fastest.

@@ -123,6 +123,15 @@ struct Scratch {
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// An air + aerosol mixture: device fields of the reference channel and the
+// channel's aerosol cross-section ratio (Eq. channelBeta).
+struct MixIn {
+    const double* air;
+    const double* aer;
+    double sig;
+    int full;  // gradient: 1 full (path scores), 0 surrogate
+};
+
 // Device memory of the library comes from one memory pool per device that
 // keeps what the calls free (release threshold: unlimited), so that the
 // tapes and bins, tens of GB each, are not mapped and unmapped on every
@@ -635,12 +644,12 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
         mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr,
-        uint32_t n_pp = 0) {
+        uint32_t n_pp = 0, const MixIn* mix = nullptr) {
     int rc = MC_OK;
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
     const int tally = prm->tally == MC_TALLY_KAHAN32 ? TALLY_K32 : TALLY_F64;
-    const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE && mode != MODE_VOXEL;
+    const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE && mode != MODE_VOXEL && mode != MODE_MIXGRAD;
 
     // occupancy mask: one bit per run of 2^msh consecutive voxels, the
     // shortest runs whose bits fit the kernels' LDS copy
@@ -653,7 +662,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                    round256(sizeof(Real) * (n_vox + BETA_PAD)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
-    if (mode == MODE_GRAD) bytes += round256(sizeof(double) * n_pix);
+    if (mode == MODE_GRAD || mode == MODE_MIXGRAD) bytes += round256(sizeof(double) * n_pix);
     if (k32 && mode == MODE_RENDER) bytes += round256(sizeof(float) * 2 * n_pix);
     if (k32 && mode == MODE_GRAD) bytes += round256(sizeof(float) * 2 * n_vox);
     if (mode == MODE_BMC) bytes += round256(sizeof(HostCam) * n_cams);
@@ -724,11 +733,20 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
     // the kernels read a copy of beta followed by zeros (an empty voxel
     // fetches beta[n_vox])
-    CHECK_HIP(hipMemcpyAsync(betap, beta, sizeof(Real) * n_vox, hipMemcpyDeviceToDevice, stream));
-    if (sizeof(Real) == 4)
-        CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(betap) + n_vox, BETA_PAD, stream));
-    else
-        CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(betap) + n_vox, BETA_PAD, stream));
+    if (mix) {
+        // a mixture: beta = air + sig * aer
+        CHECK_HIP(launch_mix_total<Real>(betap, mix->air, mix->aer, mix->sig, n_vox, BETA_PAD, stream));
+        A.mix_air = mix->air;
+        A.mix_aer = mix->aer;
+        A.mix_sig = mix->sig;
+        A.mix_full = mix->full;
+    } else {
+        CHECK_HIP(hipMemcpyAsync(betap, beta, sizeof(Real) * n_vox, hipMemcpyDeviceToDevice, stream));
+        if (sizeof(Real) == 4)
+            CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(betap) + n_vox, BETA_PAD, stream));
+        else
+            CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(betap) + n_vox, BETA_PAD, stream));
+    }
 
     A.G.nx = grid->nx;
     A.G.ny = grid->ny;
@@ -850,6 +868,12 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         A.Lc = S.take<double>(n_vox * lc_pitch);
         A.lc_pitch = lc_pitch;
         CHECK_HIP(launch_fill_f64(A.Lc, n_vox * lc_pitch, stream));
+    } else if (mode == MODE_MIXGRAD) {
+        // gradient of a mixture: added to grad
+        double* gw = S.take<double>(n_pix);
+        CHECK_HIP(launch_grad_weights(gw, dl, ncams, n_cams, n_pix, base_norm, stream));
+        A.gw = gw;
+        A.grad = grad;
     } else if (mode == MODE_GRAD) {
         double* gw = S.take<double>(n_pix);
         CHECK_HIP(launch_grad_weights(gw, dl, ncams, n_cams, n_pix, base_norm, stream));
@@ -1260,6 +1284,45 @@ int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                            0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
     return run<float>(MODE_BMC, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0, 0,
                       0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
+}
+
+int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,
+                      int n_cams, const mc_camera* cams, const mc_params* params, double* images, double* images_m2,
+                      mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta_air, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!beta_aer || !images || !(sigma > 0.0) || !std::isfinite(sigma)) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta_air) || !is_device_ptr(beta_aer) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
+    if (images_m2 && !is_device_ptr(images_m2)) return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const MixIn mix{beta_air, beta_aer, sigma, 0};
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_RENDER, grid, beta_air, n_cams, cams, params, images, images_m2, nullptr, nullptr,
+                           stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, &mix);
+    return run<float>(MODE_RENDER, grid, beta_air, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats,
+                      0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, &mix);
+}
+
+int mc_grad_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma, int n_cams,
+                    const mc_camera* cams, const mc_params* params, const double* dl_dimages, int full,
+                    double* grad_beta_aer, mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta_air, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!beta_aer || !dl_dimages || !grad_beta_aer || !(sigma > 0.0) || !std::isfinite(sigma) ||
+        (full != 0 && full != 1))
+        return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta_air) || !is_device_ptr(beta_aer) || !is_device_ptr(dl_dimages) ||
+        !is_device_ptr(grad_beta_aer))
+        return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const MixIn mix{beta_air, beta_aer, sigma, full};
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_MIXGRAD, grid, beta_air, n_cams, cams, params, nullptr, nullptr, dl_dimages,
+                           grad_beta_aer, stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, &mix);
+    return run<float>(MODE_MIXGRAD, grid, beta_air, n_cams, cams, params, nullptr, nullptr, dl_dimages,
+                      grad_beta_aer, stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, &mix);
 }
 
 int mc_voxel_render(const mc_grid* grid, const double* beta, int n_cams, const mc_camera* cams, int rays_per_side,

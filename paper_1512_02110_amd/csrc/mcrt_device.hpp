@@ -55,6 +55,8 @@ __device__ __forceinline__ float m_sqrt_fast(float x) { return __builtin_amdgcn_
 __device__ __forceinline__ double m_sqrt_fast(double x) { return sqrt(x); }
 __device__ __forceinline__ float m_rsqrt(float x) { return 1.0f / sqrtf(x); }
 __device__ __forceinline__ double m_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float m_cbrt(float x) { return cbrtf(x); }
+__device__ __forceinline__ double m_cbrt(double x) { return cbrt(x); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
 __device__ __forceinline__ double m_floor(double x) { return floor(x); }
 __device__ __forceinline__ void m_sincospi(float x, float* s, float* c) { sincospif(x, s, c); }
@@ -64,6 +66,24 @@ __device__ __forceinline__ float m_rcp(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double m_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
+
+// Rayleigh phase function, Eq. (Pray): 3 (1 + cos^2) / (16 pi).
+template <typename Real>
+__device__ __forceinline__ Real rayleigh_phase(Real cosang) {
+    return (Real)0.05968310365946075 * ((Real)1 + cosang * cosang);
+}
+
+// Inverse-transform sample of the Rayleigh polar cosine, Eq. (thetaREY):
+// mu = c - 1/c, c the cube root of gamma = 4u - 2 + sqrt((4u - 2)^2 + 1)
+// (the real root of (mu^3 + 3 mu + 4) / 8 = u).  Returns 1 - mu.
+template <typename Real>
+__device__ __forceinline__ Real rayleigh_one_minus_mu(Real u) {
+    const Real a = (Real)4 * u - (Real)2;
+    const Real c = m_cbrt(a + m_sqrt(a * a + (Real)1));
+    Real omm = (Real)1 - (c - (Real)1 / c);
+    omm = omm < (Real)0 ? (Real)0 : omm;
+    return omm > (Real)2 ? (Real)2 : omm;
+}
 
 // Henyey-Greenstein phase function, Eq. (Phg), as a function of the cosine
 // of the scattering angle.

@@ -16,7 +16,10 @@ namespace mcrt {
 // scattered power per voxel and camera (the voxelised model).
 // MODE_BMC: backward Monte Carlo, packets traced from the camera pixels with
 // the local estimate towards the sun.
-enum { MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4, MODE_VOXEL = 5, MODE_BMC = 6 };
+enum {
+    MODE_RENDER = 0, MODE_GRAD = 1, MODE_TRACE = 2, MODE_TAPE = 3, MODE_RTAPE = 4, MODE_VOXEL = 5, MODE_BMC = 6,
+    MODE_MIXGRAD = 7
+};
 enum { TALLY_F64 = 0, TALLY_K32 = 1 };
 enum {
     ST_PHOTONS = 0, ST_EVENTS, ST_LE, ST_VFREE, ST_VCONN,
@@ -107,6 +110,11 @@ struct KArgs {
     double* grad;               // F64 gradient
     double* Lc;                 // voxel model: [voxel][lc_pitch] scattered power per camera
     int lc_pitch;               // cameras rounded up to a multiple of 8
+    // air + aerosol mixture (render, MODE_MIXGRAD): beta is air + sig * aer
+    const double* mix_air;      // nullptr: one constituent
+    const double* mix_aer;      // aerosol field of the reference channel
+    double mix_sig;             // aerosol cross-section ratio of the channel
+    int mix_full;               // MODE_MIXGRAD: 1 full gradient, 0 surrogate
     const HostCam* hcams;       // backward MC: cameras in double, absolute positions
     uint32_t n_pp;              // backward MC: packets per pixel
     float* grad32;              // [2 n_vox] (K32 gradient)
@@ -167,6 +175,9 @@ hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams
 hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipStream_t s);
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
+template <typename Real>
+hipError_t launch_mix_total(Real* beta, const double* air, const double* aer, double sig, int64_t n, int64_t pad,
+                            hipStream_t s);
 template <typename Real>
 hipError_t launch_bin(const KArgs<Real>& a, bool scatter, hipStream_t s);
 template <typename Real>

@@ -57,6 +57,7 @@ struct Photon {
     Real t_exit;  // ray parameter at which the last flight left the domain
     uint32_t s;   // collisions so far
     uint64_t pid;
+    int air;      // particle of the last collision: 1 air, 0 aerosol (mixture)
 };
 
 // Absolute coordinate (km) of a voxel-local position.
@@ -289,6 +290,7 @@ __device__ __forceinline__ void launch_photon(const KArgs<Real>& A, uint64_t pid
     ph.t_exit = (Real)0;
     ph.s = 0;
     ph.pid = pid;
+    ph.air = 0;
 }
 
 // Steps (ii)-(iii): returns 0 on a collision (position and voxel updated),
@@ -302,9 +304,13 @@ __device__ __forceinline__ void launch_photon(const KArgs<Real>& A, uint64_t pid
 constexpr int FLIGHT_GOES_ON = 4;
 constexpr uint32_t FLIGHT_BUDGET = 32;
 
-template <typename Real>
+//
+// DEP: also subtract dep times the length flown in every voxel from grad
+// (the free-flight score of the full mixture gradient).
+template <typename Real, bool DEP = false>
 __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t* mask, Photon<Real>& ph,
-                                           uint64_t& vfree, uint32_t budget) {
+                                           uint64_t& vfree, uint32_t budget, double dep = 0.0,
+                                           double* grad = nullptr) {
     WalkRegs<Real> W;
     const Real f0x = ph.fx, f0y = ph.fy, f0z = ph.fz;
     const Real wx = ph.wx, wy = ph.wy, wz = ph.wz;
@@ -324,8 +330,10 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
         const Real seg = tn - W.t;
         if (b > (Real)0 && tau + b * seg >= taustar) {
             tc = W.t + (taustar - tau) / b;
+            if (DEP && dep != 0.0) unsafeAtomicAdd(grad + W.k, -dep * (double)(tc - W.t));
             break;
         }
+        if (DEP && dep != 0.0) unsafeAtomicAdd(grad + W.k, -dep * (double)seg);
         tau += b * seg;
         const bool out = walk_cross(W, A.G, tn, cx, cy, cz);
         if (out) {
@@ -361,8 +369,8 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
 template <typename Real>
 __device__ __forceinline__ bool le_geometry(const KArgs<Real>& A, const DevCam<Real>& cam, int ix, int iy, int iz,
                                             Real fx, Real fy, Real fz, Real wx, Real wy, Real wz, Real weight,
-                                            int64_t& pix, int& local_pix, Real& vx, Real& vy, Real& vz, Real& r,
-                                            Real& pre) {
+                                            int air, int64_t& pix, int& local_pix, Real& vx, Real& vy, Real& vz,
+                                            Real& r, Real& pre) {
     // X - X_c from voxel-local parts: the integer differences are exact
     const Real dx = ((Real)(ix - cam.icx) + (fx - cam.fcx)) * A.G.dx;
     const Real dy = ((Real)(iy - cam.icy) + (fy - cam.fcy)) * A.G.dy;
@@ -384,8 +392,24 @@ __device__ __forceinline__ bool le_geometry(const KArgs<Real>& A, const DevCam<R
     vy = -dy * ir;
     vz = -dz * ir;
     const Real cosang = wx * vx + wy * vy + wz * vz;
-    pre = A.albedo * weight * hg_phase(A.g, cosang) / r2;
+    // Eq. (fle) with the albedo and phase function of the particle
+    pre = air ? weight * rayleigh_phase(cosang) / r2 : A.albedo * weight * hg_phase(A.g, cosang) / r2;
     return true;
+}
+
+// Step (iv) in an air + aerosol mixture: the particle at collision s is air
+// with probability beta_air / beta in the collision voxel, from the first
+// word of Philox counter (pid_lo, pid_hi, s, 1).  Decided in FP64 for either
+// transport precision, with beta = air + sig * aer rounded as in the
+// library's copy of beta (no fused multiply-add).
+template <typename Real>
+__device__ __forceinline__ int mix_particle(const KArgs<Real>& A, const Photon<Real>& ph) {
+    const int64_t k = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
+    const double air = A.mix_air[k];
+    const double tot = __dadd_rn(air, __dmul_rn(A.mix_sig, A.mix_aer[k]));
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)ph.pid, (uint32_t)(ph.pid >> 32), ph.s, 1u),
+                                  make_uint2((uint32_t)A.seed, (uint32_t)(A.seed >> 32)));
+    return uniform01<double>(r.x) < air / tot ? 1 : 0;
 }
 
 // Steps (v)-(vi) after collision s: returns -1 while the photon lives, else
@@ -394,7 +418,7 @@ template <typename Real>
 __device__ __forceinline__ int after_collision(const KArgs<Real>& A, Photon<Real>& ph) {
     if (ph.s >= A.max_events) return MC_FATE_CAP;
     const uint4 r = draw(A.seed, ph.pid, ph.s);
-    ph.weight *= A.albedo;
+    if (!ph.air) ph.weight *= A.albedo;  // air: albedo 1
     if (ph.weight < A.rr) {
         if (uniform01<Real>(r.z) < ph.weight / A.rr) {
             ph.weight = A.rr;
@@ -402,7 +426,7 @@ __device__ __forceinline__ int after_collision(const KArgs<Real>& A, Photon<Real
             return MC_FATE_RR;
         }
     }
-    const Real omm = hg_one_minus_mu(A.g, uniform01<Real>(r.x));
+    const Real omm = ph.air ? rayleigh_one_minus_mu(uniform01<Real>(r.x)) : hg_one_minus_mu(A.g, uniform01<Real>(r.x));
     scatter_direction(ph.wx, ph.wy, ph.wz, omm, uniform01<Real>(r.y));
     ph.taustar = -m_log((Real)1 - uniform01<Real>(r.w));
     return -1;
@@ -901,6 +925,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 collided = true;
                 ph.s += 1;
                 ++n_ev;
+                if (A.mix_air) ph.air = mix_particle(A, ph);
             }
         }
         if (MODE == MODE_VOXEL) {
@@ -913,7 +938,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 int lp = 0;
                 Real vx = 0, vy = 0, vz = 0, r = 0, pre = 0;
                 const bool vis = collided && le_geometry(A, cam, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, ph.wx,
-                                                         ph.wy, ph.wz, ph.weight, pix, lp, vx, vy, vz, r, pre);
+                                                         ph.wy, ph.wz, ph.weight, ph.air, pix, lp, vx, vy, vz, r, pre);
                 const unsigned long long m = __ballot(vis);
                 if (vis) {
                     const uint32_t slot = (qtail + lanes_below(m)) & (QCAP - 1);
@@ -1417,7 +1442,7 @@ __global__ void __launch_bounds__(BLOCK) k_trace(KArgs<Real> A) {
                 int lp = -1;
                 Real vx, vy, vz, r, pre;
                 const bool vis = le_geometry(A, A.cams[c], ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, ph.wx, ph.wy,
-                                             ph.wz, ph.weight, pix, lp, vx, vy, vz, r, pre);
+                                             ph.wz, ph.weight, ph.air, pix, lp, vx, vy, vz, r, pre);
                 pix_rec[c] = vis ? lp : -1;
             }
         }
@@ -1566,6 +1591,136 @@ __global__ void __launch_bounds__(BLOCK) k_bmc(KArgs<Real> A) {
     if (vfree) atomicAdd(&s_st[ST_VFREE], (unsigned long long)vfree);
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of an air + aerosol mixture with respect to the reference aerosol
+// field, one photon per lane (both passes of a photon need all of its local
+// estimates, so they are walked where they arise rather than queued).
+
+// Connection ray from (i, f) along unit v over length r (clipped to the
+// domain): returns the optical depth, summed voxel by voxel in FP64; with
+// DEP, subtracts dep * l(m) from grad in every voxel m.  steps counts the
+// voxels visited (one for a walk that cannot start).
+template <typename Real, bool DEP>
+__device__ double mix_conn(const KArgs<Real>& A, int ix, int iy, int iz, Real fx, Real fy, Real fz, Real vx,
+                           Real vy, Real vz, Real r, double dep, uint64_t& steps) {
+    ConnWalk<Real> W;
+    const Real texit = conn_begin(W, A.G, ix, iy, iz, fx, fy, fz, vx, vy, vz);
+    if (texit < (Real)0) {
+        ++steps;
+        return 0.0;
+    }
+    const Real rr = fmin(r, texit);
+    double tau = 0.0;
+    for (;;) {
+        bool cx, cy, cz;
+        const Real tn = conn_next(W, cx, cy, cz);
+        const bool last = tn >= rr;
+        const Real l = (last ? rr : tn) - W.t;
+        ++steps;
+        tau += (double)A.beta[W.k] * (double)l;
+        if (DEP) unsafeAtomicAdd(A.grad + W.k, -dep * (double)l);
+        conn_cross(W, tn, cx, cy, cz);
+        if (last || (uint32_t)W.k >= (uint32_t)A.n_vox) break;
+    }
+    return tau;
+}
+
+// One photon.  PASS 0: surrogate deposits (in-scatter field frozen).  PASS
+// 1: sum of a = dL/di norm C over the photon's estimates (asum; any: some a
+// is not zero).  PASS 2: full-gradient deposits with ffd = sig * A_s, A_s
+// the sum of a over collisions s and later (asum at the start): the
+// free-flight scores -ffd l, at an aerosol collision ffd / beta_aer, the
+// connection terms -sig a l, then A_s minus this collision's a.
+template <typename Real, int PASS>
+__device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double& asum, bool& any,
+                           unsigned long long* s_st, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
+                           uint64_t& vconn) {
+    constexpr bool COUNT = PASS != 2;
+    uint64_t dummy = 0;
+    Photon<Real> ph;
+    launch_photon(A, pid, ph);
+    for (;;) {
+        const int left = free_flight<Real, PASS == 2>(A, (const uint32_t*)nullptr, ph, COUNT ? vfree : dummy,
+                                                      0xffffffffu, ffd, A.grad);
+        if (left) {
+            if (COUNT) atomicAdd(&s_st[ST_TOP + left - 1], 1ull);
+            return;
+        }
+        ph.s += 1;
+        if (COUNT) ++n_ev;
+        ph.air = mix_particle(A, ph);
+        const int64_t ke = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
+        double ev_a = 0.0;
+        for (int c = 0; c < A.n_cams; ++c) {
+            int64_t pix = 0;
+            int lp = 0;
+            Real vx = 0, vy = 0, vz = 0, r = 0, pre = 0;
+            if (!le_geometry(A, A.cams[c], ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, ph.wx, ph.wy, ph.wz, ph.weight,
+                             ph.air, pix, lp, vx, vy, vz, r, pre))
+                continue;
+            if (COUNT) ++n_le;
+            const double tau = mix_conn<Real, false>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, 0.0,
+                                                     COUNT ? vconn : dummy);
+            const double C = (double)pre * (double)m_exp((Real)(-tau));
+            const double a = A.gw[pix] * C;
+            if (PASS == 1) {
+                asum += a;
+                any = any || a != 0.0;
+            } else if (a != 0.0) {
+                if (PASS == 0 && !ph.air) unsafeAtomicAdd(A.grad + ke, A.mix_sig * a / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
+                if (PASS == 2) ev_a += a;
+                mix_conn<Real, true>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, A.mix_sig * a, dummy);
+            }
+        }
+        if (PASS == 2) {
+            if (!ph.air && ffd != 0.0) unsafeAtomicAdd(A.grad + ke, ffd / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
+            ffd -= A.mix_sig * ev_a;
+        }
+        const int fate = after_collision(A, ph);
+        if (fate >= 0) {
+            if (COUNT) atomicAdd(&s_st[fate == MC_FATE_CAP ? ST_CAP : ST_RR], 1ull);
+            return;
+        }
+    }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
+    __shared__ unsigned long long s_st[ST_N];
+    if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
+    __syncthreads();
+    uint64_t n_ev = 0, n_le = 0, vfree = 0, vconn = 0;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_photons;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t pid = A.pid0 + k;
+        double asum = 0.0;
+        bool any = false;
+        if (!A.mix_full) {
+            mix_photon<Real, 0>(A, pid, 0.0, asum, any, s_st, n_ev, n_le, vfree, vconn);
+        } else {
+            mix_photon<Real, 1>(A, pid, 0.0, asum, any, s_st, n_ev, n_le, vfree, vconn);
+            if (any) mix_photon<Real, 2>(A, pid, A.mix_sig * asum, asum, any, s_st, n_ev, n_le, vfree, vconn);
+        }
+    }
+    if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
+    if (n_le) atomicAdd(&s_st[ST_LE], (unsigned long long)n_le);
+    if (vfree) atomicAdd(&s_st[ST_VFREE], (unsigned long long)vfree);
+    if (vconn) atomicAdd(&s_st[ST_VCONN], (unsigned long long)vconn);
+    __syncthreads();
+    if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
+}
+
+// The channel's extinction beta = air + sig * aer (reference aerosol field
+// times the channel's cross-section ratio, Eq. channelBeta) in the kernels'
+// precision, rounded step by step (no fused multiply-add), followed by the
+// zeros of the library's copy.
+template <typename Real>
+__global__ void k_mix_total(Real* beta, const double* air, const double* aer, double sig, int64_t n, int64_t pad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) beta[i] = (Real)__dadd_rn(air[i], __dmul_rn(sig, aer[i]));
+    else if (i < n + pad) beta[i] = (Real)0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1741,6 +1896,10 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
         hipLaunchKernelGGL(k_bmc<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
         return hipGetLastError();
     }
+    if (mode == MODE_MIXGRAD) {
+        hipLaunchKernelGGL(k_mix_grad<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_trace<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
@@ -1762,6 +1921,8 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
                                                       : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
     if (mode == MODE_VOXEL) return occ_r<Real, MODE_VOXEL, TALLY_F64>(a, b);
     if (mode == MODE_BMC) return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_bmc<Real>, BLOCK, 0);
+    if (mode == MODE_MIXGRAD)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_mix_grad<Real>, BLOCK, 0);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_trace<Real>, BLOCK, 0);
 }
 
@@ -1828,6 +1989,19 @@ template hipError_t launch_build_mask<float>(const KArgs<float>&, uint32_t*, hip
 template hipError_t launch_build_mask<double>(const KArgs<double>&, uint32_t*, hipStream_t);
 template hipError_t launch_write_cams<float>(const CamChunk&, DevCam<float>*, NormCam*, hipStream_t);
 template hipError_t launch_write_cams<double>(const CamChunk&, DevCam<double>*, NormCam*, hipStream_t);
+template <typename Real>
+hipError_t launch_mix_total(Real* beta, const double* air, const double* aer, double sig, int64_t n, int64_t pad,
+                            hipStream_t s) {
+    const int64_t m = n + pad;
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mix_total<Real>, dim3(blocks_for(m)), dim3(BLOCK), 0, s, beta, air, aer, sig, n, pad);
+    return hipGetLastError();
+}
+template hipError_t launch_mix_total<float>(float*, const double*, const double*, double, int64_t, int64_t,
+                                            hipStream_t);
+template hipError_t launch_mix_total<double>(double*, const double*, const double*, double, int64_t, int64_t,
+                                             hipStream_t);
+
 template hipError_t launch_transport<float>(const KArgs<float>&, int, int, int, hipStream_t);
 template hipError_t launch_transport<double>(const KArgs<double>&, int, int, int, hipStream_t);
 template hipError_t transport_occupancy<float>(const KArgs<float>&, int, int, int*);

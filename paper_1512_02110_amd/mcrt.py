@@ -88,7 +88,7 @@ EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
            "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
            "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover",
-           "mc_bmc_render"]
+           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture"]
 
 
 class McError(RuntimeError):
@@ -130,6 +130,10 @@ def load_library(path: str = LIB_PATH):
                                     vp, vp]
         L.mc_bmc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.POINTER(McParams),
                                     C.c_uint32, vp, vp, C.POINTER(McStats), vp]
+        L.mc_render_mixture.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, C.c_int, C.POINTER(McCamera),
+                                        C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
+        L.mc_grad_mixture.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, C.c_int, C.POINTER(McCamera),
+                                      C.POINTER(McParams), vp, C.c_int, vp, C.POINTER(McStats), vp]
         L.mc_voxel_conditioning.argtypes = [C.POINTER(McGrid), C.c_int, C.POINTER(McCamera), C.c_int, vp, vp, vp]
         L.mc_regularizer.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, vp, vp, vp]
         L.mc_image_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
@@ -142,7 +146,7 @@ def load_library(path: str = LIB_PATH):
                   "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
                   "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning",
                   "mc_regularizer", "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error",
-                  "mc_recover", "mc_bmc_render"):
+                  "mc_recover", "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -338,6 +342,78 @@ def mc_bmc_render(s, beta, n_per_pixel, transport="fp32", with_m2=False, stats=T
     _check("mc_bmc_render", rc)
     out = (img, _stats(st) if stats else None)
     return out + (m2,) if with_m2 else out
+
+
+def _mix_fields(torch, s, beta_air, beta_aer):
+    for name, t in (("beta_air", beta_air), ("beta_aer", beta_aer)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and t.numel() == s.n_vox):
+            raise ValueError(f"{name} must be a contiguous float64 GPU tensor of {s.n_vox} values")
+
+
+def mc_render_mixture(s, beta_air, beta_aer, sigma=1.0, transport="fp32", with_m2=False, stats=True, stream=None,
+                      **kw):
+    """One channel of the air + aerosol mixture: extinction beta_air + sigma * beta_aer
+    (float64 GPU tensors), the scene's albedo and g for the aerosol, Rayleigh air.
+    Returns (images, stats[, m2])."""
+    torch = _torch()
+    _mix_fields(torch, s, beta_air, beta_aer)
+    n = n_pixels(s)
+    img = torch.empty(n, dtype=torch.float64, device=beta_air.device)
+    m2 = torch.empty(n, dtype=torch.float64, device=beta_air.device) if with_m2 else None
+    st = McStats() if stats else None
+    rc = load_library().mc_render_mixture(C.byref(make_grid(s)), _ptr(beta_air), _ptr(beta_aer), float(sigma),
+                                          len(s.cameras), make_cameras(s.cameras),
+                                          C.byref(make_params(s, transport=transport, **kw)), _ptr(img), _ptr(m2),
+                                          C.byref(st) if stats else None, C.c_void_p(_stream(torch, stream)))
+    _check("mc_render_mixture", rc)
+    out = (img, _stats(st) if stats else None)
+    return out + (m2,) if with_m2 else out
+
+
+def mc_grad_mixture(s, beta_air, beta_aer, dl_dimages, sigma=1.0, full=True, grad=None, transport="fp32",
+                    stats=True, stream=None, **kw):
+    """dL/d beta_aer (reference aerosol field) of the mixture render with the same
+    arguments, ADDED to grad (a new zero tensor when None): the surrogate with the
+    in-scatter field frozen (full=False) or the full derivative with the photon
+    paths' scores (full=True).  Returns (grad, stats)."""
+    torch = _torch()
+    _mix_fields(torch, s, beta_air, beta_aer)
+    n = n_pixels(s)
+    if not (isinstance(dl_dimages, torch.Tensor) and dl_dimages.is_cuda and dl_dimages.dtype == torch.float64
+            and dl_dimages.is_contiguous() and dl_dimages.numel() == n):
+        raise ValueError(f"dl_dimages must be a contiguous float64 GPU tensor of {n} values")
+    g = grad if grad is not None else torch.zeros(s.n_vox, dtype=torch.float64, device=beta_air.device)
+    _mix_fields(torch, s, beta_air, g)
+    st = McStats() if stats else None
+    rc = load_library().mc_grad_mixture(C.byref(make_grid(s)), _ptr(beta_air), _ptr(beta_aer), float(sigma),
+                                        len(s.cameras), make_cameras(s.cameras),
+                                        C.byref(make_params(s, transport=transport, **kw)), _ptr(dl_dimages),
+                                        int(bool(full)), _ptr(g), C.byref(st) if stats else None,
+                                        C.c_void_p(_stream(torch, stream)))
+    _check("mc_grad_mixture", rc)
+    return g, (_stats(st) if stats else None)
+
+
+def mc_render_rgb(s, beta_air_rgb, beta_aer, sigma_rgb, transport="fp32", stream=None, **kw):
+    """RGB images of the mixture (Eq. channelBeta): one mc_render_mixture call per
+    channel with that channel's air field and aerosol cross-section ratio.
+    Returns a list of three (images, stats)."""
+    return [mc_render_mixture(s, beta_air_rgb[c], beta_aer, sigma_rgb[c], transport=transport, stream=stream, **kw)
+            for c in range(3)]
+
+
+def mc_grad_rgb(s, beta_air_rgb, beta_aer, dl_rgb, sigma_rgb, full=True, grad=None, transport="fp32", stream=None,
+                **kw):
+    """Gradient of an RGB image loss with respect to the reference aerosol field
+    (the image term of Eq. divCost1): the three channels' mc_grad_mixture calls
+    added into one tensor.  Returns grad."""
+    torch = _torch()
+    g = grad if grad is not None else torch.zeros(s.n_vox, dtype=torch.float64, device=beta_aer.device)
+    for c in range(3):
+        mc_grad_mixture(s, beta_air_rgb[c], beta_aer, dl_rgb[c], sigma_rgb[c], full=full, grad=g,
+                        transport=transport, stats=False, stream=stream, **kw)
+    return g
 
 
 def mc_voxel_scatter(s, beta, transport="fp32", stats=True, out=None, stream=None, **kw):

@@ -1,0 +1,196 @@
+"""GPU parity of the air + aerosol mixture (step iv; Eqs. Pray, thetaREY,
+channelBeta) and of its surrogate and full gradients: the HIP library
+through its C ABI against the FP64 oracle on the same photon ids.
+
+FP64 transport: identical collisions and particles, so counters agree and
+values agree to summation order (1e-9).  FP32 transport: pixels within
+max(1e-4 relative, 3 sigma_MC); gradients within 1e-3 in relative L2."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1512_02110_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_02110_amd import mcrt
+    mcrt.load_library()
+    return mcrt
+
+
+def _air_field(s, b0, scale_km=8.0):
+    """Air extinction falling off with height, b0 at the floor (km^-1)."""
+    z = (np.arange(s.nz) + 0.5) * s.dz
+    col = b0 * np.exp(-z / scale_km)
+    return np.ascontiguousarray(np.broadcast_to(col[:, None, None], (s.nz, s.ny, s.nx)).reshape(-1))
+
+
+def _mix_scene(n, seed=0, b_air=2.0):
+    s = scenes.config1(n_photons=n, seed=seed)
+    s.albedo = 0.9
+    return s, _air_field(s, b_air), s.beta.copy()
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device="cuda")
+
+
+def _sigma(ref, m2, n):
+    return np.sqrt(np.maximum(m2 - 2 * ref ** 2 / max(n, 1), 0.0))
+
+
+@pytest.mark.parametrize("n,sig", [(1, 1.0), (3001, 1.3), (20011, 0.7)])
+def test_fp64_mixture_render_matches_oracle(M, oracle, n, sig):
+    s, air, aer = _mix_scene(n)
+    print(f"case mixture render fp64 n={n} sigma={sig}", flush=True)
+    img, st, gm2 = M.mc_render_mixture(s, _dev(air), _dev(aer), sig, transport="fp64", with_m2=True)
+    ref, rst = oracle.render_mix(s, air, aer, sigma=sig)
+    for k in ("photons", "events", "le_jobs", "vox_free", "esc_top", "esc_bottom", "esc_side", "rr_killed",
+              "capped"):
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    assert abs(st["vox_conn"] - rst["vox_conn"]) <= 2 * rst["le_jobs"]  # corner cameras
+    img = img.cpu().numpy()
+    assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * max(1e-300, np.abs(ref).max()))
+
+
+def test_fp32_mixture_render_matches_oracle(M, oracle):
+    s = scenes.config2(n_photons=6007)
+    air, aer = _air_field(s, 3.0), s.beta.copy()
+    print("case mixture render fp32 c2 n=6007", flush=True)
+    img, st, gm2 = M.mc_render_mixture(s, _dev(air), _dev(aer), 1.1, transport="fp32", with_m2=True)
+    ref, rst, m2 = oracle.render_mix(s, air, aer, sigma=1.1, with_m2=True)
+    img = img.cpu().numpy()
+    sig = _sigma(ref, m2 + gm2.cpu().numpy(), s.n_photons)
+    tol = np.maximum(1e-4 * np.abs(ref), 3 * sig)
+    bad = np.abs(img - ref) > tol
+    assert not bad.any(), (np.flatnonzero(bad)[:10], img[bad][:10], ref[bad][:10])
+    assert abs(st["events"] - rst["events"]) <= 1e-3 * rst["events"]
+
+
+def test_mixture_without_air_is_the_render(M):
+    import torch
+    s = scenes.config1(n_photons=20011)
+    print("case mixture without air", flush=True)
+    zero = torch.zeros(s.n_vox, dtype=torch.float64, device="cuda")
+    for transport in ("fp64", "fp32"):
+        a, sa = M.mc_render(s, M.beta_tensor(s, transport), transport=transport)
+        b, sb = M.mc_render_mixture(s, zero, _dev(s.beta), 1.0, transport=transport)
+        assert sa == sb
+        assert torch.allclose(a, b, rtol=1e-12, atol=1e-15 * float(a.abs().max()))
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_fp64_mixture_gradient_matches_oracle(M, oracle, full):
+    s, air, aer = _mix_scene(2003, seed=3)
+    rng = np.random.default_rng(8)
+    dl = rng.normal(size=sum(c.n_pix for c in s.cameras))
+    print(f"case mixture grad fp64 full={full}", flush=True)
+    g, st = M.mc_grad_mixture(s, _dev(air), _dev(aer), _dev(dl), 1.3, full=full, transport="fp64")
+    ref, rst = oracle.grad_mix(s, dl, air, aer, sigma=1.3, full=full)
+    for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    g = g.cpu().numpy()
+    assert np.abs(ref).max() > 0
+    assert np.allclose(g, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_fp64_mixture_gradient_random_scene(M, oracle):
+    rng = np.random.default_rng(12)
+    s = scenes.random_scene(rng, n_photons=3000)
+    air = rng.uniform(0.0, 4.0, size=s.beta.size)
+    air[rng.random(air.size) < 0.3] = 0.0
+    dl = rng.normal(size=sum(c.n_pix for c in s.cameras))
+    print("case mixture grad random scene", flush=True)
+    for full in (False, True):
+        g, _ = M.mc_grad_mixture(s, _dev(air), _dev(s.beta), _dev(dl), 0.8, full=full, transport="fp64")
+        ref, _ = oracle.grad_mix(s, dl, air, s.beta, sigma=0.8, full=full)
+        g = g.cpu().numpy()
+        assert np.allclose(g, ref, rtol=1e-9, atol=1e-12 * max(np.abs(ref).max(), 1e-300))
+
+
+def test_fp32_mixture_gradient(M, oracle):
+    s, air, aer = _mix_scene(4001, seed=5)
+    rng = np.random.default_rng(9)
+    dl = rng.normal(size=sum(c.n_pix for c in s.cameras))
+    print("case mixture grad fp32", flush=True)
+    for full in (False, True):
+        g, _ = M.mc_grad_mixture(s, _dev(air), _dev(aer), _dev(dl), 1.0, full=full, transport="fp32")
+        ref, _ = oracle.grad_mix(s, dl, air, aer, sigma=1.0, full=full)
+        g = g.cpu().numpy()
+        assert np.linalg.norm(g - ref) <= 1e-3 * np.linalg.norm(ref), (full, np.linalg.norm(g - ref),
+                                                                        np.linalg.norm(ref))
+
+
+def test_rgb_gradient_adds_the_channels(M, oracle):
+    import torch
+    s, air, aer = _mix_scene(1501, seed=7)
+    sig = (0.8, 1.0, 1.25)
+    airs = [air * f for f in (0.5, 1.0, 2.0)]
+    rng = np.random.default_rng(4)
+    n_pix = sum(c.n_pix for c in s.cameras)
+    dls = [rng.normal(size=n_pix) for _ in range(3)]
+    print("case rgb gradient", flush=True)
+    imgs = M.mc_render_rgb(s, [_dev(a) for a in airs], _dev(aer), sig, transport="fp64")
+    g = M.mc_grad_rgb(s, [_dev(a) for a in airs], _dev(aer), [_dev(d) for d in dls], sig, full=True,
+                      transport="fp64")
+    ref = np.zeros(s.n_vox)
+    for c in range(3):
+        img_ref, _ = oracle.render_mix(s, airs[c], aer, sigma=sig[c])
+        assert np.allclose(imgs[c][0].cpu().numpy(), img_ref, rtol=1e-9, atol=1e-13 * np.abs(img_ref).max())
+        oracle.grad_mix(s, dls[c], airs[c], aer, sigma=sig[c], full=True, grad=ref)
+    assert np.allclose(g.cpu().numpy(), ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    # accumulation: a second call adds the same again
+    g2 = M.mc_grad_rgb(s, [_dev(a) for a in airs], _dev(aer), [_dev(d) for d in dls], sig, full=True,
+                       grad=g.clone(), transport="fp64")
+    assert torch.allclose(g2, 2 * g, rtol=1e-12, atol=1e-15 * float(g.abs().max()))
+
+
+def test_mixture_edge_cases(M):
+    import torch
+    s, air, aer = _mix_scene(100)
+    A, B = _dev(air), _dev(aer)
+    dl = torch.ones(sum(c.n_pix for c in s.cameras), dtype=torch.float64, device="cuda")
+    print("case mixture edge cases", flush=True)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(M.McError):
+            M.mc_render_mixture(s, A, B, bad)
+        with pytest.raises(M.McError):
+            M.mc_grad_mixture(s, A, B, dl, bad)
+    with pytest.raises(ValueError):
+        M.mc_render_mixture(s, A.float(), B)
+    with pytest.raises(ValueError):
+        M.mc_grad_mixture(s, A, B, dl[:-1])
+    # no photons: zero images, the gradient left as it was
+    img, st = M.mc_render_mixture(s, A, B, 1.0, n_photons=0)
+    assert st["photons"] == 0 and float(img.abs().sum()) == 0.0
+    g0 = torch.full((s.n_vox,), 3.0, dtype=torch.float64, device="cuda")
+    g, st = M.mc_grad_mixture(s, A, B, dl, 1.0, grad=g0, n_photons=0)
+    assert st["photons"] == 0 and bool((g == 3.0).all())
+    # all air: no aerosol collision, so no delta term; the gradient is the
+    # (negative) path and connection terms only, finite everywhere (up to the
+    # rounding left in A_s after the last collision)
+    g, st = M.mc_grad_mixture(s, A, torch.zeros_like(B), dl, 1.0, full=True, n_photons=2000, transport="fp64")
+    assert st["events"] > 0 and bool(torch.isfinite(g).all())
+    assert float(g.max()) <= 1e-12 * float(g.abs().max()) and float(g.min()) < 0.0
+
+
+def test_full_size_mixture_without_air_c2(M):
+    """The c2 workload at 1e8 photons in the launch the benchmark times: with
+    no air the mixture kernel must reproduce the render (same photons, same
+    arithmetic, summation order aside)."""
+    import torch
+    s = scenes.config2()
+    print("case c2 full size mixture without air", flush=True)
+    zero = torch.zeros(s.n_vox, dtype=torch.float64, device="cuda")
+    a, sa = M.mc_render(s, M.beta_tensor(s, "fp32"), transport="fp32")
+    b, sb = M.mc_render_mixture(s, zero, _dev(s.beta), 1.0, transport="fp32")
+    assert sa == sb
+    assert torch.allclose(a, b, rtol=1e-9, atol=1e-12 * float(a.abs().max()))
