@@ -361,24 +361,30 @@ def main():
     # roofline of the transport kernel k_render (one launch per render),
     # timed by the library with HIP events on the launch stream; algorithmic
     # work from the launch's own counters: per voxel step (free flight or
-    # connection ray) 10 flops and one 4-byte extinction read, per local
-    # estimate 60 flops and a 16-byte FP64 tally, per event 150 flops
+    # connection ray) one 4-byte extinction read and 10 flops, per local
+    # estimate a 16-byte FP64 tally and 60 flops, per event 150 flops.  The
+    # kernel is bound by its memory side (the gathers: the vector-memory
+    # address/data units are the busiest units, the VALU is not the limit),
+    # so the memory roof is the one it is measured against; the grid itself
+    # stays in L2, hence traffic (HBM bytes) well below the algorithmic bytes
     k_ms = [r[1].timing["transport_ms"] for r in recs]
     k_s = sum(k_ms) / 1e3
     steps = st["vox_free"] + st["vox_conn"]
     flops = 10.0 * steps + 60.0 * st["le_jobs"] + 150.0 * st["events"]
     gbytes = 4.0 * steps + 16.0 * st["le_jobs"]
-    achieved_tflops = flops / k_s / 1e12
+    achieved_gbps = gbytes / k_s / 1e9
     traffic = measured_traffic()
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": PEAK_HBM_GBPS,
+                "unit": "GB/s", "frac": round(achieved_gbps / PEAK_HBM_GBPS, 4),
                 "traffic": traffic,
                 "kernel": "k_render<float, MODE_RENDER, TALLY_F64>",
                 "kernel_ms_avg": round(sum(k_ms) / len(k_ms), 3),
                 "algorithmic_bytes_per_launch": gbytes / len(recs),
-                "gather_GBps_algorithmic": round(gbytes / k_s / 1e9, 1),
+                "binding_unit": "vector-memory gather pipeline (TA/TD busy; profiles/k_render_fwd_c2_counters.md)",
                 "gather_ceiling_GBps_measured": GATHER_CEILING_GBPS,
-                "frac_of_gather_ceiling": round(gbytes / k_s / 1e9 / GATHER_CEILING_GBPS, 3),
+                "frac_of_gather_ceiling": round(achieved_gbps / GATHER_CEILING_GBPS, 3),
+                "alu_tflops": round(flops / k_s / 1e12, 3),
+                "alu_frac_of_fp32_peak": round(flops / k_s / 1e12 / PEAK_FP32_TFLOPS, 4),
                 "voxel_steps_per_s": steps / k_s}
 
     out = {
