@@ -1559,6 +1559,7 @@ __global__ void __launch_bounds__(BLOCK) k_bmc(KArgs<Real> A) {
         ph.t_exit = (Real)0;
         ph.s = 0;
         ph.pid = id;
+        ph.air = 0;
         double packet = 0.0;
         for (;;) {
             const int left = free_flight(A, (const uint32_t*)nullptr, ph, vfree, 0xffffffffu);
