@@ -659,7 +659,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
     size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
-                   round256(sizeof(Real) * (n_vox + BETA_PAD)) +
+                   round256(sizeof(Real) * (n_vox + BETA_PAD + grid->nz)) + round256(sizeof(uint32_t)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
     if (mode == MODE_GRAD || mode == MODE_MIXGRAD) bytes += round256(sizeof(double) * n_pix);
@@ -698,7 +698,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
     counters = S.take<unsigned long long>(1 + ST_N);
-    betap = S.take<Real>(n_vox + BETA_PAD);
+    // beta, the zeros, then the air column of a mixture (one value per layer)
+    betap = S.take<Real>(n_vox + BETA_PAD + grid->nz);
     dcams = S.take<DevCam<Real>>(n_cams);
     ncams = S.take<NormCam>(n_cams);
 
@@ -733,13 +734,29 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
     // the kernels read a copy of beta followed by zeros (an empty voxel
     // fetches beta[n_vox])
+    A.air_base = (uint32_t)n_vox;
+    A.air_step = 0;
     if (mix) {
-        // a mixture: beta = air + sig * aer
+        // a mixture: beta = air + sig * aer; when the air depends on the
+        // height only, empty runs (of aerosol) read the air column
         CHECK_HIP(launch_mix_total<Real>(betap, mix->air, mix->aer, mix->sig, n_vox, BETA_PAD, stream));
         A.mix_air = mix->air;
         A.mix_aer = mix->aer;
         A.mix_sig = mix->sig;
         A.mix_full = mix->full;
+        if (mode == MODE_RENDER) {
+            uint32_t* flag = S.take<uint32_t>(1);
+            uint32_t h_flag = 1;
+            CHECK_HIP(launch_fill_u32(flag, 1, stream));
+            CHECK_HIP(launch_air_column<Real>(mix->air, n_vox, (int64_t)grid->nx * grid->ny, grid->nz,
+                                              betap + n_vox + BETA_PAD, flag, stream));
+            CHECK_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            CHECK_HIP(hipStreamSynchronize(stream));
+            if (h_flag == 0) {
+                A.air_base = (uint32_t)(n_vox + BETA_PAD);
+                A.air_step = 1;
+            }
+        }
     } else {
         CHECK_HIP(hipMemcpyAsync(betap, beta, sizeof(Real) * n_vox, hipMemcpyDeviceToDevice, stream));
         if (sizeof(Real) == 4)
@@ -818,7 +835,10 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
-        CHECK_HIP(launch_build_mask<Real>(A, mask, stream));
+        if (A.air_step)
+            CHECK_HIP(launch_build_mask_aer<Real>(A, mask, stream));
+        else
+            CHECK_HIP(launch_build_mask<Real>(A, mask, stream));
     }
     base_norm = n_norm ? std::cos(prm->sun_zenith) * (grid->nx * grid->dx) * (grid->ny * grid->dy) / (double)n_norm
                        : 0.0;

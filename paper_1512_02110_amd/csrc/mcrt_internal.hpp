@@ -115,6 +115,9 @@ struct KArgs {
     const double* mix_aer;      // aerosol field of the reference channel
     double mix_sig;             // aerosol cross-section ratio of the channel
     int mix_full;               // MODE_MIXGRAD: 1 full gradient, 0 surrogate
+    // the word a voxel of an empty run reads: beta[air_base + iz * air_step]
+    // (n_vox and 0: the zero; the air column and 1: air by height)
+    uint32_t air_base, air_step;
     const HostCam* hcams;       // backward MC: cameras in double, absolute positions
     uint32_t n_pp;              // backward MC: packets per pixel
     float* grad32;              // [2 n_vox] (K32 gradient)
@@ -175,6 +178,11 @@ hipError_t launch_grad_weights(double* gw, const double* dl, const NormCam* cams
 hipError_t launch_kahan_reduce(double* out, const float* pairs, int64_t n, hipStream_t s);
 template <typename Real>
 hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
+template <typename Real>
+hipError_t launch_build_mask_aer(const KArgs<Real>& a, uint32_t* mask, hipStream_t s);
+template <typename Real>
+hipError_t launch_air_column(const double* air, int64_t n_vox, int64_t nxy, int nz, Real* col, uint32_t* flag,
+                             hipStream_t s);
 template <typename Real>
 hipError_t launch_mix_total(Real* beta, const double* air, const double* aer, double sig, int64_t n, int64_t pad,
                             hipStream_t s);

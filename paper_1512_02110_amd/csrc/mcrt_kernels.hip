@@ -249,21 +249,28 @@ __device__ __forceinline__ bool occupied(const KArgs<Real>& A, const uint32_t* m
     return (mask[cell >> 5] >> (cell & 31u)) & 1u;
 }
 
-// Extinction of voxel k, or 0 without a gather when its run is empty (no
-// mask: always gathered).
+// Where a voxel of an empty run (layer iz) reads its extinction: the zero
+// after the last voxel, or, for a mixture whose air depends on the height
+// only (the runs then mark the aerosol), the air column's value for the
+// layer.  Either way every lane reads one of a few words (no gather).
 template <typename Real>
-__device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* mask, int k) {
-    if (mask && !occupied(A, mask, k)) return (Real)0;
+__device__ __forceinline__ uint32_t empty_index(const KArgs<Real>& A, int iz) {
+    return A.air_base + (uint32_t)iz * A.air_step;
+}
+
+// Extinction of voxel k (layer iz), read from the empty-run word when its
+// run is empty (no mask: always gathered).
+template <typename Real>
+__device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* mask, int k, int iz) {
+    if (mask && !occupied(A, mask, k)) return A.air_step ? A.beta[empty_index(A, iz)] : (Real)0;
     return A.beta[k];
 }
 
-// The same value as one unconditional load: an empty voxel reads the zero
-// after the last voxel, which every lane shares (one cache line, no
-// gather), so that the loaded register can stay in flight across a step
-// without a select or a copy.
+// The same value as one unconditional load, so that the loaded register can
+// stay in flight across a step without a select or a copy.
 template <typename Real>
-__device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k) {
-    return A.beta[occupied(A, mask, k) ? (uint32_t)k : (uint32_t)A.n_vox];
+__device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k, int iz) {
+    return A.beta[occupied(A, mask, k) ? (uint32_t)k : empty_index(A, iz)];
 }
 
 // ---------------------------------------------------------------------------
@@ -320,7 +327,7 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
         return 3;
     }
     Real tau = (Real)0, tc = (Real)0;
-    Real b = beta_at(A, mask, W.k);
+    Real b = beta_at(A, mask, W.k, W.iz);
     uint32_t steps = 0;
     int left = 0;
     for (;;) {
@@ -345,7 +352,7 @@ __device__ __forceinline__ int free_flight(const KArgs<Real>& A, const uint32_t*
             tc = W.t;
             break;
         }
-        b = beta_at(A, mask, W.k);
+        b = beta_at(A, mask, W.k, W.iz);
     }
     vfree += steps;
     if (left == 0 || left == FLIGHT_GOES_ON) {
@@ -510,6 +517,7 @@ __device__ __forceinline__ void voxel_tally(const KArgs<Real>& A, JobQueue<Real,
 template <typename Real>
 struct ConnWalk {
     int k, kx, ky, kz;
+    int iz, izs;  // layer of the current voxel and its step on a z crossing
     Real sfx, sfy, sfz;
     Real rx, ry, rz;
     Real gx, gy, gz;
@@ -531,6 +539,8 @@ __device__ __forceinline__ Real conn_begin(ConnWalk<Real>& C, const DevGrid<Real
     C.kx = sx;
     C.ky = sy * G.nx;
     C.kz = sz * G.nxy;
+    C.iz = iz;
+    C.izs = sz;
     C.t = (Real)0;
     // the domain face on each axis lies (n - 1 - i) voxels beyond the first
     // face when moving up, i voxels beyond it when moving down
@@ -554,6 +564,7 @@ template <typename Real>
 __device__ __forceinline__ void conn_cross(ConnWalk<Real>& C, Real tn, bool cx, bool cy, bool cz) {
     C.t = tn;
     C.k += (cx ? C.kx : 0) + (cy ? C.ky : 0) + (cz ? C.kz : 0);
+    C.iz += cz ? C.izs : 0;
     C.rx += cx ? C.sfx : (Real)0;
     C.ry += cy ? C.sfy : (Real)0;
     C.rz += cz ? C.sfz : (Real)0;
@@ -602,7 +613,10 @@ struct Job {
 // Exactly one axis crosses, so the index moves by one of kx, ky, kz; the
 // occupancy bit of run c = k >> msh is bit c mod 32 of word k >> (msh + 5)
 // (the bit-field extract reads the low 5 bits of its offset).
-template <typename Real, int PH>
+//
+// AIRZ: the empty runs read the air column by layer (a mixture whose air
+// depends on the height only), so the walk tracks its layer.
+template <typename Real, int PH, bool AIRZ>
 __device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* mask, uint32_t msh5, Job<Real>& J) {
     Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
     Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
@@ -618,6 +632,7 @@ __device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* 
     W.t = tend;
     const int kx = W.kx, ky = W.ky, kz = W.kz;  // values: a select of fields would select addresses
     W.k += cx ? kx : (cy ? ky : kz);
+    if (AIRZ) W.iz += (!cx && !cy) ? W.izs : 0;
     W.rx += cx ? W.sfx : (Real)0;
     W.ry += cy ? W.sfy : (Real)0;
     W.rz += (!cx && !cy) ? W.sfz : (Real)0;
@@ -629,7 +644,10 @@ __device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* 
     // branch free: voxel 0 is a valid index to test when the ray is done
     const uint32_t kk = done ? 0u : (uint32_t)W.k;
     const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> A.msh, 1u) != 0u;
-    bo = A.beta[(done || !occ) ? (uint32_t)A.n_vox : kk];
+    if (AIRZ)
+        bo = A.beta[done ? (uint32_t)A.n_vox : (occ ? kk : empty_index(A, W.iz))];
+    else
+        bo = A.beta[(done || !occ) ? (uint32_t)A.n_vox : kk];
     return done;
 }
 
@@ -643,7 +661,7 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
     } else {
         J.r = fmin(J.r, texit);
     }
-    J.b0 = J.phase == 2 ? (Real)0 : beta_load(A, mask, J.W.k);
+    J.b0 = J.phase == 2 ? (Real)0 : beta_load(A, mask, J.W.k, J.W.iz);
     J.b1 = J.b2 = (Real)0;
     J.L0 = J.L1 = J.L2 = J.lp = (Real)0;
     J.tau = 0.0;
@@ -755,7 +773,7 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>
 
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
-template <typename Real, int MODE, int TALLY>
+template <typename Real, int MODE, int TALLY, bool AIRZ>
 __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
                                       JobQueue<Real, MODE>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
                                       bool& fin, bool final_pass, uint64_t& vconn, uint64_t& vconn_w,
@@ -822,15 +840,15 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
             for (;;) {
                 const uint32_t n0 = (uint32_t)__popcll(__ballot(b));
                 if (n0 <= keep) break;
-                const bool d0 = job_step3<Real, 0>(A, mask, msh5, J);
+                const bool d0 = job_step3<Real, 0, AIRZ>(A, mask, msh5, J);
                 f = f || (b && d0);
                 b = b && !d0;
                 const uint32_t n1 = (uint32_t)__popcll(__ballot(b));
-                const bool d1 = job_step3<Real, 1>(A, mask, msh5, J);
+                const bool d1 = job_step3<Real, 1, AIRZ>(A, mask, msh5, J);
                 f = f || (b && d1);
                 b = b && !d1;
                 const uint32_t n2 = (uint32_t)__popcll(__ballot(b));
-                const bool d2 = job_step3<Real, 2>(A, mask, msh5, J);
+                const bool d2 = job_step3<Real, 2, AIRZ>(A, mask, msh5, J);
                 f = f || (b && d2);
                 b = b && !d2;
                 vconn_w += n0 + n1 + n2;
@@ -863,7 +881,7 @@ struct RenderThreads {
 
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
 // the gradient is privatised, one double per voxel.
-template <typename Real, int MODE, int TALLY>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false>
 __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Real, MODE>::value))
     k_render(KArgs<Real> A) {
     constexpr int NT = RenderThreads<MODE>::value;
@@ -956,7 +974,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
+                    drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
             }
         }
         if (collided) {
@@ -966,9 +984,9 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
+        drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
     }
-    drain<Real, MODE, TALLY>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used, w_first);
+    drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used, w_first);
 
     if ((MODE == MODE_TAPE || MODE == MODE_RTAPE) && __lane_id() == 0) {
         A.tp.wave_count[wave_id] = w_used;
@@ -1845,6 +1863,35 @@ __global__ void k_build_mask(KArgs<Real> A, uint32_t* mask) {
     mask[w] = word;
 }
 
+// Occupancy mask of a mixture whose air depends on the height only: runs
+// holding aerosol (aer > 0); the air of the other voxels is the column's.
+template <typename Real>
+__global__ void k_build_mask_aer(KArgs<Real> A, uint32_t* mask) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= A.mask_words) return;
+    uint32_t word = 0;
+    for (int j = 0; j < 32; ++j) {
+        const int64_t k0 = ((int64_t)w * 32 + j) << A.msh;
+        const int64_t k1 = min(k0 + ((int64_t)1 << A.msh), A.n_vox);
+        bool any = false;
+        for (int64_t k = k0; k < k1 && !any; ++k) any = !(A.mix_aer[k] == 0.0);
+        if (any) word |= 1u << j;
+    }
+    mask[w] = word;
+}
+
+// Air column of a mixture: col[iz] = the channel's extinction of an
+// aerosol-free voxel of layer iz (the value the library's copy of beta holds
+// there), and flag != 0 when some voxel's air differs from its layer's
+// first voxel (the air is then not a function of the height alone).
+template <typename Real>
+__global__ void k_air_column(const double* air, int64_t n_vox, int64_t nxy, int nz, Real* col, uint32_t* flag) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nz) col[k] = (Real)air[k * nxy];
+    const bool diff = k < n_vox && !(air[k] == air[(k / nxy) * nxy]);
+    if (__ballot(diff) != 0ull && __lane_id() == 0) atomicOr(flag, 1u);
+}
+
 __global__ void k_kahan_reduce(double* out, const float* pairs, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (double)pairs[2 * i] + (double)pairs[2 * i + 1];
@@ -1870,15 +1917,20 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
     return bytes;
 }
 
-template <typename Real, int MODE, int TALLY>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false>
 static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
     const size_t dyn = render_dyn_lds(a, MODE);
-    hipLaunchKernelGGL((k_render<Real, MODE, TALLY>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn, s, a);
+    hipLaunchKernelGGL((k_render<Real, MODE, TALLY, AIRZ>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn, s,
+                       a);
     return hipGetLastError();
 }
 
 template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s) {
+    if (mode == MODE_RENDER && a.air_step) {
+        return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, true>(a, grid, s)
+                                  : launch_r<Real, MODE_RENDER, TALLY_K32, true>(a, grid, s);
+    }
     if (mode == MODE_RENDER) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_RENDER, TALLY_K32>(a, grid, s);
@@ -1905,14 +1957,17 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
     return hipGetLastError();
 }
 
-template <typename Real, int MODE, int TALLY>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false>
 static hipError_t occ_r(const KArgs<Real>& a, int* b) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY, AIRZ>,
                                                         RenderThreads<MODE>::value, render_dyn_lds(a, MODE));
 }
 
 template <typename Real>
 hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b) {
+    if (mode == MODE_RENDER && a.air_step)
+        return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, true>(a, b)
+                                  : occ_r<Real, MODE_RENDER, TALLY_K32, true>(a, b);
     if (mode == MODE_RENDER) return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64>(a, b)
                                                        : occ_r<Real, MODE_RENDER, TALLY_K32>(a, b);
     if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
@@ -1946,6 +2001,26 @@ hipError_t launch_build_mask(const KArgs<Real>& a, uint32_t* mask, hipStream_t s
     hipLaunchKernelGGL(k_build_mask<Real>, dim3(blocks_for(a.mask_words)), dim3(BLOCK), 0, s, a, mask);
     return hipGetLastError();
 }
+
+template <typename Real>
+hipError_t launch_build_mask_aer(const KArgs<Real>& a, uint32_t* mask, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_mask_aer<Real>, dim3(blocks_for(a.mask_words)), dim3(BLOCK), 0, s, a, mask);
+    return hipGetLastError();
+}
+template hipError_t launch_build_mask_aer<float>(const KArgs<float>&, uint32_t*, hipStream_t);
+template hipError_t launch_build_mask_aer<double>(const KArgs<double>&, uint32_t*, hipStream_t);
+
+template <typename Real>
+hipError_t launch_air_column(const double* air, int64_t n_vox, int64_t nxy, int nz, Real* col, uint32_t* flag,
+                             hipStream_t s) {
+    const int64_t n = n_vox > nz ? n_vox : nz;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_air_column<Real>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, air, n_vox, nxy, nz, col, flag);
+    return hipGetLastError();
+}
+template hipError_t launch_air_column<float>(const double*, int64_t, int64_t, int, float*, uint32_t*, hipStream_t);
+template hipError_t launch_air_column<double>(const double*, int64_t, int64_t, int, double*, uint32_t*,
+                                              hipStream_t);
 
 template <typename Real>
 hipError_t launch_bin(const KArgs<Real>& a, bool scatter, hipStream_t s) {

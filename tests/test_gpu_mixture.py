@@ -61,6 +61,29 @@ def test_fp64_mixture_render_matches_oracle(M, oracle, n, sig):
     assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * max(1e-300, np.abs(ref).max()))
 
 
+@pytest.mark.parametrize("layered", [True, False])
+def test_fp64_mixture_render_air_layouts(M, oracle, layered):
+    """Air by height only (empty aerosol runs then read the air column) and
+    air varying in 3-D (every voxel gathered): both against the oracle."""
+    rng = np.random.default_rng(31)
+    s = scenes.random_scene(rng, nx=6, ny=5, nz=4, n_photons=4000)
+    aer = s.beta.copy()
+    aer[rng.random(aer.size) < 0.5] = 0.0
+    air = _air_field(s, 1.5, scale_km=0.3)
+    if not layered:
+        air = air * rng.uniform(0.5, 1.5, size=air.size)
+    print(f"case mixture render layered={layered}", flush=True)
+    img, st = M.mc_render_mixture(s, _dev(air), _dev(aer), 1.2, transport="fp64")
+    ref, rst = oracle.render_mix(s, air, aer, sigma=1.2)
+    for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    img = img.cpu().numpy()
+    assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * max(1e-300, np.abs(ref).max()))
+    # the FP32 path through the same layout, statistically
+    img32, _ = M.mc_render_mixture(s, _dev(air), _dev(aer), 1.2, transport="fp32")
+    assert abs(float(img32.sum()) / ref.sum() - 1) < 1e-3
+
+
 def test_fp32_mixture_render_matches_oracle(M, oracle):
     s = scenes.config2(n_photons=6007)
     air, aer = _air_field(s, 3.0), s.beta.copy()
