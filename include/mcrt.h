@@ -268,8 +268,11 @@ int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double*
  *      sigma * [sum_s A_s ([t_s aerosol] delta(m,k_s) / beta_aer,ch(k_s) - l_s(m))
  *               - sum_e a_e l_e(m)],
  *      by replaying each photon twice (once for the sum of its a).
- * (beta_aer,ch = sigma * beta_aer.)  One photon per lane with FP64 device
- * atomics; params->tally is ignored.  stats count the photons' first
+ * (beta_aer,ch = sigma * beta_aer.)  One photon per lane; the connection
+ * terms go through tile bins and LDS deposits (records of at most
+ * params->tape_limit estimates per chunk of photons when > 0, else sized
+ * from the free memory), the path terms and whatever does not fit use FP64
+ * device atomics; params->tally is ignored.  stats count the photons' first
  * replay. */
 int mc_grad_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma, int n_cams,
                     const mc_camera* cams, const mc_params* params, const double* dl_dimages, int full,

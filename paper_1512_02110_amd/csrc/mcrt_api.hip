@@ -530,7 +530,7 @@ uint64_t camera_hash(int n_cams, const mc_camera* cams) {
 // the bin space (crossings per ray estimated from the passes so far).
 template <typename Real>
 int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit, int n_cu, double* t_tape,
-                  hipStream_t stream) {
+                  hipStream_t stream, int scale_gw = 1) {
     int rc = MC_OK;
     hipEvent_t b0 = nullptr, b1 = nullptr;
     float ms = 0.f;
@@ -563,7 +563,7 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     A.tp.rec = reinterpret_cast<TapeRec<Real>*>(T->rec);
     A.tp.rw = T->rw;
     A.tp.wave_count = T->wave_count;
-    A.tp.scale_gw = 1;
+    A.tp.scale_gw = scale_gw;
     A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool);
     A.tp.tile_count = meta;
     A.tp.bin_start = meta + nt;
@@ -639,6 +639,66 @@ void tape_release(mc_tape* t, hipStream_t stream) {
 }
 
 // One call of the transport kernel with all its preparation.
+// Gradient of a mixture: k_mix_grad over the photons in chunks; each chunk's
+// connection terms go to per-wavefront record slices, binned by tile and
+// deposited in LDS (run_tape_kept on the slices, weights already final);
+// records that do not fit a slice, and grids without tiles, deposit with
+// device atomics in the kernel.
+template <typename Real>
+int run_mixgrad(KArgs<Real> A, const mc_params* prm, int grid_blocks, int n_cu, double* t_tape, hipStream_t stream) {
+    int rc = MC_OK;
+    const int nw = grid_blocks * (BLOCK / 64);
+    void* rec = nullptr;
+    uint32_t* wc = nullptr;
+    uint64_t rw = 0, chunk = prm->n_photons;
+    if (A.tape) {
+        // records: sized for 16 local estimates per photon (cloud scenes have
+        // about that many) with half again as margin per slice, in chunks of
+        // photons whose records fit a quarter of the free memory (at most
+        // 16 GiB); a slice that still fills up deposits the rest directly
+        size_t avail = 0;
+        CHECK_HIP(available_bytes(&avail));
+        const double per_photon = 16.0;
+        uint64_t cap = std::min<uint64_t>(avail / 4, (uint64_t)16 << 30) / sizeof(TapeRec<Real>);
+        if (prm->tape_limit > 0) cap = std::min<uint64_t>(cap, (uint64_t)prm->tape_limit);
+        chunk = std::min<uint64_t>(prm->n_photons, (uint64_t)(0.66 * (double)cap / per_photon));
+        rw = std::min<uint64_t>((uint64_t)(1.5 * per_photon * (double)chunk / nw) + 64,
+                                std::min<uint64_t>(cap / nw, 0xffffffffull / nw));
+        if (chunk == 0 || rw < 64 || lib_alloc(&rec, sizeof(TapeRec<Real>) * rw * nw, stream) != hipSuccess ||
+            lib_alloc((void**)&wc, sizeof(uint32_t) * (nw + 1), stream) != hipSuccess) {
+            (void)hipGetLastError();
+            A.tape = 0;
+            chunk = prm->n_photons;
+        } else {
+            A.tp.rec = reinterpret_cast<TapeRec<Real>*>(rec);
+            A.tp.rw = (uint32_t)rw;
+            A.tp.wave_count = wc;
+        }
+    }
+    for (uint64_t done = 0; done < prm->n_photons; done += chunk) {
+        A.pid0 = prm->photon_offset + done;
+        A.n_photons = std::min<uint64_t>(chunk, prm->n_photons - done);
+        if (A.tape) CHECK_HIP(launch_fill_u32(wc, nw + 1, stream));
+        CHECK_HIP(launch_transport<Real>(A, MODE_MIXGRAD, TALLY_F64, grid_blocks, stream));
+        if (A.tape) {
+            mc_tape T;
+            T.rec = rec;
+            T.wave_count = wc;
+            T.nw = nw;
+            T.rw = (uint32_t)rw;
+            rc = run_tape_kept<Real>(A, TALLY_F64, &T, 0, n_cu, t_tape, stream, 0);
+            if (rc != MC_OK) goto done;
+        }
+    }
+done:
+    for (void* p : {rec, (void*)wc}) {
+        if (!p) continue;
+        hipError_t e = hipFreeAsync(p, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    return rc;
+}
+
 template <typename Real>
 int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
@@ -800,7 +860,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         A.grad_lds = mode == MODE_GRAD && lds_fits;
         keep_rays = mode == MODE_RENDER && keep && !lds_fits && prm->n_photons > 0;
     }
-    if ((mode == MODE_GRAD && !A.grad_lds) || keep_rays) {
+    if ((mode == MODE_GRAD && !A.grad_lds) || keep_rays || mode == MODE_MIXGRAD) {
         int shx, shy, shz;
         tape_tiles(grid, shx, shy, shz);
         const int tx = 1 << shx, ty = 1 << shy, tz = 1 << shz;
@@ -831,7 +891,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         A.tape = 0;  // the render itself runs in one launch
         launch_mode = MODE_RTAPE;
     }
-    CHECK_HIP(transport_occupancy<Real>(A, A.tape ? MODE_TAPE : launch_mode, tally, &per_cu));
+    CHECK_HIP(transport_occupancy<Real>(A, A.tape && mode != MODE_MIXGRAD ? MODE_TAPE : launch_mode, tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
@@ -960,7 +1020,13 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             CHECK_HIP(launch_fill_u32(kt->wave_count, nw + 1, stream));
         }
     }
-    if (A.tape && prm->n_photons > 0 && src) {
+    if (mode == MODE_MIXGRAD) {
+        if (prm->n_photons > 0 && grid_blocks > 0) {
+            std::memset(host_counters, 0, sizeof(host_counters));
+            rc = run_mixgrad<Real>(A, prm, grid_blocks, n_cu, &t_tape, stream);
+            if (rc != MC_OK) goto done;
+        }
+    } else if (A.tape && prm->n_photons > 0 && src) {
         // the rays of the render: no replay
         std::memcpy(host_counters, src->counters, sizeof(host_counters));
         rc = run_tape_kept<Real>(A, tally, src, prm->tape_limit, n_cu, &t_tape, stream);

@@ -64,7 +64,8 @@ struct alignas(16) TapeRec {
     uint32_t id;        // pixel (ray tape) or camera index (bins)
     Real fx, fy, fz;    // start fraction in the voxel
     Real a;             // gradient weight dL/di_p * norm_p * C
-    Real ab;            // bins: a / beta(start voxel)
+    Real ab;            // bins: a / beta(start voxel); mixture records: 1 for an
+                        // aerosol collision, 0 for air (bins: a / beta_aer or 0)
 };
 
 template <typename Real>

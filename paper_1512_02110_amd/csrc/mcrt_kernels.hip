@@ -1125,7 +1125,13 @@ __global__ void __launch_bounds__(BLOCK) k_bin(KArgs<Real> A, int scatter) {
     __syncthreads();
     for_each_block_ray(A, s_off, [&](const TapeRec<Real>& R0, int ix, int iy, int iz, Real vx, Real vy, Real vz, Real r) {
         TapeRec<Real> R = R0;
-        if (scatter) R.ab = (Real)((double)R.a / (double)A.beta[ix + A.G.nx * iy + A.G.nxy * iz]);
+        if (scatter) {
+            const int64_t k = ix + A.G.nx * iy + A.G.nxy * iz;
+            if (A.mix_aer)  // the collision's score term: aerosol only, over the aerosol extinction
+                R.ab = R.ab != (Real)0 ? (Real)((double)R.a / __dmul_rn(A.mix_sig, A.mix_aer[k])) : (Real)0;
+            else
+                R.ab = (Real)((double)R.a / (double)A.beta[k]);
+        }
         for_each_tile(P, R, ix, iy, iz, vx, vy, vz, r, [&](int t) {
             if (t >= lo && t < hi) {
                 const uint32_t p = atomicAdd(&s_cnt[t - lo], 1u);
@@ -1646,15 +1652,46 @@ __device__ double mix_conn(const KArgs<Real>& A, int ix, int iy, int iz, Real fx
     return tau;
 }
 
-// One photon.  PASS 0: surrogate deposits (in-scatter field frozen).  PASS
-// 1: sum of a = dL/di norm C over the photon's estimates (asum; any: some a
-// is not zero).  PASS 2: full-gradient deposits with ffd = sig * A_s, A_s
-// the sum of a over collisions s and later (asum at the start): the
-// free-flight scores -ffd l, at an aerosol collision ffd / beta_aer, the
-// connection terms -sig a l, then A_s minus this collision's a.
+// The connection term of one local estimate (sa = sig * a): a ray record for
+// the tile bins, whose deposit kernel adds -sa l(m) along the ray and, for
+// an aerosol collision, sa / beta_aer at its start (k_bin, k_deposit); when
+// the wavefront's slice is full, or the grid has no tiles, the same terms
+// go straight to grad with device atomics.
+template <typename Real>
+__device__ void mix_record(const KArgs<Real>& A, uint32_t* s_wc, const Photon<Real>& ph, int64_t pix, double sa,
+                           int64_t ke, Real vx, Real vy, Real vz, Real r) {
+    if (A.tape) {
+        const uint32_t slot = atomicAdd(&s_wc[threadIdx.x / WAVE], 1u);
+        if (slot < A.tp.rw) {
+            TapeRec<Real> R;
+            R.vox = (uint32_t)ph.ix | ((uint32_t)ph.iy << 11) | ((uint32_t)ph.iz << 22);
+            R.id = (uint32_t)pix;
+            R.fx = ph.fx;
+            R.fy = ph.fy;
+            R.fz = ph.fz;
+            R.a = (Real)sa;
+            R.ab = ph.air ? (Real)0 : (Real)1;
+            const size_t w = (size_t)blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+            A.tp.rec[w * A.tp.rw + slot] = R;
+            return;
+        }
+    }
+    uint64_t dummy = 0;
+    if (!ph.air) unsafeAtomicAdd(A.grad + ke, sa / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
+    mix_conn<Real, true>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, sa, dummy);
+}
+
+// One photon.  PASS 0: the surrogate (in-scatter field frozen): every
+// estimate's connection term (mix_record).  PASS 1: the same, and the sum of
+// a = dL/di norm C over the photon's estimates (asum; any: some a is not
+// zero).  PASS 2: the path scores of the full gradient with ffd = sig * A_s,
+// A_s the sum of a over collisions s and later (asum at the start): the
+// free-flight terms -ffd l, at an aerosol collision (ffd - sig a_s) /
+// beta_aer (the collision's own estimates are in their records), then A_s
+// minus this collision's a.
 template <typename Real, int PASS>
 __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double& asum, bool& any,
-                           unsigned long long* s_st, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
+                           unsigned long long* s_st, uint32_t* s_wc, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
                            uint64_t& vconn) {
     constexpr bool COUNT = PASS != 2;
     uint64_t dummy = 0;
@@ -1687,15 +1724,17 @@ __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, doubl
             if (PASS == 1) {
                 asum += a;
                 any = any || a != 0.0;
+            }
+            if (PASS == 2) {
+                ev_a += a;
             } else if (a != 0.0) {
-                if (PASS == 0 && !ph.air) unsafeAtomicAdd(A.grad + ke, A.mix_sig * a / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
-                if (PASS == 2) ev_a += a;
-                mix_conn<Real, true>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, A.mix_sig * a, dummy);
+                mix_record(A, s_wc, ph, pix, A.mix_sig * a, ke, vx, vy, vz, r);
             }
         }
         if (PASS == 2) {
-            if (!ph.air && ffd != 0.0) unsafeAtomicAdd(A.grad + ke, ffd / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
-            ffd -= A.mix_sig * ev_a;
+            const double later = ffd - A.mix_sig * ev_a;
+            if (!ph.air && later != 0.0) unsafeAtomicAdd(A.grad + ke, later / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
+            ffd = later;
         }
         const int fate = after_collision(A, ph);
         if (fate >= 0) {
@@ -1708,7 +1747,9 @@ __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, doubl
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
     __shared__ unsigned long long s_st[ST_N];
+    __shared__ uint32_t s_wc[BLOCK / WAVE];  // records written per wavefront
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
+    if (threadIdx.x < BLOCK / WAVE) s_wc[threadIdx.x] = 0u;
     __syncthreads();
     uint64_t n_ev = 0, n_le = 0, vfree = 0, vconn = 0;
     for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_photons;
@@ -1717,10 +1758,10 @@ __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
         double asum = 0.0;
         bool any = false;
         if (!A.mix_full) {
-            mix_photon<Real, 0>(A, pid, 0.0, asum, any, s_st, n_ev, n_le, vfree, vconn);
+            mix_photon<Real, 0>(A, pid, 0.0, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
         } else {
-            mix_photon<Real, 1>(A, pid, 0.0, asum, any, s_st, n_ev, n_le, vfree, vconn);
-            if (any) mix_photon<Real, 2>(A, pid, A.mix_sig * asum, asum, any, s_st, n_ev, n_le, vfree, vconn);
+            mix_photon<Real, 1>(A, pid, 0.0, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
+            if (any) mix_photon<Real, 2>(A, pid, A.mix_sig * asum, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
         }
     }
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
@@ -1729,6 +1770,7 @@ __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
     if (vconn) atomicAdd(&s_st[ST_VCONN], (unsigned long long)vconn);
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
+    if (A.tape && threadIdx.x < BLOCK / WAVE) A.tp.wave_count[blockIdx.x * (BLOCK / WAVE) + threadIdx.x] = s_wc[threadIdx.x];
 }
 
 // The channel's extinction beta = air + sig * aer (reference aerosol field

@@ -110,13 +110,16 @@ def test_mixture_without_air_is_the_render(M):
         assert torch.allclose(a, b, rtol=1e-12, atol=1e-15 * float(a.abs().max()))
 
 
-@pytest.mark.parametrize("full", [False, True])
-def test_fp64_mixture_gradient_matches_oracle(M, oracle, full):
+@pytest.mark.parametrize("full,tape_limit", [(False, 0), (True, 0), (True, 48485), (False, 1000), (True, 1000)])
+def test_fp64_mixture_gradient_matches_oracle(M, oracle, full, tape_limit):
+    # tape_limit: 0 = records sized from memory; 48485 = chunks of 2000
+    # photons; 1000 = too few records for a slice: every deposit direct
     s, air, aer = _mix_scene(2003, seed=3)
     rng = np.random.default_rng(8)
     dl = rng.normal(size=sum(c.n_pix for c in s.cameras))
-    print(f"case mixture grad fp64 full={full}", flush=True)
-    g, st = M.mc_grad_mixture(s, _dev(air), _dev(aer), _dev(dl), 1.3, full=full, transport="fp64")
+    print(f"case mixture grad fp64 full={full} tape_limit={tape_limit}", flush=True)
+    g, st = M.mc_grad_mixture(s, _dev(air), _dev(aer), _dev(dl), 1.3, full=full, transport="fp64",
+                              tape_limit=tape_limit)
     ref, rst = oracle.grad_mix(s, dl, air, aer, sigma=1.3, full=full)
     for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
         assert st[k] == rst[k], (k, st[k], rst[k])
