@@ -181,7 +181,7 @@ RGB_AIR_KM = (0.0059, 0.0116, 0.0259)
 RGB_SIGMA = (0.80, 1.0, 1.30)
 
 
-def mixture(M, torch, np, stream, s, n_grad=1_000_000):
+def mixture(M, torch, np, stream, s, n_grad=10_000_000):
     """Air + aerosol mixture (step iv; Eqs. Pray, thetaREY, channelBeta) on the
     same grid and cameras: the cloud is the green aerosol field, air falls off
     with height; one RGB render (FP32 transport, the workload's photons per
