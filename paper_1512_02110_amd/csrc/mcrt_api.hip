@@ -650,6 +650,7 @@ int run_mixgrad(KArgs<Real> A, const mc_params* prm, int grid_blocks, int n_cu, 
     const int nw = grid_blocks * (BLOCK / 64);
     void* rec = nullptr;
     uint32_t* wc = nullptr;
+    double* evs = nullptr;
     uint64_t rw = 0, chunk = prm->n_photons;
     if (A.tape) {
         // records: sized for 16 local estimates per photon (cloud scenes have
@@ -675,6 +676,17 @@ int run_mixgrad(KArgs<Real> A, const mc_params* prm, int grid_blocks, int n_cu, 
             A.tp.wave_count = wc;
         }
     }
+    if (A.mix_full) {
+        // the full gradient's second pass reads the first collisions' sums
+        // of the first pass instead of walking their estimates again
+        const uint32_t cap = 32;
+        if (lib_alloc((void**)&evs, sizeof(double) * cap * (size_t)grid_blocks * BLOCK, stream) == hipSuccess) {
+            A.mix_evs = evs;
+            A.mix_evcap = cap;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     for (uint64_t done = 0; done < prm->n_photons; done += chunk) {
         A.pid0 = prm->photon_offset + done;
         A.n_photons = std::min<uint64_t>(chunk, prm->n_photons - done);
@@ -691,7 +703,7 @@ int run_mixgrad(KArgs<Real> A, const mc_params* prm, int grid_blocks, int n_cu, 
         }
     }
 done:
-    for (void* p : {rec, (void*)wc}) {
+    for (void* p : {rec, (void*)wc, (void*)evs}) {
         if (!p) continue;
         hipError_t e = hipFreeAsync(p, stream);
         if (rc == MC_OK && e != hipSuccess) rc = map_err(e);

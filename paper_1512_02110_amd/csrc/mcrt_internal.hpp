@@ -116,6 +116,8 @@ struct KArgs {
     const double* mix_aer;      // aerosol field of the reference channel
     double mix_sig;             // aerosol cross-section ratio of the channel
     int mix_full;               // MODE_MIXGRAD: 1 full gradient, 0 surrogate
+    double* mix_evs;            // full gradient: per lane, the first mix_evcap collisions' sums of a
+    uint32_t mix_evcap;
     // the word a voxel of an empty run reads: beta[air_base + iz * air_step]
     // (n_vox and 0: the zero; the air column and 1: air by height)
     uint32_t air_base, air_step;

@@ -1684,11 +1684,13 @@ __device__ void mix_record(const KArgs<Real>& A, uint32_t* s_wc, const Photon<Re
 // One photon.  PASS 0: the surrogate (in-scatter field frozen): every
 // estimate's connection term (mix_record).  PASS 1: the same, and the sum of
 // a = dL/di norm C over the photon's estimates (asum; any: some a is not
-// zero).  PASS 2: the path scores of the full gradient with ffd = sig * A_s,
-// A_s the sum of a over collisions s and later (asum at the start): the
-// free-flight terms -ffd l, at an aerosol collision (ffd - sig a_s) /
-// beta_aer (the collision's own estimates are in their records), then A_s
-// minus this collision's a.
+// zero), keeping the sums of its first mix_evcap collisions in the lane's
+// row of mix_evs.  PASS 2: the path scores of the full gradient with
+// ffd = sig * A_s, A_s the sum of a over collisions s and later (asum at
+// the start): the free-flight terms -ffd l, at an aerosol collision
+// (ffd - sig a_s) / beta_aer (the collision's own estimates are in their
+// records), then A_s minus this collision's a (read back from mix_evs, or
+// its estimates walked again past the first mix_evcap collisions).
 template <typename Real, int PASS>
 __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double& asum, bool& any,
                            unsigned long long* s_st, uint32_t* s_wc, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
@@ -1709,7 +1711,10 @@ __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, doubl
         ph.air = mix_particle(A, ph);
         const int64_t ke = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
         double ev_a = 0.0;
-        for (int c = 0; c < A.n_cams; ++c) {
+        double* ev_row = A.mix_evs ? A.mix_evs + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * A.mix_evcap : nullptr;
+        const bool kept = ev_row && ph.s <= A.mix_evcap;
+        if (PASS == 2 && kept) ev_a = ev_row[ph.s - 1];
+        for (int c = 0; c < A.n_cams && !(PASS == 2 && kept); ++c) {
             int64_t pix = 0;
             int lp = 0;
             Real vx = 0, vy = 0, vz = 0, r = 0, pre = 0;
@@ -1725,12 +1730,10 @@ __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, doubl
                 asum += a;
                 any = any || a != 0.0;
             }
-            if (PASS == 2) {
-                ev_a += a;
-            } else if (a != 0.0) {
-                mix_record(A, s_wc, ph, pix, A.mix_sig * a, ke, vx, vy, vz, r);
-            }
+            if (PASS != 0) ev_a += a;
+            if (PASS != 2 && a != 0.0) mix_record(A, s_wc, ph, pix, A.mix_sig * a, ke, vx, vy, vz, r);
         }
+        if (PASS == 1 && kept) ev_row[ph.s - 1] = ev_a;
         if (PASS == 2) {
             const double later = ffd - A.mix_sig * ev_a;
             if (!ph.air && later != 0.0) unsafeAtomicAdd(A.grad + ke, later / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
