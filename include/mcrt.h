@@ -231,6 +231,19 @@ int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                   const mc_params* params, uint32_t n_per_pixel, double* images, double* images_m2,
                   mc_stats* stats, void* hip_stream);
 
+/* Frozen-event render (a test and diagnostic export): the photons are
+ * transported through beta_sample, and every local estimate walks its
+ * connection ray through beta_eval and is scaled by
+ * beta_eval(k_e) / beta_sample(k_e) at its collision voxel k_e.  At
+ * beta_eval = beta_sample this is mc_render; its derivative with respect to
+ * beta_eval there is the surrogate gradient of mc_grad_beta (Sec. 5.2 with
+ * the in-scatter field frozen, carried to one scattering event).  Both
+ * fields in the transport precision (params->transport), device memory;
+ * images and stats as in mc_render. */
+int mc_render_frozen(const mc_grid* grid, const void* beta_sample, const void* beta_eval, int n_cams,
+                     const mc_camera* cams, const mc_params* params, double* images, mc_stats* stats,
+                     void* hip_stream);
+
 /* Air + aerosol mixture, one colour channel (Sec. 2.1.2 step iv; Eqs.
  * (Pray), (thetaREY), (channelBeta)).  The channel's extinction is
  * beta = beta_air + sigma * beta_aer: beta_air (the known air field of the

@@ -716,7 +716,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
         mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr,
-        uint32_t n_pp = 0, const MixIn* mix = nullptr) {
+        uint32_t n_pp = 0, const MixIn* mix = nullptr, const void* beta_eval = nullptr) {
     int rc = MC_OK;
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -731,7 +731,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
     size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
-                   round256(sizeof(Real) * (n_vox + BETA_PAD + grid->nz)) + round256(sizeof(uint32_t)) +
+                   round256(sizeof(Real) * (n_vox + BETA_PAD + grid->nz)) * (beta_eval ? 2 : 1) +
+                   round256(sizeof(uint32_t)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
     if (mode == MODE_GRAD || mode == MODE_MIXGRAD) bytes += round256(sizeof(double) * n_pix);
@@ -772,6 +773,18 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     counters = S.take<unsigned long long>(1 + ST_N);
     // beta, the zeros, then the air column of a mixture (one value per layer)
     betap = S.take<Real>(n_vox + BETA_PAD + grid->nz);
+    A.beta_le = betap;
+    if (beta_eval) {
+        // frozen-event render: the local estimates walk a copy of beta_eval
+        Real* bl = S.take<Real>(n_vox + BETA_PAD + grid->nz);
+        CHECK_HIP(hipMemcpyAsync(bl, beta_eval, sizeof(Real) * n_vox, hipMemcpyDeviceToDevice, stream));
+        if (sizeof(Real) == 4)
+            CHECK_HIP(launch_fill_f32(reinterpret_cast<float*>(bl) + n_vox, BETA_PAD, stream));
+        else
+            CHECK_HIP(launch_fill_f64(reinterpret_cast<double*>(bl) + n_vox, BETA_PAD, stream));
+        A.beta_le = bl;
+        A.frozen = 1;
+    }
     dcams = S.take<DevCam<Real>>(n_cams);
     ncams = S.take<NormCam>(n_cams);
 
@@ -1382,6 +1395,22 @@ int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                            0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
     return run<float>(MODE_BMC, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0, 0,
                       0, nullptr, nullptr, nullptr, s, nullptr, nullptr, n_per_pixel);
+}
+
+int mc_render_frozen(const mc_grid* grid, const void* beta_sample, const void* beta_eval, int n_cams,
+                     const mc_camera* cams, const mc_params* params, double* images, mc_stats* stats,
+                     void* hip_stream) {
+    int rc = validate(grid, beta_sample, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!beta_eval || !images) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta_sample) || !is_device_ptr(beta_eval) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_RENDER, grid, beta_sample, n_cams, cams, params, images, nullptr, nullptr, nullptr,
+                           stats, 0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, beta_eval);
+    return run<float>(MODE_RENDER, grid, beta_sample, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats,
+                      0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, beta_eval);
 }
 
 int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma,

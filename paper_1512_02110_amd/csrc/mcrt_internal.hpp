@@ -94,6 +94,9 @@ struct Tape {
 template <typename Real>
 struct KArgs {
     DevGrid<Real> G;
+    const Real* beta_le;        // the extinction the local estimates walk (beta, or
+                                // the frozen-event render's evaluation field)
+    int frozen;                 // frozen-event render: C *= beta_le / beta at the collision
     const Real* beta;           // the library's copy: n_vox values, then zeros
                                 // (beta[n_vox] is fetched for empty voxels)
     const DevCam<Real>* cams;

@@ -270,7 +270,7 @@ __device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* ma
 // stay in flight across a step without a select or a copy.
 template <typename Real>
 __device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k, int iz) {
-    return A.beta[occupied(A, mask, k) ? (uint32_t)k : empty_index(A, iz)];
+    return A.beta_le[occupied(A, mask, k) ? (uint32_t)k : empty_index(A, iz)];
 }
 
 // ---------------------------------------------------------------------------
@@ -645,9 +645,9 @@ __device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* 
     const uint32_t kk = done ? 0u : (uint32_t)W.k;
     const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> A.msh, 1u) != 0u;
     if (AIRZ)
-        bo = A.beta[done ? (uint32_t)A.n_vox : (occ ? kk : empty_index(A, W.iz))];
+        bo = A.beta_le[done ? (uint32_t)A.n_vox : (occ ? kk : empty_index(A, W.iz))];
     else
-        bo = A.beta[(done || !occ) ? (uint32_t)A.n_vox : kk];
+        bo = A.beta_le[(done || !occ) ? (uint32_t)A.n_vox : kk];
     return done;
 }
 
@@ -698,7 +698,7 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     // valid index to test when the ray is done)
     const int kk = done ? 0 : J.W.k;
     const bool none = (int)done | (int)!occupied(A, mask, kk);
-    prev = A.beta[none ? (uint32_t)A.n_vox : (uint32_t)kk];
+    prev = A.beta_le[none ? (uint32_t)A.n_vox : (uint32_t)kk];
     return done;
 }
 
@@ -950,6 +950,12 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
             const unsigned long long cm = __ballot(collided);
             if (cm && A.n_cams > 0) voxel_tally<Real, MODE>(A, Q, ph, collided, cm, v_e0, v_c0, v_estep, v_cstep, n_le);
         } else if (__ballot(collided)) {
+            // frozen-event render: the estimate scaled by beta_le / beta at the collision
+            Real fr = (Real)1;
+            if (A.frozen && collided) {
+                const int64_t k = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
+                fr = (Real)((double)A.beta_le[k] / (double)A.beta[k]);
+            }
             for (int c = 0; c < A.n_cams; ++c) {
                 const DevCam<Real>& cam = A.cams[c];
                 int64_t pix = 0;
@@ -968,7 +974,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                     Q.vy[slot] = vy;
                     Q.vz[slot] = vz;
                     Q.r[slot] = r;
-                    Q.pre[slot] = pre;
+                    Q.pre[slot] = A.frozen ? pre * fr : pre;
                     Q.pix[slot] = (int32_t)pix;
                     ++n_le;
                 }
@@ -1902,7 +1908,7 @@ __global__ void k_build_mask(KArgs<Real> A, uint32_t* mask) {
         const int64_t k0 = ((int64_t)w * 32 + j) << A.msh;
         const int64_t k1 = min(k0 + ((int64_t)1 << A.msh), A.n_vox);
         bool any = false;
-        for (int64_t k = k0; k < k1 && !any; ++k) any = !(A.beta[k] == (Real)0);
+        for (int64_t k = k0; k < k1 && !any; ++k) any = !(A.beta[k] == (Real)0) || !(A.beta_le[k] == (Real)0);
         if (any) word |= 1u << j;
     }
     mask[w] = word;

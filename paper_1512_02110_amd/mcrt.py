@@ -88,7 +88,7 @@ EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
            "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
            "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover",
-           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture"]
+           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen"]
 
 
 class McError(RuntimeError):
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH):
                                     vp, vp]
         L.mc_bmc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.POINTER(McParams),
                                     C.c_uint32, vp, vp, C.POINTER(McStats), vp]
+        L.mc_render_frozen.argtypes = [C.POINTER(McGrid), vp, vp, C.c_int, C.POINTER(McCamera),
+                                       C.POINTER(McParams), vp, C.POINTER(McStats), vp]
         L.mc_render_mixture.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, C.c_int, C.POINTER(McCamera),
                                         C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
         L.mc_grad_mixture.argtypes = [C.POINTER(McGrid), vp, vp, C.c_double, C.c_int, C.POINTER(McCamera),
@@ -146,7 +148,7 @@ def load_library(path: str = LIB_PATH):
                   "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
                   "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning",
                   "mc_regularizer", "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error",
-                  "mc_recover", "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture"):
+                  "mc_recover", "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen"):
             getattr(L, f).restype = C.c_int
         L.mc_device_count.argtypes = []
         L.mc_error_string.argtypes = [C.c_int]
@@ -342,6 +344,24 @@ def mc_bmc_render(s, beta, n_per_pixel, transport="fp32", with_m2=False, stats=T
     _check("mc_bmc_render", rc)
     out = (img, _stats(st) if stats else None)
     return out + (m2,) if with_m2 else out
+
+
+def mc_render_frozen(s, beta_sample, beta_eval, transport="fp32", stats=True, stream=None, **kw):
+    """Frozen-event images: photons through beta_sample, local estimates through
+    beta_eval scaled by beta_eval / beta_sample at the collision (both GPU tensors in
+    the transport's dtype).  Returns (images, stats)."""
+    torch = _torch()
+    _check_beta(torch, s, beta_sample, transport)
+    _check_beta(torch, s, beta_eval, transport)
+    img = torch.empty(n_pixels(s), dtype=torch.float64, device=beta_sample.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_render_frozen(C.byref(make_grid(s)), C.c_void_p(beta_sample.data_ptr()),
+                                         C.c_void_p(beta_eval.data_ptr()), len(s.cameras), make_cameras(s.cameras),
+                                         C.byref(make_params(s, transport=transport, **kw)),
+                                         C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
+                                         C.c_void_p(_stream(torch, stream)))
+    _check("mc_render_frozen", rc)
+    return img, (_stats(st) if stats else None)
 
 
 def _mix_fields(torch, s, beta_air, beta_aer):

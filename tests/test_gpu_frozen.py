@@ -1,0 +1,93 @@
+"""The frozen-event render on the GPU (transport through beta_sample, local
+estimates through beta_eval, scaled by beta_eval / beta_sample at the
+collision): against the oracle, against the plain render at beta_eval =
+beta_sample, and as the function whose derivative the surrogate gradient is
+(central differences of the GPU's own frozen render against mc_grad_beta)."""
+import numpy as np
+import pytest
+
+from paper_1512_02110_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_02110_amd import mcrt
+    mcrt.load_library()
+    return mcrt
+
+
+def _fields(s, seed=3):
+    rng = np.random.default_rng(seed)
+    ev = s.beta * rng.uniform(0.7, 1.3, size=s.beta.size)
+    ev[rng.random(ev.size) < 0.1] = 0.0
+    return ev
+
+
+def test_fp64_frozen_matches_oracle(M, oracle):
+    s = scenes.config1(n_photons=5003)
+    ev = _fields(s)
+    print("case frozen fp64 c1", flush=True)
+    img, st = M.mc_render_frozen(s, M.beta_tensor(s, "fp64"), M.beta_tensor(s, "fp64", beta=ev), transport="fp64")
+    ref, rst = oracle.render_frozen(s, s.beta, ev)
+    for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    img = img.cpu().numpy()
+    assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * np.abs(ref).max())
+
+
+def test_fp32_frozen_matches_oracle(M, oracle):
+    s = scenes.config1(n_photons=20011)
+    ev = _fields(s, 4)
+    print("case frozen fp32 c1", flush=True)
+    img, _ = M.mc_render_frozen(s, M.beta_tensor(s, "fp32"), M.beta_tensor(s, "fp32", beta=ev), transport="fp32")
+    ref, _ = oracle.render_frozen(s, s.beta, ev)
+    img = img.cpu().numpy()
+    assert abs(img.sum() / ref.sum() - 1) < 1e-3
+    assert np.linalg.norm(img - ref) <= 1e-3 * np.linalg.norm(ref)
+
+
+def test_frozen_at_the_sampling_field_is_the_render(M):
+    import torch
+    s = scenes.config2(n_photons=20011)
+    print("case frozen = render", flush=True)
+    for transport in ("fp64", "fp32"):
+        b = M.beta_tensor(s, transport)
+        a, sa = M.mc_render(s, b, transport=transport)
+        f, sf = M.mc_render_frozen(s, b, b.clone(), transport=transport)
+        assert sa == sf
+        assert torch.allclose(a, f, rtol=1e-12, atol=1e-15 * float(a.abs().max()))
+
+
+def test_surrogate_gradient_is_the_frozen_derivative(M):
+    """<mc_grad_beta(beta, dl), h> = d/de sum(dl * frozen(beta, beta + e h)) at
+    e = 0, both on the GPU (FP64), central differences with e = 1e-4."""
+    import torch
+    s = scenes.config3_initial(n_photons=20011)
+    rng = np.random.default_rng(6)
+    n_pix = sum(c.n_pix for c in s.cameras)
+    dl = torch.as_tensor(rng.normal(size=n_pix), device="cuda")
+    h = s.beta * rng.uniform(-1.0, 1.0, size=s.beta.size)
+    print("case frozen derivative", flush=True)
+    b = M.beta_tensor(s, "fp64")
+    g, _ = M.mc_grad_beta(s, b, dl, transport="fp64")
+    eps = 1e-4
+    lp, _ = M.mc_render_frozen(s, b, M.beta_tensor(s, "fp64", beta=s.beta + eps * h), transport="fp64")
+    lm, _ = M.mc_render_frozen(s, b, M.beta_tensor(s, "fp64", beta=s.beta - eps * h), transport="fp64")
+    fd = float(((lp - lm) * dl).sum()) / (2 * eps)
+    an = float((g.cpu() * torch.as_tensor(h)).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+
+def test_frozen_argument_errors(M):
+    import torch
+    s = scenes.config1(n_photons=10)
+    b = M.beta_tensor(s, "fp32")
+    with pytest.raises(ValueError):
+        M.mc_render_frozen(s, b, b.double(), transport="fp32")
+    with pytest.raises(ValueError):
+        M.mc_render_frozen(s, b, b[:-1].contiguous(), transport="fp32")
