@@ -403,7 +403,8 @@ def main():
         "config": {"workload": f"{args.config}: {s.nx}x{s.ny}x{s.nz} voxels of {s.dx} km, "
                                f"{s.n_cams} cameras {s.cameras[0].width}x{s.cameras[0].height}, "
                                f"{s.n_photons:.0e} photons/render, FP32 transport + FP64 tallies",
-                   "photons": s.n_photons, "n_cams": s.n_cams},
+                   "photons": s.n_photons, "n_cams": s.n_cams,
+                   "max_column_tau": round(float((s.beta3d() * s.dz).sum(axis=0).max()), 2)},
         "fwd_ms": round(sum(fwd_ms) / len(fwd_ms), 3),
         "events_per_render": events // args.steps,
         "stats_per_render": {k: v // args.steps for k, v in st.items()},

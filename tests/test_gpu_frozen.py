@@ -91,3 +91,43 @@ def test_frozen_argument_errors(M):
         M.mc_render_frozen(s, b, b.double(), transport="fp32")
     with pytest.raises(ValueError):
         M.mc_render_frozen(s, b, b[:-1].contiguous(), transport="fp32")
+
+
+@pytest.mark.parametrize("transport,tally", [("fp64", "f64"), ("fp32", "kahan32")])
+def test_gradient_finite_differences_64_voxels(M, transport, tally):
+    """The adjoint workload's check: the L2 loss of the 16^3 initial estimate
+    against the truth's images, the GPU gradient against central differences
+    (h = 1e-3 beta0(m)) of the GPU's frozen-event images on 64 random voxels
+    (default_rng(3)); FP64 transport to the differencing error, FP32 with
+    Kahan tallies to 1e-3."""
+    import torch
+    s = scenes.config3_initial(n_photons=100_003)
+    truth = scenes.config3_truth(n_photons=100_003, seed=1)
+    print(f"case fd 64 voxels {transport} {tally}", flush=True)
+    meas, _ = M.mc_render(truth, M.beta_tensor(truth, transport), transport=transport, tally=tally)
+    b = M.beta_tensor(s, transport)
+    img, _ = M.mc_render(s, b, transport=transport, tally=tally)
+    dl = 2.0 * (img - meas)
+    g, _ = M.mc_grad_beta(s, b, dl, transport=transport, tally=tally)
+    g = g.cpu().numpy()
+    cand = np.flatnonzero(s.beta > 0)
+    vox = np.random.default_rng(3).choice(cand, size=64, replace=False)
+    m_np = meas.cpu().numpy()
+    fd = np.zeros(64)
+    for i, m in enumerate(vox):
+        h = 1e-3 * s.beta[m]
+        bp, bm = s.beta.copy(), s.beta.copy()
+        bp[m] += h
+        bm[m] -= h
+        ip, _ = M.mc_render_frozen(s, b, M.beta_tensor(s, transport, beta=bp), transport=transport, tally=tally)
+        im, _ = M.mc_render_frozen(s, b, M.beta_tensor(s, transport, beta=bm), transport=transport, tally=tally)
+        ip, im = ip.cpu().numpy(), im.cpu().numpy()
+        fd[i] = (((ip - m_np) ** 2).sum() - ((im - m_np) ** 2).sum()) / (2 * h)
+    gm = g[vox]
+    scale = np.abs(gm).max()
+    assert scale > 0
+    if transport == "fp64":
+        assert np.all(np.abs(gm - fd) <= 1e-5 * scale + 1e-4 * np.abs(gm)), np.c_[gm, fd]
+    else:
+        assert np.all(np.abs(gm - fd) <= 1e-3 * scale + 1e-2 * np.abs(gm)), np.c_[gm, fd]
+        assert np.linalg.norm(gm - fd) <= 1e-3 * np.linalg.norm(gm)
