@@ -118,12 +118,17 @@ def adjoint_c3(M, torch, np, stream, n_photons):
     timed(lambda: M.mc_grad_beta(s, beta, dl, stats=False))  # warm-up
     (g64, _), t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl, stats=False))
     (g32, _), t_adj32 = timed(lambda: M.mc_grad_beta(s, beta, dl, tally="kahan32", stats=False))
-    a, b = g64.cpu().numpy(), g32.cpu().numpy()
+    # the adjoint on the events of an independent photon stream (seed 7)
+    (gi, _), t_adji = timed(lambda: M.mc_grad_beta(s, beta, dl, seed=7, stats=False))
+    a, b, c = g64.cpu().numpy(), g32.cpu().numpy(), gi.cpu().numpy()
     return {"workload": f"c3: 16^3 blob, 4 cameras 32x32, {n_photons:.0e} photons, FP32 transport",
             "fwd_ms": round(t_fwd, 3), "adj_ms_f64": round(t_adj, 3), "adj_ms_kahan32": round(t_adj32, 3),
             "fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 4),
             "kahan32_vs_f64_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(a)),
-            "kahan32_vs_f64_max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(a)))}
+            "kahan32_vs_f64_max_rel": float(np.max(np.abs(a - b)) / np.max(np.abs(a))),
+            "adj_ms_independent_seed": round(t_adji, 3),
+            "independent_seed_vs_same_seed_rel_l2": float(np.linalg.norm(c - a) / np.linalg.norm(a)),
+            "independent_seed_cosine": float(np.dot(a, c) / (np.linalg.norm(a) * np.linalg.norm(c)))}
 
 
 def voxel_model(M, torch, np, stream, s, n_side=2):
