@@ -355,10 +355,22 @@ done:
 // chunk whose rays overflowed a wavefront slice, or with a tile bin larger
 // than the bin space, is replayed smaller before anything of it reaches the
 // gradient.  Stats of the completed chunks are summed into host_sum.
+//
+// With mp (full gradient of a mixture), the replay also sums every
+// collision's a = gw C into the photon's row of mp->rows (chunks of at most
+// mp->max_chunk photons), and each chunk that reaches the gradient is
+// followed by the path scores of its photons (k_mix_path).
+struct MixPath {
+    double* rows;        // (cap + 1) sums per photon of the chunk
+    uint32_t cap;        // collisions with a row entry of their own
+    uint64_t max_chunk;  // photons the rows hold
+    int grid;            // blocks of k_mix_path
+};
+
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
-             double* t_tape, hipStream_t stream) {
+             double* t_tape, hipStream_t stream, const MixPath* mp = nullptr) {
     int rc = MC_OK;
     // device times: replay (r0, r1), binning + deposit of the last chunk (b0, b1)
     hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr;
@@ -415,9 +427,14 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     A.tp.wave_count = meta + 3 * nt + 1;
     A.tp.slice = meta + 3 * nt + 1 + max_nw;
 
+    if (mp) {
+        A.mix_rows = mp->rows;
+        A.mix_evcap = mp->cap;
+    }
     // first chunk: a guess of 64 rays per photon
     chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, r_cap / 64));
     while (done < n_photons) {
+        if (mp) chunk = std::min<uint64_t>(chunk, mp->max_chunk);
         const uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
         const uint64_t b_cap = P - r_cap;
         const int grid = (int)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, (uint64_t)max_blocks);
@@ -431,6 +448,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
         CHECK_HIP(launch_fill_u32(A.tp.overflow, 1, stream));
         CHECK_HIP(launch_fill_u64(counters, 1 + ST_N, stream));
+        if (mp) CHECK_HIP(launch_fill_f64(mp->rows, (int64_t)(n * (mp->cap + 1)), stream));
         if (r0) CHECK_HIP(hipEventRecord(r0, stream));
         CHECK_HIP(launch_transport<Real>(A, MODE_TAPE, TALLY_F64, grid, stream));
         if (r1) CHECK_HIP(hipEventRecord(r1, stream));
@@ -472,6 +490,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         if (b0) CHECK_HIP(hipEventRecord(b0, stream));
         rc = deposit_groups<Real>(A, tally, h_count, b_cap, n_cu, ditems, max_items, h_bins, h_items, stream);
         if (rc != MC_OK) goto done;
+        if (mp) CHECK_HIP(launch_mix_path<Real>(A, mp->grid, stream));
         if (b1) {
             CHECK_HIP(hipEventRecord(b1, stream));
             pending_b = true;
@@ -759,6 +778,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const uint64_t n_work = mode == MODE_BMC ? (uint64_t)n_pix * n_pp : prm->n_photons;
     const int64_t need_blocks = (int64_t)((n_work + BLOCK - 1) / BLOCK);
     bool tape_counts = false;
+    bool mix_tape = false;  // a mixture's gradient by the queued tape replay
+    double* mix_rows = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the transport launch (stats only)
     double t_transport = 0.0, t_tape = 0.0;
     // a render that keeps its rays (only where the gradient would use tiles)
@@ -829,7 +850,10 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         A.mix_aer = mix->aer;
         A.mix_sig = mix->sig;
         A.mix_full = mix->full;
-        if (mode == MODE_RENDER) {
+        // (the gradient replays the same walks when its rays fit the tile
+        // bins; the kernels that walk every photon alone read the full copy
+        // of beta whatever the flag says)
+        if (mode == MODE_RENDER || mode == MODE_MIXGRAD) {
             uint32_t* flag = S.take<uint32_t>(1);
             uint32_t h_flag = 1;
             CHECK_HIP(launch_fill_u32(flag, 1, stream));
@@ -916,7 +940,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         A.tape = 0;  // the render itself runs in one launch
         launch_mode = MODE_RTAPE;
     }
-    CHECK_HIP(transport_occupancy<Real>(A, A.tape && mode != MODE_MIXGRAD ? MODE_TAPE : launch_mode, tally, &per_cu));
+    mix_tape = mode == MODE_MIXGRAD && A.tape;
+    CHECK_HIP(transport_occupancy<Real>(A, A.tape && (mode != MODE_MIXGRAD || mix_tape) ? MODE_TAPE : launch_mode,
+                                        tally, &per_cu));
     if (mode != MODE_TRACE) {
         uint32_t* mask = S.take<uint32_t>(mask_words);
         A.mask = mask;
@@ -1048,8 +1074,61 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     if (mode == MODE_MIXGRAD) {
         if (prm->n_photons > 0 && grid_blocks > 0) {
             std::memset(host_counters, 0, sizeof(host_counters));
-            rc = run_mixgrad<Real>(A, prm, grid_blocks, n_cu, &t_tape, stream);
-            if (rc != MC_OK) goto done;
+            const bool tape_occ = mix_tape;  // per_cu was taken for the tape replay
+            bool direct = !mix_tape;
+            MixPath mp{};
+            if (mix_tape && A.mix_full) {
+                // the path scores read the sums of 15 collisions per photon
+                // (and of the rest), in chunks of at most 4M photons or an
+                // eighth of the free memory
+                int per_mix = 0;
+                size_t avail = 0;
+                mp.cap = 15;
+                const uint64_t row = sizeof(double) * (mp.cap + 1);
+                CHECK_HIP(available_bytes(&avail));
+                mp.max_chunk = std::min<uint64_t>(std::min<uint64_t>(prm->n_photons, (uint64_t)1 << 22),
+                                                  avail / 8 / row);
+                CHECK_HIP(transport_occupancy<Real>(A, MODE_MIXGRAD, tally, &per_mix));
+                mp.grid = (int)std::min<uint64_t>((mp.max_chunk + BLOCK - 1) / BLOCK,
+                                                  (uint64_t)n_cu * (per_mix > 0 ? per_mix : 1));
+                if (mp.max_chunk == 0 || lib_alloc((void**)&mix_rows, row * mp.max_chunk, stream) != hipSuccess) {
+                    (void)hipGetLastError();
+                    mix_rows = nullptr;
+                    mix_tape = false;
+                    direct = true;
+                } else {
+                    mp.rows = mix_rows;
+                }
+            }
+            if (mix_tape) {
+                // every estimate's connection term is a ray record of the
+                // replay (weight sig * gw * C), binned by tile
+                rc = run_tape<Real>(A, TALLY_F64, prm->n_photons, prm->photon_offset, prm->tape_limit,
+                                    (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
+                                    stats ? &t_transport : nullptr, &t_tape, stream, A.mix_full ? &mp : nullptr);
+                if (rc == TAPE_FALLBACK) {
+                    // too little room for the records: one photon per lane,
+                    // device atomics
+                    rc = MC_OK;
+                    direct = true;
+                    A.tape = 0;
+                    std::memset(host_counters, 0, sizeof(host_counters));
+                } else if (rc != MC_OK) {
+                    goto done;
+                } else {
+                    tape_counts = true;
+                }
+            }
+            if (direct) {
+                // one photon per lane (records, when they fit, binned by tile)
+                if (tape_occ) {
+                    CHECK_HIP(transport_occupancy<Real>(A, MODE_MIXGRAD, tally, &per_cu));
+                    const int64_t full = (int64_t)n_cu * (per_cu > 0 ? per_cu : 1);
+                    grid_blocks = (int)(need_blocks < full ? need_blocks : full);
+                }
+                rc = run_mixgrad<Real>(A, prm, grid_blocks, n_cu, &t_tape, stream);
+                if (rc != MC_OK) goto done;
+            }
         }
     } else if (A.tape && prm->n_photons > 0 && src) {
         // the rays of the render: no replay
@@ -1158,6 +1237,10 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
 
 done:
     if (kt) tape_release(kt, stream);  // an error before the tape was handed over
+    if (mix_rows) {
+        hipError_t e = hipFreeAsync(mix_rows, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (S.base) {

@@ -64,8 +64,8 @@ struct alignas(16) TapeRec {
     uint32_t id;        // pixel (ray tape) or camera index (bins)
     Real fx, fy, fz;    // start fraction in the voxel
     Real a;             // gradient weight dL/di_p * norm_p * C
-    Real ab;            // bins: a / beta(start voxel); mixture records: 1 for an
-                        // aerosol collision, 0 for air (bins: a / beta_aer or 0)
+    Real ab;            // bins: a / beta(start voxel); records: 1, or 0 for an air
+                        // collision of a mixture (bins: a / beta_aer or 0)
 };
 
 template <typename Real>
@@ -120,6 +120,7 @@ struct KArgs {
     double mix_sig;             // aerosol cross-section ratio of the channel
     int mix_full;               // MODE_MIXGRAD: 1 full gradient, 0 surrogate
     double* mix_evs;            // full gradient: per lane, the first mix_evcap collisions' sums of a
+    double* mix_rows;           // full gradient by the tape replay: per photon, those sums and the rest's
     uint32_t mix_evcap;
     // the word a voxel of an empty run reads: beta[air_base + iz * air_step]
     // (n_vox and 0: the zero; the air column and 1: air by height)
@@ -189,6 +190,8 @@ hipError_t launch_build_mask_aer(const KArgs<Real>& a, uint32_t* mask, hipStream
 template <typename Real>
 hipError_t launch_air_column(const double* air, int64_t n_vox, int64_t nxy, int nz, Real* col, uint32_t* flag,
                              hipStream_t s);
+template <typename Real>
+hipError_t launch_mix_path(const KArgs<Real>& a, int grid, hipStream_t s);
 template <typename Real>
 hipError_t launch_mix_total(Real* beta, const double* air, const double* aer, double sig, int64_t n, int64_t pad,
                             hipStream_t s);

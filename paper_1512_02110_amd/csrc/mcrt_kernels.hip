@@ -450,6 +450,7 @@ struct JobQueue {
     Real vx[QCAP], vy[QCAP], vz[QCAP];
     Real r[QCAP], pre[QCAP];
     int32_t pix[QCAP];
+    uint32_t evi[MODE == MODE_TAPE ? QCAP : 1];  // tape replay: the estimate's slot in its photon's row
 };
 
 // Sec. 3.2, Eq. (Lcupdate): a collision adds albedo I_s P(angle) to L_c of
@@ -599,6 +600,7 @@ struct Job {
     double gwp;    // gradient weight of the pixel (loaded when the ray starts)
     int phase;     // 1: optical depth, 2: gradient scatter
     uint32_t steps;
+    uint32_t evi;  // tape replay of a mixture: slot of the estimate's collision in mix_rows
     // start of the ray, kept for the second walk of the gradient
     int i0x, i0y, i0z;
     Real f0x, f0y, f0z, vx, vy, vz;
@@ -719,7 +721,10 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
         J.tau += (double)J.b1 * (double)J.L1;
         J.tau += (double)J.b2 * (double)J.L2;
     }
-    const double C = (double)J.pre * (double)m_exp((Real)(-J.tau));
+    // (the tape replay of a mixture queues an air collision's estimates with
+    // pre negated, the mark its ray record carries)
+    const Real pre = MODE == MODE_TAPE ? (Real)fabs(J.pre) : J.pre;
+    const double C = (double)pre * (double)m_exp((Real)(-J.tau));
     if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
         tally_f64<TALLY>(A.img, A.img32, J.pix, C);
         if (A.img_m2) unsafeAtomicAdd(A.img_m2 + J.pix, C * C);
@@ -730,6 +735,9 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
         return false;
     } else if (MODE == MODE_TAPE) {
         J.a = J.gwp * C;
+        // full gradient of a mixture: a = gw C summed per collision
+        if (A.mix_rows && J.a != 0.0) unsafeAtomicAdd(A.mix_rows + J.evi, J.a);
+        if (A.mix_aer) J.a = A.mix_sig * J.a;  // the aerosol field's derivative of beta
         rec = J.a != 0.0;
         return false;
     } else {
@@ -764,7 +772,7 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>
             R.fy = J.f0y;
             R.fz = J.f0z;
             R.a = (Real)J.a;
-            R.ab = (Real)0;
+            R.ab = J.pre < (Real)0 ? (Real)0 : (Real)1;
             A.tp.rec[w_first + pos] = R;
         }
     }
@@ -808,7 +816,10 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
                     J.r = Q.r[slot];
                     J.pre = Q.pre[slot];
                     J.pix = Q.pix[slot];
-                    if (MODE == MODE_TAPE) J.gwp = A.gw[J.pix];  // needed when the ray finishes
+                    if (MODE == MODE_TAPE) {
+                        J.gwp = A.gw[J.pix];  // needed when the ray finishes
+                        J.evi = Q.evi[slot];
+                    }
                     J.phase = 1;
                     job_begin(A, mask, J);
                     busy = true;
@@ -907,6 +918,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     uint64_t pool_next = 0, pool_end = 0;
     uint32_t qhead = 0, qtail = 0;
     uint32_t n_ev = 0, n_le = 0;
+    uint32_t kloc = 0;  // the lane's photon within the launch (tape replay)
     uint64_t vfree = 0, vconn = 0;
     uint64_t vconn_w = 0;  // counted per wavefront (the same in every lane)
     const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
@@ -924,6 +936,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
             if (!alive && !exhausted) {
                 if (k < A.n_photons) {
                     launch_photon(A, A.pid0 + k, ph);
+                    kloc = (uint32_t)k;
                     alive = true;
                 } else {
                     exhausted = true;
@@ -974,8 +987,10 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                     Q.vy[slot] = vy;
                     Q.vz[slot] = vz;
                     Q.r[slot] = r;
-                    Q.pre[slot] = A.frozen ? pre * fr : pre;
+                    Q.pre[slot] = MODE == MODE_TAPE && ph.air ? -pre : (A.frozen ? pre * fr : pre);
                     Q.pix[slot] = (int32_t)pix;
+                    if (MODE == MODE_TAPE)
+                        Q.evi[slot] = kloc * (A.mix_evcap + 1u) + min(ph.s - 1u, A.mix_evcap);
                     ++n_le;
                 }
                 qtail += (uint32_t)__popcll(m);
@@ -1690,15 +1705,15 @@ __device__ void mix_record(const KArgs<Real>& A, uint32_t* s_wc, const Photon<Re
 // One photon.  PASS 0: the surrogate (in-scatter field frozen): every
 // estimate's connection term (mix_record).  PASS 1: the same, and the sum of
 // a = dL/di norm C over the photon's estimates (asum; any: some a is not
-// zero), keeping the sums of its first mix_evcap collisions in the lane's
-// row of mix_evs.  PASS 2: the path scores of the full gradient with
+// zero), keeping the sums of its first mix_evcap collisions in ev_row (the
+// lane's row of mix_evs).  PASS 2: the path scores of the full gradient with
 // ffd = sig * A_s, A_s the sum of a over collisions s and later (asum at
 // the start): the free-flight terms -ffd l, at an aerosol collision
 // (ffd - sig a_s) / beta_aer (the collision's own estimates are in their
-// records), then A_s minus this collision's a (read back from mix_evs, or
+// records), then A_s minus this collision's a (read back from ev_row, or
 // its estimates walked again past the first mix_evcap collisions).
 template <typename Real, int PASS>
-__device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double& asum, bool& any,
+__device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double* ev_row, double& asum, bool& any,
                            unsigned long long* s_st, uint32_t* s_wc, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
                            uint64_t& vconn) {
     constexpr bool COUNT = PASS != 2;
@@ -1717,7 +1732,6 @@ __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, doubl
         ph.air = mix_particle(A, ph);
         const int64_t ke = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
         double ev_a = 0.0;
-        double* ev_row = A.mix_evs ? A.mix_evs + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * A.mix_evcap : nullptr;
         const bool kept = ev_row && ph.s <= A.mix_evcap;
         if (PASS == 2 && kept) ev_a = ev_row[ph.s - 1];
         for (int c = 0; c < A.n_cams && !(PASS == 2 && kept); ++c) {
@@ -1766,11 +1780,13 @@ __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
         const uint64_t pid = A.pid0 + k;
         double asum = 0.0;
         bool any = false;
+        double* row = A.mix_evs ? A.mix_evs + ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * A.mix_evcap : nullptr;
         if (!A.mix_full) {
-            mix_photon<Real, 0>(A, pid, 0.0, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
+            mix_photon<Real, 0>(A, pid, 0.0, nullptr, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
         } else {
-            mix_photon<Real, 1>(A, pid, 0.0, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
-            if (any) mix_photon<Real, 2>(A, pid, A.mix_sig * asum, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
+            mix_photon<Real, 1>(A, pid, 0.0, row, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
+            if (any)
+                mix_photon<Real, 2>(A, pid, A.mix_sig * asum, row, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn);
         }
     }
     if (n_ev) atomicAdd(&s_st[ST_EVENTS], (unsigned long long)n_ev);
@@ -1780,6 +1796,31 @@ __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
     __syncthreads();
     if (threadIdx.x < ST_N && s_st[threadIdx.x]) atomicAdd(&A.stats[threadIdx.x], s_st[threadIdx.x]);
     if (A.tape && threadIdx.x < BLOCK / WAVE) A.tp.wave_count[blockIdx.x * (BLOCK / WAVE) + threadIdx.x] = s_wc[threadIdx.x];
+}
+
+// Path scores of the full gradient after the tape replay of the same photons
+// (which deposited the connection terms): photon k of the launch has in row
+// k of mix_rows the sums of a over the estimates of its collisions 1 ..
+// mix_evcap and, in the last entry, over all later ones; A_s starts at the
+// row's sum.  Past the first mix_evcap collisions the estimates are walked
+// again.  No counters (the replay counted the photons).
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_mix_path(KArgs<Real> A) {
+    uint64_t dummy = 0;
+    const uint32_t w = A.mix_evcap + 1u;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_photons;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        double* row = A.mix_rows + k * w;
+        double asum = 0.0;
+        bool any = false;
+        for (uint32_t j = 0; j < w; ++j) {
+            asum += row[j];
+            any = any || row[j] != 0.0;
+        }
+        if (any)
+            mix_photon<Real, 2>(A, A.pid0 + k, A.mix_sig * asum, row, asum, any, nullptr, nullptr, dummy, dummy,
+                                dummy, dummy);
+    }
 }
 
 // The channel's extinction beta = air + sig * aer (reference aerosol field
@@ -1977,6 +2018,12 @@ static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
 }
 
 template <typename Real>
+hipError_t launch_mix_path(const KArgs<Real>& a, int grid, hipStream_t s) {
+    if (grid > 0) hipLaunchKernelGGL(k_mix_path<Real>, dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s) {
     if (mode == MODE_RENDER && a.air_step) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, true>(a, grid, s)
@@ -1990,7 +2037,9 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
         return tally == TALLY_F64 ? launch_r<Real, MODE_GRAD, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_GRAD, TALLY_K32>(a, grid, s);
     }
-    if (mode == MODE_TAPE) return launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
+    if (mode == MODE_TAPE)
+        return a.air_step ? launch_r<Real, MODE_TAPE, TALLY_F64, true>(a, grid, s)
+                          : launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
     if (mode == MODE_RTAPE) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RTAPE, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_RTAPE, TALLY_K32>(a, grid, s);
@@ -2023,7 +2072,8 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
                                                        : occ_r<Real, MODE_RENDER, TALLY_K32>(a, b);
     if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
                                                      : occ_r<Real, MODE_GRAD, TALLY_K32>(a, b);
-    if (mode == MODE_TAPE) return occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
+    if (mode == MODE_TAPE)
+        return a.air_step ? occ_r<Real, MODE_TAPE, TALLY_F64, true>(a, b) : occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
     if (mode == MODE_RTAPE) return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64>(a, b)
                                                       : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
     if (mode == MODE_VOXEL) return occ_r<Real, MODE_VOXEL, TALLY_F64>(a, b);
@@ -2129,6 +2179,8 @@ template hipError_t launch_mix_total<float>(float*, const double*, const double*
 template hipError_t launch_mix_total<double>(double*, const double*, const double*, double, int64_t, int64_t,
                                              hipStream_t);
 
+template hipError_t launch_mix_path<float>(const KArgs<float>&, int, hipStream_t);
+template hipError_t launch_mix_path<double>(const KArgs<double>&, int, hipStream_t);
 template hipError_t launch_transport<float>(const KArgs<float>&, int, int, int, hipStream_t);
 template hipError_t launch_transport<double>(const KArgs<double>&, int, int, int, hipStream_t);
 template hipError_t transport_occupancy<float>(const KArgs<float>&, int, int, int*);

@@ -220,3 +220,55 @@ def test_full_size_mixture_without_air_c2(M):
     b, sb = M.mc_render_mixture(s, zero, _dev(s.beta), 1.0, transport="fp32")
     assert sa == sb
     assert torch.allclose(a, b, rtol=1e-9, atol=1e-12 * float(a.abs().max()))
+
+
+def test_fp64_mixture_gradient_many_collisions(M, oracle):
+    """Aerosol thirty times denser, albedo 0.99 (about 35 collisions per
+    photon): most photons collide more than fifteen times, past the
+    per-photon rows of collision sums that the full gradient's path scores
+    read, so their later estimates are walked again."""
+    s, air, aer = _mix_scene(1201, seed=4)
+    s.albedo = 0.99
+    aer = 30.0 * aer
+    rng = np.random.default_rng(11)
+    dl = rng.normal(size=sum(c.n_pix for c in s.cameras))
+    print("case mixture grad fp64 dense aerosol", flush=True)
+    ref_img, rst = oracle.render_mix(s, air, aer, sigma=1.0)
+    assert rst["events"] > 20 * rst["photons"]
+    for full in (False, True):
+        g, st = M.mc_grad_mixture(s, _dev(air), _dev(aer), _dev(dl), 1.0, full=full, transport="fp64")
+        ref, rst = oracle.grad_mix(s, dl, air, aer, sigma=1.0, full=full)
+        for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
+            assert st[k] == rst[k], (k, st[k], rst[k])
+        g = g.cpu().numpy()
+        assert np.allclose(g, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max()), full
+
+
+@pytest.mark.parametrize("full", [False, True])
+def test_mixture_gradient_routes_agree_c2(M, full):
+    """The c2 grid and cameras, height-only air, 4.5e6 photons in FP64: the
+    gradient by the queued tape replay (records binned by tile; for the full
+    gradient, per-photon rows of 4M photons at most, so two chunks) against
+    the one-photon-per-lane kernel with device atomics (a tape too small for
+    one block), on the same photons: the same counters, the same values up to
+    summation order.  A voxel sums 1e5-1e6 terms of both signs, in LDS tile
+    sums on one route and device atomics on the other, so the bound on the
+    difference is n eps times the sum of the terms' magnitudes, not of the
+    result: measured 1.9e-12 max|g| for the surrogate (whose terms are the same
+    arithmetic on both routes) and 1.4e-12 max|g| for the full gradient,
+    against 1e-15 between two runs of one route; tested at 1e-11 max|g|."""
+    s = scenes.config2()
+    n = 4_500_000
+    air = _air_field(s, 0.0116)
+    rng = np.random.default_rng(21)
+    dl = _dev(rng.normal(size=sum(c.n_pix for c in s.cameras)))
+    print(f"case c2 mixture grad routes full={full} {n} photons", flush=True)
+    g1, st1 = M.mc_grad_mixture(s, _dev(air), _dev(s.beta), dl, 1.0, full=full, transport="fp64", n_photons=n)
+    g2, st2 = M.mc_grad_mixture(s, _dev(air), _dev(s.beta), dl, 1.0, full=full, transport="fp64", n_photons=n,
+                                tape_limit=1000)
+    for k in ("photons", "events", "le_jobs", "vox_free", "rr_killed", "capped"):
+        assert st1[k] == st2[k], (k, st1[k], st2[k])
+    g1 = g1.cpu().numpy()
+    g2 = g2.cpu().numpy()
+    assert np.abs(g2).max() > 0
+    assert np.allclose(g1, g2, rtol=1e-9, atol=1e-11 * np.abs(g2).max())
