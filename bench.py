@@ -73,6 +73,18 @@ def _cpu_worker(args):
     return st["events"], time.perf_counter() - t0
 
 
+def _cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(cfg, per_proc, procs):
     """The oracle as it stands, P independent processes over disjoint photon
     ranges (one thread each)."""
@@ -91,7 +103,7 @@ def cpu_baseline(cfg, per_proc, procs):
             "sample": f"{cfg} workload, photon ids 0..{procs * per_proc - 1} split over {procs} "
                       f"single-threaded processes ({per_proc} photons each), FP64",
             "events": events, "wall_s": round(wall, 3), "cpu_s": round(cpu_s, 3),
-            "per_core": events / cpu_s}
+            "per_core": events / cpu_s, "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
 
 
 def adjoint_c3(M, torch, np, stream, n_photons):
