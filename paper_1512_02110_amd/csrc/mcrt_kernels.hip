@@ -1702,68 +1702,78 @@ __device__ void mix_record(const KArgs<Real>& A, uint32_t* s_wc, const Photon<Re
     mix_conn<Real, true>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, sa, dummy);
 }
 
-// One photon.  PASS 0: the surrogate (in-scatter field frozen): every
-// estimate's connection term (mix_record).  PASS 1: the same, and the sum of
-// a = dL/di norm C over the photon's estimates (asum; any: some a is not
-// zero), keeping the sums of its first mix_evcap collisions in ev_row (the
-// lane's row of mix_evs).  PASS 2: the path scores of the full gradient with
-// ffd = sig * A_s, A_s the sum of a over collisions s and later (asum at
-// the start): the free-flight terms -ffd l, at an aerosol collision
-// (ffd - sig a_s) / beta_aer (the collision's own estimates are in their
-// records), then A_s minus this collision's a (read back from ev_row, or
-// its estimates walked again past the first mix_evcap collisions).
+// One leg of a photon: its free flight and, if it collides, the collision;
+// returns false when the photon has left or ended.  PASS 0: the surrogate
+// (in-scatter field frozen): every estimate's connection term (mix_record).
+// PASS 1: the same, and the sum of a = dL/di norm C over the photon's
+// estimates (asum; any: some a is not zero), keeping the sums of its first
+// mix_evcap collisions in ev_row.  PASS 2: the path scores of the full
+// gradient with ffd = sig * A_s, A_s the sum of a over collisions s and
+// later (the photon's whole sum at the start): the free-flight terms
+// -ffd l, at an aerosol collision (ffd - sig a_s) / beta_aer (the
+// collision's own estimates are in their records), then A_s minus this
+// collision's a (read back from ev_row, or its estimates walked again past
+// the first mix_evcap collisions).
+template <typename Real, int PASS>
+__device__ __forceinline__ bool mix_leg(const KArgs<Real>& A, Photon<Real>& ph, double& ffd, double* ev_row,
+                                        double& asum, bool& any, unsigned long long* s_st, uint32_t* s_wc,
+                                        uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree, uint64_t& vconn) {
+    constexpr bool COUNT = PASS != 2;
+    uint64_t dummy = 0;
+    const int left = free_flight<Real, PASS == 2>(A, (const uint32_t*)nullptr, ph, COUNT ? vfree : dummy,
+                                                  0xffffffffu, ffd, A.grad);
+    if (left) {
+        if (COUNT) atomicAdd(&s_st[ST_TOP + left - 1], 1ull);
+        return false;
+    }
+    ph.s += 1;
+    if (COUNT) ++n_ev;
+    ph.air = mix_particle(A, ph);
+    const int64_t ke = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
+    double ev_a = 0.0;
+    const bool kept = ev_row && ph.s <= A.mix_evcap;
+    if (PASS == 2 && kept) ev_a = ev_row[ph.s - 1];
+    for (int c = 0; c < A.n_cams && !(PASS == 2 && kept); ++c) {
+        int64_t pix = 0;
+        int lp = 0;
+        Real vx = 0, vy = 0, vz = 0, r = 0, pre = 0;
+        if (!le_geometry(A, A.cams[c], ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, ph.wx, ph.wy, ph.wz, ph.weight,
+                         ph.air, pix, lp, vx, vy, vz, r, pre))
+            continue;
+        if (COUNT) ++n_le;
+        const double tau = mix_conn<Real, false>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, 0.0,
+                                                 COUNT ? vconn : dummy);
+        const double C = (double)pre * (double)m_exp((Real)(-tau));
+        const double a = A.gw[pix] * C;
+        if (PASS == 1) {
+            asum += a;
+            any = any || a != 0.0;
+        }
+        if (PASS != 0) ev_a += a;
+        if (PASS != 2 && a != 0.0) mix_record(A, s_wc, ph, pix, A.mix_sig * a, ke, vx, vy, vz, r);
+    }
+    if (PASS == 1 && kept) ev_row[ph.s - 1] = ev_a;
+    if (PASS == 2) {
+        const double later = ffd - A.mix_sig * ev_a;
+        if (!ph.air && later != 0.0) unsafeAtomicAdd(A.grad + ke, later / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
+        ffd = later;
+    }
+    const int fate = after_collision(A, ph);
+    if (fate >= 0) {
+        if (COUNT) atomicAdd(&s_st[fate == MC_FATE_CAP ? ST_CAP : ST_RR], 1ull);
+        return false;
+    }
+    return true;
+}
+
+// One photon, all of its legs in one lane (see mix_leg).
 template <typename Real, int PASS>
 __device__ void mix_photon(const KArgs<Real>& A, uint64_t pid, double ffd, double* ev_row, double& asum, bool& any,
                            unsigned long long* s_st, uint32_t* s_wc, uint64_t& n_ev, uint64_t& n_le, uint64_t& vfree,
                            uint64_t& vconn) {
-    constexpr bool COUNT = PASS != 2;
-    uint64_t dummy = 0;
     Photon<Real> ph;
     launch_photon(A, pid, ph);
-    for (;;) {
-        const int left = free_flight<Real, PASS == 2>(A, (const uint32_t*)nullptr, ph, COUNT ? vfree : dummy,
-                                                      0xffffffffu, ffd, A.grad);
-        if (left) {
-            if (COUNT) atomicAdd(&s_st[ST_TOP + left - 1], 1ull);
-            return;
-        }
-        ph.s += 1;
-        if (COUNT) ++n_ev;
-        ph.air = mix_particle(A, ph);
-        const int64_t ke = (int64_t)ph.ix + (int64_t)A.G.nx * ph.iy + (int64_t)A.G.nxy * ph.iz;
-        double ev_a = 0.0;
-        const bool kept = ev_row && ph.s <= A.mix_evcap;
-        if (PASS == 2 && kept) ev_a = ev_row[ph.s - 1];
-        for (int c = 0; c < A.n_cams && !(PASS == 2 && kept); ++c) {
-            int64_t pix = 0;
-            int lp = 0;
-            Real vx = 0, vy = 0, vz = 0, r = 0, pre = 0;
-            if (!le_geometry(A, A.cams[c], ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, ph.wx, ph.wy, ph.wz, ph.weight,
-                             ph.air, pix, lp, vx, vy, vz, r, pre))
-                continue;
-            if (COUNT) ++n_le;
-            const double tau = mix_conn<Real, false>(A, ph.ix, ph.iy, ph.iz, ph.fx, ph.fy, ph.fz, vx, vy, vz, r, 0.0,
-                                                     COUNT ? vconn : dummy);
-            const double C = (double)pre * (double)m_exp((Real)(-tau));
-            const double a = A.gw[pix] * C;
-            if (PASS == 1) {
-                asum += a;
-                any = any || a != 0.0;
-            }
-            if (PASS != 0) ev_a += a;
-            if (PASS != 2 && a != 0.0) mix_record(A, s_wc, ph, pix, A.mix_sig * a, ke, vx, vy, vz, r);
-        }
-        if (PASS == 1 && kept) ev_row[ph.s - 1] = ev_a;
-        if (PASS == 2) {
-            const double later = ffd - A.mix_sig * ev_a;
-            if (!ph.air && later != 0.0) unsafeAtomicAdd(A.grad + ke, later / __dmul_rn(A.mix_sig, A.mix_aer[ke]));
-            ffd = later;
-        }
-        const int fate = after_collision(A, ph);
-        if (fate >= 0) {
-            if (COUNT) atomicAdd(&s_st[fate == MC_FATE_CAP ? ST_CAP : ST_RR], 1ull);
-            return;
-        }
+    while (mix_leg<Real, PASS>(A, ph, ffd, ev_row, asum, any, s_st, s_wc, n_ev, n_le, vfree, vconn)) {
     }
 }
 
@@ -1803,23 +1813,39 @@ __global__ void __launch_bounds__(BLOCK) k_mix_grad(KArgs<Real> A) {
 // k of mix_rows the sums of a over the estimates of its collisions 1 ..
 // mix_evcap and, in the last entry, over all later ones; A_s starts at the
 // row's sum.  Past the first mix_evcap collisions the estimates are walked
-// again.  No counters (the replay counted the photons).
+// again.  One leg per pass of the loop, as in the forward: a lane whose
+// photon ends takes its next photon with a non-zero row at once, instead of
+// waiting for the wavefront's longest photon.  No counters (the replay
+// counted the photons).
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_mix_path(KArgs<Real> A) {
     uint64_t dummy = 0;
     const uint32_t w = A.mix_evcap + 1u;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_photons;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        double* row = A.mix_rows + k * w;
-        double asum = 0.0;
-        bool any = false;
-        for (uint32_t j = 0; j < w; ++j) {
-            asum += row[j];
-            any = any || row[j] != 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // the lane's next photon
+    Photon<Real> ph;
+    double ffd = 0.0, asum = 0.0;
+    double* row = nullptr;
+    bool alive = false, any = false;
+    for (;;) {
+        while (!alive && k < A.n_photons) {
+            row = A.mix_rows + k * w;
+            asum = 0.0;
+            any = false;
+            for (uint32_t j = 0; j < w; ++j) {
+                asum += row[j];
+                any = any || row[j] != 0.0;
+            }
+            if (any) {
+                launch_photon(A, A.pid0 + k, ph);
+                ffd = A.mix_sig * asum;
+                alive = true;
+            }
+            k += stride;
         }
-        if (any)
-            mix_photon<Real, 2>(A, A.pid0 + k, A.mix_sig * asum, row, asum, any, nullptr, nullptr, dummy, dummy,
-                                dummy, dummy);
+        if (__ballot(alive) == 0ull) break;
+        if (alive)
+            alive = mix_leg<Real, 2>(A, ph, ffd, row, asum, any, nullptr, nullptr, dummy, dummy, dummy, dummy);
     }
 }
 
