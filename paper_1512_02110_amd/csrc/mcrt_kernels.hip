@@ -818,7 +818,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
                     J.pix = Q.pix[slot];
                     if (MODE == MODE_TAPE) {
                         J.gwp = A.gw[J.pix];  // needed when the ray finishes
-                        J.evi = Q.evi[slot];
+                        if (A.mix_rows) J.evi = Q.evi[slot];
                     }
                     J.phase = 1;
                     job_begin(A, mask, J);
@@ -989,7 +989,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                     Q.r[slot] = r;
                     Q.pre[slot] = MODE == MODE_TAPE && ph.air ? -pre : (A.frozen ? pre * fr : pre);
                     Q.pix[slot] = (int32_t)pix;
-                    if (MODE == MODE_TAPE)
+                    if (MODE == MODE_TAPE && A.mix_rows)
                         Q.evi[slot] = kloc * (A.mix_evcap + 1u) + min(ph.s - 1u, A.mix_evcap);
                     ++n_le;
                 }
