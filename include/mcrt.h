@@ -281,12 +281,18 @@ int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double*
  *      sigma * [sum_s A_s ([t_s aerosol] delta(m,k_s) / beta_aer,ch(k_s) - l_s(m))
  *               - sum_e a_e l_e(m)],
  *      by replaying each photon twice (once for the sum of its a).
- * (beta_aer,ch = sigma * beta_aer.)  One photon per lane; the connection
- * terms go through tile bins and LDS deposits (records of at most
- * params->tape_limit estimates per chunk of photons when > 0, else sized
- * from the free memory), the path terms and whatever does not fit use FP64
- * device atomics; params->tally is ignored.  stats count the photons' first
- * replay. */
+ * (beta_aer,ch = sigma * beta_aer.)  When the grid's tiles fit the tile
+ * bins, the photons are replayed with the forward's local-estimate queue and
+ * every connection term becomes a ray record, binned by tile and deposited
+ * in LDS (chunks of photons whose records fit params->tape_limit when > 0,
+ * else the free memory); the full gradient's path terms follow each chunk,
+ * one photon per lane with FP64 device atomics, reading the per-collision
+ * sums of a that the replay kept (15 collisions per photon, the later ones
+ * walked again).  Otherwise, or when params->tape_limit is too small for one
+ * block of records, one photon per lane does everything, with records where
+ * they fit and FP64 device atomics for the rest.  params->tally is ignored.
+ * The result depends on the route only through FP64 summation order.
+ * stats count the photons' first replay. */
 int mc_grad_mixture(const mc_grid* grid, const double* beta_air, const double* beta_aer, double sigma, int n_cams,
                     const mc_camera* cams, const mc_params* params, const double* dl_dimages, int full,
                     double* grad_beta_aer, mc_stats* stats, void* hip_stream);
