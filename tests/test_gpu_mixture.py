@@ -272,3 +272,21 @@ def test_mixture_gradient_routes_agree_c2(M, full):
     g2 = g2.cpu().numpy()
     assert np.abs(g2).max() > 0
     assert np.allclose(g1, g2, rtol=1e-9, atol=1e-11 * np.abs(g2).max())
+
+
+def test_mixture_gradient_zero_adjoint(M):
+    """dL/di = 0: every estimate's weight is zero, so there is no record, no
+    collision sum and no path term; the gradient passed in comes back
+    unchanged, on both routes (tape replay; a tape too small for one block),
+    for the surrogate and the full gradient."""
+    import torch
+    s, air, aer = _mix_scene(3000, seed=2)
+    dl = torch.zeros(sum(c.n_pix for c in s.cameras), dtype=torch.float64, device="cuda")
+    print("case mixture grad zero adjoint", flush=True)
+    for full in (False, True):
+        for tape_limit in (0, 1000):
+            g0 = torch.full((s.n_vox,), 0.5, dtype=torch.float64, device="cuda")
+            g, st = M.mc_grad_mixture(s, _dev(air), _dev(aer), dl, 1.0, full=full, grad=g0, transport="fp32",
+                                      tape_limit=tape_limit)
+            assert st["events"] > 0 and st["photons"] == 3000
+            assert bool((g == 0.5).all()), (full, tape_limit)
