@@ -25,9 +25,11 @@
 // Eqs. Jaco1, TcofJaco1, DivTc for one event): grad[k_e] += a / beta(k_e)
 // and, walking the ray again, grad[m] -= a l(m), with a = dL/di_p norm_p C.
 // Small grids accumulate this in a per-workgroup LDS copy of the gradient.
-// Large grids replay in MODE_TAPE instead: the finished ray goes to a tape,
-// k_bin copies it into the bin of every gradient tile it crosses, and
-// k_deposit accumulates every tile's bin in LDS.  A device-scope atomic add
+// Large grids replay in MODE_TAPE instead (or keep the rays of the render,
+// MODE_RTAPE): the finished ray goes to a tape, k_bin copies it into the bin
+// of every gradient tile it crosses, and k_deposit accumulates every tile's
+// bin in LDS.  The gradients of an air + aerosol mixture use the same
+// replay and bins.  A device-scope atomic add
 // per voxel crossing would run at the memory-side atomic rate, far below the
 // walk.
 //
@@ -1641,8 +1643,11 @@ __global__ void __launch_bounds__(BLOCK) k_bmc(KArgs<Real> A) {
 
 // ---------------------------------------------------------------------------
 // Gradient of an air + aerosol mixture with respect to the reference aerosol
-// field, one photon per lane (both passes of a photon need all of its local
-// estimates, so they are walked where they arise rather than queued).
+// field.  The connection terms come from the MODE_TAPE replay (records with
+// weight sig * gw * C, an air collision's marked 0), which for the full
+// gradient also sums each collision's a into its photon's row of mix_rows;
+// k_mix_path then adds the path scores.  Where the records cannot be binned
+// by tile, k_mix_grad does both passes of a photon in one lane.
 
 // Connection ray from (i, f) along unit v over length r (clipped to the
 // domain): returns the optical depth, summed voxel by voxel in FP64; with
