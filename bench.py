@@ -143,6 +143,58 @@ def adjoint_c3(M, torch, np, stream, n_photons):
             "independent_seed_cosine": float(np.dot(a, c) / (np.linalg.norm(a) * np.linalg.norm(c)))}
 
 
+def large_grids(M, torch, np, stream, n_photons):
+    """The 128^3 cloud (25 cameras of 256^2) and the 256x256x128 multi-cloud
+    field (36 cameras of 256^2), whose extinction copies (8 and 34 MB) sit in
+    the MALL rather than in L2: the forward's events/s and voxel steps/s, and
+    the render that keeps its rays plus the gradient from them against the
+    plain render, at n_photons (their own photon counts, 1e9 and 2e9, take a
+    minute and more per render); warm-up, then one timed call of each."""
+    from paper_1512_02110_amd import scenes
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    out = {}
+    for name, make, what in (("c4", scenes.config4, "128^3 cloud, 25 cameras 256x256"),
+                             ("c5", scenes.config5, "256x256x128 multi-cloud field, 36 cameras 256x256")):
+        s = make(n_photons=n_photons)
+        beta = M.beta_tensor(s, "fp32")
+        M.mc_render(s, beta, n_photons=min(n_photons, 1_000_000), stats=False)  # warm-up
+        (img, st), t_fwd = timed(lambda: M.mc_render(s, beta))
+        dl = torch.as_tensor(np.random.default_rng(2).normal(size=img.numel()), device=img.device)
+        steps = st["vox_free"] + st["vox_conn"]
+        r = {"workload": f"{name}: {what}, {n_photons:.0e} photons, FP32 transport + FP64 tallies",
+             "fwd_ms": round(t_fwd, 3), "events_per_s": st["events"] / (t_fwd * 1e-3),
+             "events": st["events"], "le_jobs": st["le_jobs"], "voxel_steps_per_s": steps / (t_fwd * 1e-3),
+             "gather_GBps": 4.0 * steps / (t_fwd * 1e-3) / 1e9}
+        (_, _, tape), t_tape = timed(lambda: M.mc_render_tape(s, beta, stats=False))
+        if tape is None:
+            # the library sizes a kept tape from the rays per photon of the
+            # last kept render; a new workload with more rays overflows it
+            # once, and the next kept render is sized from its own count
+            (_, _, tape), t_tape = timed(lambda: M.mc_render_tape(s, beta, stats=False))
+        if tape is not None:
+            # the render's rays kept: render with rays + gradient from them
+            _, t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl, tape=tape, stats=False))
+            tape.free()
+            r.update({"adj_route": "kept rays", "fwd_tape_ms": round(t_tape, 3), "adj_ms": round(t_adj, 3),
+                      "fwd_plus_adj_over_fwd": round((t_tape + t_adj) / t_fwd, 4)})
+        else:
+            # more rays than the tape holds: the gradient replays the photons
+            _, t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl, stats=False))
+            r.update({"adj_route": "replay", "adj_ms": round(t_adj, 3),
+                      "fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 4)})
+        out[name] = r
+        del tape, img, beta
+    return out
+
+
 def voxel_model(M, torch, np, stream, s, n_side=2):
     """The paper's voxelised forward model (Sec. 3) on the same workload: the
     scatter pass (photons without local estimates, j_c(k) per camera and
@@ -308,6 +360,8 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=None)
     ap.add_argument("--c3-photons", type=int, default=100_000_000)
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxelised-model section")
+    ap.add_argument("--no-large", action="store_true", help="skip the 128^3 and 256x256x128 section")
+    ap.add_argument("--large-photons", type=int, default=20_000_000)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -475,6 +529,8 @@ def main():
                        "events_fp32_minus_fp64": int(recs[0][1]["events"] - st64["events"])}
     if not args.no_adjoint and args.config == "c2":
         out["fwd_adjoint_c3"] = adjoint_c3(M, torch, np, stream, args.c3_photons)
+    if not args.no_large and not args.no_adjoint and args.config == "c2":
+        out["large_grids"] = large_grids(M, torch, np, stream, args.large_photons)
     if not args.no_voxel:
         out["voxel_model"] = voxel_model(M, torch, np, stream, s)
         out["recovery"] = recovery(M, torch, np, stream, s)
