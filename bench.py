@@ -175,9 +175,9 @@ def large_grids(M, torch, np, stream, n_photons):
              "gather_GBps": 4.0 * steps / (t_fwd * 1e-3) / 1e9}
         (_, _, tape), t_tape = timed(lambda: M.mc_render_tape(s, beta, stats=False))
         if tape is None:
-            # the library sizes a kept tape from the rays per photon of the
-            # last kept render; a new workload with more rays overflows it
-            # once, and the next kept render is sized from its own count
+            # a kept tape that overflowed (sized from an earlier kept render
+            # of this workload with fewer rays per photon): the next kept
+            # render is sized from this one's count
             (_, _, tape), t_tape = timed(lambda: M.mc_render_tape(s, beta, stats=False))
         if tape is not None:
             # the render's rays kept: render with rays + gradient from them

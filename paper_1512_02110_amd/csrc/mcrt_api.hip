@@ -137,11 +137,13 @@ struct MixIn {
 // tapes and bins, tens of GB each, are not mapped and unmapped on every
 // call; mc_release_memory hands the cached memory back to the device.  The
 // same lock guards the tape sizing hint (rays per photon of the busiest
-// wavefront of the last kept render on the device).
+// wavefront of the last kept render on the device, and the key of the
+// workload it was measured on: grid, cameras, albedo, phase and sun).
 constexpr int MAX_DEVICES = 64;
 std::mutex g_mu;
 hipMemPool_t g_pool[MAX_DEVICES] = {};
 double g_tape_rate[MAX_DEVICES] = {};
+uint64_t g_tape_key[MAX_DEVICES] = {};
 
 hipError_t lib_pool(int dev, hipMemPool_t* out) {
     if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
@@ -543,6 +545,17 @@ uint64_t camera_hash(int n_cams, const mc_camera* cams) {
     return h;
 }
 
+// Key of a workload for the tape sizing hint: the grid, the cameras and the
+// parameters that shape the photon paths (not the photon count or seed).
+uint64_t workload_key(const mc_grid* g, int n_cams, const mc_camera* cams, const mc_params* p) {
+    uint64_t h = camera_hash(n_cams, cams);
+    const double v[10] = {(double)g->nx, (double)g->ny, (double)g->nz, g->dx, g->dy, g->dz,
+                          p->albedo, p->g, p->sun_zenith, p->sun_azimuth};
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(v);
+    for (size_t i = 0; i < sizeof(v); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
 // Gradient of a large grid from the rays a render kept: the record weights
 // are local estimates, scaled by the pixel weights in the binning passes;
 // the slices are binned and deposited in passes whose tile crossings fit
@@ -779,6 +792,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const int64_t need_blocks = (int64_t)((n_work + BLOCK - 1) / BLOCK);
     bool tape_counts = false;
     bool mix_tape = false;  // a mixture's gradient by the queued tape replay
+    uint64_t tape_key = 0;  // workload key of the tape sizing hint
     double* mix_rows = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // around the transport launch (stats only)
     double t_transport = 0.0, t_tape = 0.0;
@@ -1040,10 +1054,13 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         CHECK_HIP(available_bytes(&avail));
         uint64_t cap = prm->tape_limit > 0 ? (uint64_t)prm->tape_limit
                                            : (uint64_t)(avail / 8 * 3) / sizeof(TapeRec<Real>);
+        // (the hint only for the workload it was measured on: another grid or
+        // camera set can have many more rays per photon)
         double rate = 0.0;
+        tape_key = workload_key(grid, n_cams, cams, prm);
         {
             std::lock_guard<std::mutex> lock(g_mu);
-            rate = dev < MAX_DEVICES ? g_tape_rate[dev] : 0.0;
+            rate = dev < MAX_DEVICES && g_tape_key[dev] == tape_key ? g_tape_rate[dev] : 0.0;
         }
         if (rate > 0.0 && prm->tape_limit == 0)
             cap = std::min<uint64_t>(cap, (uint64_t)(1.25 * rate * (double)prm->n_photons) + 64 * (uint64_t)nw);
@@ -1193,7 +1210,11 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             for (int w = 0; w < kt->nw; ++w) busiest = std::max(busiest, h_wave[w]);
             const double r = (double)busiest * kt->nw / (double)prm->n_photons;
             std::lock_guard<std::mutex> lock(g_mu);
-            if (dev < MAX_DEVICES) g_tape_rate[dev] = over ? std::max(2.0 * g_tape_rate[dev], r) : r;
+            if (dev < MAX_DEVICES) {
+                const double prev = g_tape_key[dev] == tape_key ? g_tape_rate[dev] : 0.0;
+                g_tape_rate[dev] = over ? std::max(2.0 * prev, r) : r;
+                g_tape_key[dev] = tape_key;
+            }
         }
         if (over) {
             tape_release(kt, stream);

@@ -382,3 +382,24 @@ def test_full_size_config2_sampled_and_invariants(M, oracle):
     tail, gm2, _ = M.mc_render_moments(s, beta, n_photons=n, photon_offset=100_000_000 - n)
     ref, rst, m2 = oracle.render(s, with_m2=True, n_photons=n, photon_offset=100_000_000 - n)
     _assert_pixels(tail.cpu().numpy(), ref, _sigma(ref, m2 + gm2.cpu().numpy(), n))
+
+
+def test_kept_tape_sizing_per_workload(M):
+    """The kept tape is sized from the rays per photon of the last kept render
+    of the same workload only: after the 64^3 workload (about 14 local
+    estimates per photon), a kept render of the 128^3 workload with 25
+    cameras (about 117) still keeps its rays, and so does the next one."""
+    import torch
+    s2 = scenes.config2(n_photons=1_000_000)
+    _, _, t2 = M.mc_render_tape(s2, M.beta_tensor(s2, "fp32"))
+    assert t2 is not None
+    t2.free()
+    s4 = scenes.config4(n_photons=1_000_000)
+    print("case kept tape sizing c2 then c4", flush=True)
+    b4 = M.beta_tensor(s4, "fp32")
+    for k in range(2):
+        img, st, t4 = M.mc_render_tape(s4, b4)
+        assert t4 is not None, k
+        assert st["le_jobs"] > 50 * st["photons"]
+        t4.free()
+    torch.cuda.synchronize()
