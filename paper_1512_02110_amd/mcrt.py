@@ -11,6 +11,8 @@ Entry points (same names as the C ABI in include/mcrt.h):
     mc_grad_beta(..., tape=t)        -> the gradient of that render from its rays (no replay)
     mc_trace_paths(scene, beta, first_pid, count, max_rec, ...)
     MCRender: torch.autograd.Function (forward = render, backward = surrogate gradient)
+    MCRenderMixture: the same for one channel of an air + aerosol mixture (backward =
+        dL/d beta_aer, full or surrogate)
 """
 from __future__ import annotations
 
@@ -670,4 +672,48 @@ def _autograd_fn():
 
         _fn = _MCRender
     return _fn
+
+
+class MCRenderMixture:
+    """torch.autograd.Function wrapper for one channel of the air + aerosol
+    mixture (Eq. channelBeta): images = mc_render_mixture(beta_air,
+    beta_aer, sigma); the backward pass returns dL/d beta_aer from
+    mc_grad_mixture on the same photons, the full derivative (full=True,
+    default) or the surrogate with the in-scatter field frozen.  beta_air is
+    a constant (no gradient)."""
+
+    @staticmethod
+    def apply(beta_aer, scene, beta_air, sigma=1.0, full=True, transport="fp32", **kw):
+        return _mixture_fn().apply(beta_aer, scene, beta_air, float(sigma), bool(full), transport, kw)
+
+
+_mix_fn = None
+
+
+def _mixture_fn():
+    global _mix_fn
+    if _mix_fn is None:
+        torch = _torch()
+
+        class _MCRenderMixture(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, beta_aer, scene, beta_air, sigma, full, transport, kw):
+                aer = beta_aer.detach().to(dtype=torch.float64).contiguous().reshape(-1)
+                air = beta_air.detach().to(device=aer.device, dtype=torch.float64).contiguous().reshape(-1)
+                img, _ = mc_render_mixture(scene, air, aer, sigma, transport=transport, stats=False, **kw)
+                ctx.save_for_backward(air, aer)
+                ctx.scene, ctx.sigma, ctx.full, ctx.transport, ctx.kw = scene, sigma, full, transport, kw
+                ctx.aer_dtype, ctx.aer_shape = beta_aer.dtype, beta_aer.shape
+                return img
+
+            @staticmethod
+            def backward(ctx, g_img):
+                air, aer = ctx.saved_tensors
+                dl = g_img.detach().to(dtype=torch.float64).contiguous().reshape(-1)
+                g, _ = mc_grad_mixture(ctx.scene, air, aer, dl, ctx.sigma, full=ctx.full, transport=ctx.transport,
+                                       stats=False, **ctx.kw)
+                return g.to(ctx.aer_dtype).reshape(ctx.aer_shape), None, None, None, None, None, None
+
+        _mix_fn = _MCRenderMixture
+    return _mix_fn
 

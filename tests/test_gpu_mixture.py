@@ -290,3 +290,25 @@ def test_mixture_gradient_zero_adjoint(M):
                                       tape_limit=tape_limit)
             assert st["events"] > 0 and st["photons"] == 3000
             assert bool((g == 0.5).all()), (full, tape_limit)
+
+
+def test_autograd_mixture(M):
+    """MCRenderMixture: forward = mc_render_mixture, backward = mc_grad_mixture
+    on the same photons (full and surrogate), an L2 loss through torch."""
+    import torch
+    s, air, aer = _mix_scene(3001, seed=6)
+    print("case autograd mixture", flush=True)
+    meas = torch.as_tensor(np.random.default_rng(4).uniform(0.0, 1e-2, size=sum(c.n_pix for c in s.cameras)),
+                           device="cuda")
+    for full in (True, False):
+        a = _dev(aer).reshape(s.nz, s.ny, s.nx).requires_grad_(True)
+        img = M.MCRenderMixture.apply(a, s, _dev(air), 1.3, full, "fp64")
+        ref, _ = M.mc_render_mixture(s, _dev(air), _dev(aer), 1.3, transport="fp64")
+        assert torch.allclose(img, ref, rtol=1e-12, atol=1e-15 * float(ref.abs().max()))
+        loss = ((img - meas) ** 2).sum()
+        loss.backward()
+        g, _ = M.mc_grad_mixture(s, _dev(air), _dev(aer), 2.0 * (ref - meas), 1.3, full=full, transport="fp64")
+        assert a.grad.shape == a.shape
+        gg = a.grad.reshape(-1)
+        assert float(g.abs().max()) > 0
+        assert torch.allclose(gg, g, rtol=1e-9, atol=1e-12 * float(g.abs().max())), full
