@@ -898,6 +898,9 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.G.idx = (Real)(1.0 / grid->dx);
     A.G.idy = (Real)(1.0 / grid->dy);
     A.G.idz = (Real)(1.0 / grid->dz);
+    A.G.ddx = grid->dx;
+    A.G.ddy = grid->dy;
+    A.G.ddz = grid->dz;
     A.beta = betap;
     A.cams = dcams;
     A.n_cams = n_cams;

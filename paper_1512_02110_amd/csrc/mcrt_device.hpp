@@ -144,17 +144,25 @@ struct DevGrid {
     int nx, ny, nz, nxy;
     Real dx, dy, dz;     // voxel edges (km)
     Real idx, idy, idz;  // 1 / edge
+    double ddx, ddy, ddz;  // voxel edges in double (the projection onto the cameras)
 };
 
+// A camera as the kernels see it.  The connection rays use the centre in the
+// transport precision; the projection of a collision (its pixel and the cull
+// of collisions at the centre) is computed in FP64 whatever the transport
+// precision, from the camera's double parameters, so that the pixel of a
+// local estimate depends only on the collision point the transport computed
+// and not on the rounding of the projection.
 template <typename Real>
 struct DevCam {
     int32_t icx, icy, icz;  // camera centre = (ic + fc) voxel edges along each axis
     int32_t width;
     Real fcx, fcy, fcz;
-    Real R[9];
-    Real fx, fy, cx, cy;
-    Real fw, fh;  // width, height as Real
     int32_t pix_off, pad_;
+    double pfcx, pfcy, pfcz;  // the centre's fraction in double
+    double R[9];
+    double fx, fy, cx, cy;
+    double fw, fh;  // width, height
 };
 
 // Voxel walk (regular tracking) from the voxel-local point (i, f) along the

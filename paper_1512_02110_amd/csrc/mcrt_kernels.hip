@@ -380,26 +380,30 @@ __device__ __forceinline__ bool le_geometry(const KArgs<Real>& A, const DevCam<R
                                             Real fx, Real fy, Real fz, Real wx, Real wy, Real wz, Real weight,
                                             int air, int64_t& pix, int& local_pix, Real& vx, Real& vy, Real& vz,
                                             Real& r, Real& pre) {
-    // X - X_c from voxel-local parts: the integer differences are exact
-    const Real dx = ((Real)(ix - cam.icx) + (fx - cam.fcx)) * A.G.dx;
-    const Real dy = ((Real)(iy - cam.icy) + (fy - cam.fcy)) * A.G.dy;
-    const Real dz = ((Real)(iz - cam.icz) + (fz - cam.fcz)) * A.G.dz;
-    const Real qz = cam.R[6] * dx + cam.R[7] * dy + cam.R[8] * dz;
-    if (!(qz > (Real)0)) return false;
-    const Real qx = cam.R[0] * dx + cam.R[1] * dy + cam.R[2] * dz;
-    const Real qy = cam.R[3] * dx + cam.R[4] * dy + cam.R[5] * dz;
-    const Real u = cam.fx * qx / qz + cam.cx;
-    const Real v = cam.fy * qy / qz + cam.cy;
-    if (!(u >= (Real)0 && u < cam.fw && v >= (Real)0 && v < cam.fh)) return false;
-    const Real r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < (Real)1e-12) return false;
+    // X - X_c from voxel-local parts (the integer differences are exact),
+    // projected in FP64 for either transport precision: the pixel and the
+    // cull are discrete choices, made in double from the collision point
+    const double dx = ((double)(ix - cam.icx) + ((double)fx - cam.pfcx)) * A.G.ddx;
+    const double dy = ((double)(iy - cam.icy) + ((double)fy - cam.pfcy)) * A.G.ddy;
+    const double dz = ((double)(iz - cam.icz) + ((double)fz - cam.pfcz)) * A.G.ddz;
+    const double qz = cam.R[6] * dx + cam.R[7] * dy + cam.R[8] * dz;
+    if (!(qz > 0.0)) return false;
+    const double qx = cam.R[0] * dx + cam.R[1] * dy + cam.R[2] * dz;
+    const double qy = cam.R[3] * dx + cam.R[4] * dy + cam.R[5] * dz;
+    const double u = cam.fx * qx / qz + cam.cx;
+    const double v = cam.fy * qy / qz + cam.cy;
+    if (!(u >= 0.0 && u < cam.fw && v >= 0.0 && v < cam.fh)) return false;
+    const double r2d = dx * dx + dy * dy + dz * dz;
+    if (r2d < 1e-12) return false;
     local_pix = (int)v * cam.width + (int)u;
     pix = (int64_t)cam.pix_off + local_pix;
+    // the rest in the transport precision
+    const Real r2 = (Real)r2d;
     r = m_sqrt(r2);
     const Real ir = (Real)1 / r;
-    vx = -dx * ir;
-    vy = -dy * ir;
-    vz = -dz * ir;
+    vx = -(Real)dx * ir;
+    vy = -(Real)dy * ir;
+    vz = -(Real)dz * ir;
     const Real cosang = wx * vx + wy * vy + wz * vz;
     // Eq. (fle) with the albedo and phase function of the particle
     pre = air ? weight * rayleigh_phase(cosang) / r2 : A.albedo * weight * hg_phase(A.g, cosang) / r2;
@@ -1884,13 +1888,16 @@ __global__ void k_write_cams(CamChunk chunk, DevCam<Real>* dev, NormCam* norm) {
     d.fcy = (Real)(pcy - iy);
     d.fcz = (Real)(pcz - iz);
     d.pad_ = 0;
-    for (int j = 0; j < 9; ++j) d.R[j] = (Real)h.R[j];
-    d.fx = (Real)h.fx;
-    d.fy = (Real)h.fy;
-    d.cx = (Real)h.cx;
-    d.cy = (Real)h.cy;
-    d.fw = (Real)h.width;
-    d.fh = (Real)h.height;
+    d.pfcx = pcx - ix;
+    d.pfcy = pcy - iy;
+    d.pfcz = pcz - iz;
+    for (int j = 0; j < 9; ++j) d.R[j] = h.R[j];
+    d.fx = h.fx;
+    d.fy = h.fy;
+    d.cx = h.cx;
+    d.cy = h.cy;
+    d.fw = (double)h.width;
+    d.fh = (double)h.height;
     d.width = h.width;
     d.pix_off = (int32_t)h.pix_off;
     dev[chunk.first + i] = d;

@@ -654,7 +654,7 @@ def _autograd_fn():
                     img, _ = mc_render(scene, b, transport=transport, tally=tally, stats=False, **kw)
                 ctx.save_for_backward(b)
                 ctx.scene, ctx.transport, ctx.tally, ctx.grad_seed, ctx.kw = scene, transport, tally, grad_seed, kw
-                ctx.beta_dtype = beta.dtype
+                ctx.beta_dtype, ctx.beta_shape = beta.dtype, beta.shape
                 return img
 
             @staticmethod
@@ -668,7 +668,7 @@ def _autograd_fn():
                 if ctx.tape is not None:
                     ctx.tape.free()
                     ctx.tape = None
-                return g.to(ctx.beta_dtype), None, None, None, None, None
+                return g.to(ctx.beta_dtype).reshape(ctx.beta_shape), None, None, None, None, None
 
         _fn = _MCRender
     return _fn

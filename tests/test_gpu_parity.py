@@ -365,6 +365,24 @@ def test_autograd_function(M):
     assert torch.allclose(beta.grad.double(), g.float().double(), rtol=1e-6, atol=1e-6 * g.abs().max().item())
 
 
+def test_autograd_function_3d_beta(M):
+    """A (nz, ny, nx) extinction gets a gradient of its own shape, equal to the
+    flat one."""
+    import torch
+    s = scenes.config3_initial(n_photons=20000)
+    print("case autograd 3-d beta c3", flush=True)
+    beta = torch.tensor(s.beta3d(), dtype=torch.float32, device="cuda", requires_grad=True)
+    img = M.MCRender.apply(beta, s)
+    ((img - img.detach() * 1.1) ** 2).sum().backward()
+    assert beta.grad.shape == beta.shape
+    flat = torch.tensor(s.beta, dtype=torch.float32, device="cuda", requires_grad=True)
+    img_f = M.MCRender.apply(flat, s)
+    ((img_f - img_f.detach() * 1.1) ** 2).sum().backward()
+    # (the same events; FP64 atomics may sum in another order)
+    assert torch.allclose(beta.grad.reshape(-1).double(), flat.grad.double(), rtol=1e-5,
+                          atol=1e-6 * flat.grad.abs().max().item())
+
+
 def test_full_size_config2_sampled_and_invariants(M, oracle):
     """The bench workload (64^3, 9 cameras of 128^2, 1e8 photons, FP32 transport)
     in the same launch configuration: photon bookkeeping holds, the images are
