@@ -877,15 +877,12 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 }
 
 // Wavefronts per SIMD the compiler must leave room for: 4 (at most 128
-// VGPRs) for the FP32 forward and tape replay, which are latency bound and
-// gain more from a fourth wavefront than they lose to the tighter register
-// budget; the FP64 and small-grid gradient kernels keep their registers.
+// VGPRs) for the FP32 kernels, which are latency bound and gain more from a
+// fourth wavefront than they lose to the tighter register budget; the FP64
+// kernels keep their registers.
 template <typename Real, int MODE>
 struct RenderWaves {
-    static constexpr int value =
-        sizeof(Real) == 4 && (MODE == MODE_RENDER || MODE == MODE_TAPE || MODE == MODE_RTAPE || MODE == MODE_VOXEL)
-            ? 4
-            : 1;
+    static constexpr int value = sizeof(Real) == 4 && MODE != MODE_TRACE && MODE != MODE_BMC ? 4 : 1;
 };
 
 // Threads per block: 512 for the gradient, whose privatised copy of the
@@ -1469,7 +1466,12 @@ __global__ void __launch_bounds__(BLOCK) k_trace(KArgs<Real> A) {
     launch_photon(A, A.first_pid + tid, ph);
     uint64_t vfree = 0;
     for (;;) {
-        const int left = free_flight(A, (const uint32_t*)nullptr, ph, vfree, 0xffffffffu);
+        // flights in the render's budgeted pieces, so that a path is the
+        // render's to the last rounding
+        int left;
+        do {
+            left = free_flight(A, (const uint32_t*)nullptr, ph, vfree, FLIGHT_BUDGET);
+        } while (left == FLIGHT_GOES_ON);
         if (left) {
             record_path(A, tid, ph, left - 1);
             return;
