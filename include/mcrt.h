@@ -65,7 +65,8 @@ enum {
     MC_ERR_INVALID_ARG = -1,   /* an argument is out of range or a pointer is missing */
     MC_ERR_NO_DEVICE = -2,     /* no HIP device is visible */
     MC_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
-    MC_ERR_OUT_OF_MEMORY = -4  /* scratch allocation failed */
+    MC_ERR_OUT_OF_MEMORY = -4, /* scratch allocation failed */
+    MC_ERR_SCRATCH_LIMIT = -5  /* mc_render_noalloc: the call needs more than its fixed scratch */
 };
 
 /* Transport precision: positions, directions, traversal and free-path
@@ -160,6 +161,25 @@ int mc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_camera
 int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
                       const mc_params* params, double* images, double* images_m2, mc_stats* stats,
                       void* hip_stream);
+
+/* mc_render without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it).  Same arguments, images and counters as mc_render; the
+ * library's scratch (counters, camera table, the copy of beta, the occupancy
+ * bitmask, the compensated tally) lives in a fixed device array of 64 MiB
+ * that every device the library runs on holds until the process ends.  The
+ * call allocates nothing (no hipMalloc, no pool, no events): stats, when
+ * non-NULL, report the counters with transport_ms = 0 and make the call wait
+ * for the stream.  The scratch a call needs is about sizeof(real) bytes per
+ * voxel (4 for MC_FP32 transport, 8 for MC_FP64), 8 bytes per pixel with
+ * MC_TALLY_KAHAN32, and under 40 KB besides; a call that needs more than
+ * 64 MiB (e.g. FP64 transport on 256 x 256 x 128 voxels) returns
+ * MC_ERR_SCRATCH_LIMIT and enqueues nothing.  Every call on one device shares
+ * that device's array and leaves its contents behind; calls that overlap on
+ * one device (other streams, other threads) race and give wrong images:
+ * serialise them. */
+int mc_render_noalloc(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                      const mc_params* params, double* images, mc_stats* stats, void* hip_stream);
 
 /* Surrogate gradient dL/dbeta for a loss L(images) whose image gradient is
  * dl_dimages (device, same layout as mc_render's images; for an L2 loss,

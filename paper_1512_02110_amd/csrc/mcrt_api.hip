@@ -30,6 +30,14 @@ struct mc_tape {
     unsigned long long counters[1 + ST_N];  // the render's counters (host copy)
 };
 
+// Device scratch of mc_render_noalloc, for callers that cannot allocate: a
+// file-scope array of NOALLOC_SCRATCH_BYTES, one copy per device, held until
+// the process ends.  In host code its name is only a host-side stand-in:
+// every kernel argument or copy uses the device address that
+// hipGetSymbolAddress returned for the current device (g_noalloc_ptr).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
@@ -144,6 +152,26 @@ std::mutex g_mu;
 hipMemPool_t g_pool[MAX_DEVICES] = {};
 double g_tape_rate[MAX_DEVICES] = {};
 uint64_t g_tape_key[MAX_DEVICES] = {};
+void* g_noalloc_ptr[MAX_DEVICES] = {};  // device address of `scratch` on each device
+
+// Device address of the no-allocation scratch on the current device, looked
+// up once per device (with that device current).
+hipError_t noalloc_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t lib_pool(int dev, hipMemPool_t* out) {
     if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
@@ -748,7 +776,11 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         const mc_params* prm, double* images, double* images_m2, const double* dl, double* grad, mc_stats* stats,
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
         mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr,
-        uint32_t n_pp = 0, const MixIn* mix = nullptr, const void* beta_eval = nullptr) {
+        uint32_t n_pp = 0, const MixIn* mix = nullptr, const void* beta_eval = nullptr,
+        void* fixed_scratch = nullptr) {
+    // fixed_scratch: the no-allocation render; its scratch is the library's
+    // fixed device array (NOALLOC_SCRATCH_BYTES) and the call allocates
+    // nothing and creates no events
     int rc = MC_OK;
     const int64_t n_pix = pixel_count(n_cams, cams);
     const int64_t n_vox = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -804,7 +836,12 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
 
     CHECK_HIP(hipGetDevice(&dev));
     CHECK_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
+    if (fixed_scratch) {
+        if (bytes > NOALLOC_SCRATCH_BYTES) return MC_ERR_SCRATCH_LIMIT;  // nothing enqueued yet
+        S.base = static_cast<char*>(fixed_scratch);
+    } else {
+        CHECK_HIP(lib_alloc((void**)&S.base, bytes, stream));
+    }
     counters = S.take<unsigned long long>(1 + ST_N);
     // beta, the zeros, then the air column of a mixture (one value per layer)
     betap = S.take<Real>(n_vox + BETA_PAD + grid->nz);
@@ -1181,13 +1218,13 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             tape_counts = true;
         }
     } else if (grid_blocks > 0 && (mode == MODE_TRACE || n_work > 0)) {
-        if (stats) {
+        if (stats && !fixed_scratch) {
             CHECK_HIP(hipEventCreate(&ev0));
             CHECK_HIP(hipEventCreate(&ev1));
             CHECK_HIP(hipEventRecord(ev0, stream));
         }
         CHECK_HIP(launch_transport<Real>(A, launch_mode, tally, grid_blocks, stream));
-        if (stats) CHECK_HIP(hipEventRecord(ev1, stream));
+        if (ev1) CHECK_HIP(hipEventRecord(ev1, stream));
     }
 
     if (mode == MODE_VOXEL)
@@ -1267,7 +1304,7 @@ done:
     }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    if (S.base) {
+    if (S.base && !fixed_scratch) {
         hipError_t e = hipFreeAsync(S.base, stream);
         if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
     }
@@ -1385,6 +1422,7 @@ const char* mc_error_string(int code) {
         case MC_ERR_NO_DEVICE: return "no HIP device";
         case MC_ERR_HIP: return "HIP runtime error";
         case MC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case MC_ERR_SCRATCH_LIMIT: return "the call needs more scratch than the fixed 64 MiB of mc_render_noalloc";
         default: return "unknown status code";
     }
 }
@@ -1409,6 +1447,23 @@ int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const m
                            0, 0, 0, nullptr, nullptr, nullptr, s);
     return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0,
                       0, 0, nullptr, nullptr, nullptr, s);
+}
+
+int mc_render_noalloc(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
+                      const mc_params* params, double* images, mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (!images) return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
+    void* fixed = nullptr;
+    if ((rc = map_err(noalloc_scratch(&fixed))) != MC_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (params->transport == MC_FP64)
+        return run<double>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats,
+                           0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, nullptr, fixed);
+    return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0,
+                      0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, nullptr, fixed);
 }
 
 int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams, const mc_params* params,

@@ -25,6 +25,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmcrt.so")
 
 MC_OK, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE, MC_ERR_HIP, MC_ERR_OUT_OF_MEMORY = 0, -1, -2, -3, -4
+MC_ERR_SCRATCH_LIMIT = -5
 MC_FP32, MC_FP64 = 0, 1
 MC_TALLY_F64, MC_TALLY_KAHAN32 = 0, 1
 TRANSPORTS = {"fp32": MC_FP32, "fp64": MC_FP64}
@@ -90,7 +91,7 @@ EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
            "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
            "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover",
-           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen"]
+           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen", "mc_render_noalloc"]
 
 
 class McError(RuntimeError):
@@ -112,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         L.mc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
                                 C.POINTER(McParams), vp, C.POINTER(McStats), vp]
+        L.mc_render_noalloc.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
+                                        C.POINTER(McParams), vp, C.POINTER(McStats), vp]
         L.mc_render_moments.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
                                         C.POINTER(McParams), vp, vp, C.POINTER(McStats), vp]
         L.mc_grad_beta.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
@@ -235,6 +238,24 @@ def mc_render(s, beta, transport="fp32", tally="f64", stats=True, out=None, stre
                                   C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
                                   C.c_void_p(_stream(torch, stream)))
     _check("mc_render", rc)
+    return img, (_stats(st) if stats else None)
+
+
+def mc_render_noalloc(s, beta, transport="fp32", tally="f64", stats=True, out=None, stream=None, **kw):
+    """mc_render through the entry point that allocates nothing in the library (its
+    scratch is a fixed 64 MiB device array).  Returns (images, stats or None); `out`
+    (a float64 CUDA tensor of the pixel count) avoids the allocation of the images."""
+    torch = _torch()
+    _check_beta(torch, s, beta, transport)
+    n = n_pixels(s)
+    img = out if out is not None else torch.empty(n, dtype=torch.float64, device=beta.device)
+    st = McStats() if stats else None
+    rc = load_library().mc_render_noalloc(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                          make_cameras(s.cameras),
+                                          C.byref(make_params(s, transport=transport, tally=tally, **kw)),
+                                          C.c_void_p(img.data_ptr()), C.byref(st) if stats else None,
+                                          C.c_void_p(_stream(torch, stream)))
+    _check("mc_render_noalloc", rc)
     return img, (_stats(st) if stats else None)
 
 

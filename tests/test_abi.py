@@ -56,7 +56,7 @@ def test_struct_layouts_match_header():
 
 
 def test_error_strings(lib):
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert mcrt.error_string(code)
     assert mcrt.error_string(-99) == "unknown status code"
 
