@@ -69,10 +69,23 @@ enum {
     MC_ERR_SCRATCH_LIMIT = -5  /* mc_render_noalloc: the call needs more than its fixed scratch */
 };
 
-/* Transport precision: positions, directions, traversal and free-path
- * optical depth.  Connection-ray optical depths and all tallies are FP64 in
- * both. */
-enum { MC_FP32 = 0, MC_FP64 = 1 };
+/* Transport precision.  Connection-ray optical depths and all tallies are
+ * FP64 in every mode, and so is the projection of a collision onto a camera
+ * (its pixel and the cull at the camera centre).
+ *   MC_FP32: photon state (position, direction, weight), free flights,
+ *     scattering and the connection-ray walks in FP32; beta is float.
+ *   MC_FP64: all of it in FP64; beta is double.
+ *   MC_MIXED: the photons (launch, free flights, collisions, roulette,
+ *     scattering) in FP64, exactly as MC_FP64, and the walks of the
+ *     connection rays -- most of the voxel steps -- in FP32 over a float copy
+ *     of beta; beta is double.  The photon paths, events, counters and pixels
+ *     are those of MC_FP64; only the connection rays' optical depths differ
+ *     by FP32 rounding (segment lengths and the float copy of beta).
+ *     Accepted by mc_render, mc_render_moments, mc_render_noalloc,
+ *     mc_render_tape (which then keeps no tape), mc_grad_beta (the gradient
+ *     of the same events, computed with the FP64 walks) and mc_trace_paths
+ *     (the FP64 paths); the other entry points return MC_ERR_INVALID_ARG. */
+enum { MC_FP32 = 0, MC_FP64 = 1, MC_MIXED = 2 };
 
 /* Tally accumulation: FP64 atomics, or FP32 sum + FP32 compensation term
  * (error-free transformation of every atomic add), reduced to FP64 at the
@@ -114,7 +127,7 @@ typedef struct mc_params {
                                  the total of all shards when photon ranges are split. */
     uint32_t max_events;      /* collisions after which a photon is stopped and counted as
                                  capped, >= 1 */
-    int32_t transport;        /* MC_FP32 or MC_FP64 */
+    int32_t transport;        /* MC_FP32, MC_FP64 or MC_MIXED */
     int32_t tally;            /* MC_TALLY_F64 or MC_TALLY_KAHAN32 */
     int32_t tape_limit;       /* mc_grad_beta on grids too large for an LDS copy of the
                                  gradient: most records of its ray tape (stream-ordered
@@ -141,7 +154,7 @@ typedef struct mc_stats {
 
 /* Forward render (FMC + local estimation).
  * beta: device array of nx*ny*nz values, float for MC_FP32 transport and
- *   double for MC_FP64.
+ *   double for MC_FP64 and MC_MIXED.
  * images: device array of sum_c width_c*height_c doubles, [camera][row][col],
  *   overwritten with radiance per unit solar irradiance: the sum of local
  *   estimates of a pixel times mu0 * A_top / (N * Omega_p), with

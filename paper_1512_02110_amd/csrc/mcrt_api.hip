@@ -93,7 +93,7 @@ int validate(const mc_grid* g, const void* beta, int n_cams, const mc_camera* ca
     if (!std::isfinite(p->sun_azimuth)) return MC_ERR_INVALID_ARG;
     if (!(p->rr_weight > 0.0 && p->rr_weight <= 1.0)) return MC_ERR_INVALID_ARG;
     if (p->max_events < 1) return MC_ERR_INVALID_ARG;
-    if (p->transport != MC_FP32 && p->transport != MC_FP64) return MC_ERR_INVALID_ARG;
+    if (p->transport != MC_FP32 && p->transport != MC_FP64 && p->transport != MC_MIXED) return MC_ERR_INVALID_ARG;
     if (p->tally != MC_TALLY_F64 && p->tally != MC_TALLY_KAHAN32) return MC_ERR_INVALID_ARG;
     if (p->tape_limit < 0) return MC_ERR_INVALID_ARG;
     return MC_OK;
@@ -788,18 +788,24 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     const bool k32 = tally == TALLY_K32 && mode != MODE_TRACE && mode != MODE_VOXEL && mode != MODE_MIXGRAD;
 
     // occupancy mask: one bit per run of 2^msh consecutive voxels, the
-    // shortest runs whose bits fit the kernels' LDS copy
-    const int64_t mask_budget = sizeof(Real) == 4 ? MASK_WORDS_FP32 : MASK_WORDS;
+    // shortest runs whose bits fit the kernels' LDS copy (the FP32 budget for
+    // the mixed-precision render, which runs four blocks per CU as FP32 does)
+    const bool mixed_render = prm->transport == MC_MIXED && mode == MODE_RENDER;
+    const int64_t mask_budget = sizeof(Real) == 4 || mixed_render ? MASK_WORDS_FP32 : MASK_WORDS;
     int msh = 0;
     while (((n_vox + ((int64_t)1 << msh) - 1) >> msh) > mask_budget * 32) ++msh;
     const int64_t mask_words = (((n_vox + ((int64_t)1 << msh) - 1) >> msh) + 31) / 32;
 
+    // mixed precision: the photons in FP64 (Real = double), the connection
+    // rays on a float copy of beta
+    const bool mixed = sizeof(Real) == 8 && prm->transport == MC_MIXED && mode == MODE_RENDER && !mix && !beta_eval;
     size_t bytes = round256(sizeof(unsigned long long) * (1 + ST_N)) +
                    round256(sizeof(Real) * (n_vox + BETA_PAD + grid->nz)) * (beta_eval ? 2 : 1) +
                    round256(sizeof(uint32_t)) +
                    round256(sizeof(DevCam<Real>) * n_cams) + round256(sizeof(NormCam) * n_cams) +
                    round256(sizeof(uint32_t) * mask_words);
     if (mode == MODE_GRAD || mode == MODE_MIXGRAD) bytes += round256(sizeof(double) * n_pix);
+    if (mixed) bytes += round256(sizeof(float) * (n_vox + BETA_PAD + grid->nz));
     if (k32 && mode == MODE_RENDER) bytes += round256(sizeof(float) * 2 * n_pix);
     if (k32 && mode == MODE_GRAD) bytes += round256(sizeof(float) * 2 * n_vox);
     if (mode == MODE_BMC) bytes += round256(sizeof(HostCam) * n_cams);
@@ -939,6 +945,25 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.G.ddy = grid->dy;
     A.G.ddz = grid->dz;
     A.beta = betap;
+    if (mixed) {
+        float* bw = S.take<float>(n_vox + BETA_PAD + grid->nz);
+        CHECK_HIP(launch_d2f(n_vox + BETA_PAD, reinterpret_cast<const double*>(betap), bw, stream));
+        A.walk32 = 1;
+        A.beta_w32 = bw;
+        A.G32.nx = grid->nx;
+        A.G32.ny = grid->ny;
+        A.G32.nz = grid->nz;
+        A.G32.nxy = grid->nx * grid->ny;
+        A.G32.dx = (float)grid->dx;
+        A.G32.dy = (float)grid->dy;
+        A.G32.dz = (float)grid->dz;
+        A.G32.idx = (float)(1.0 / grid->dx);
+        A.G32.idy = (float)(1.0 / grid->dy);
+        A.G32.idz = (float)(1.0 / grid->dz);
+        A.G32.ddx = grid->dx;
+        A.G32.ddy = grid->dy;
+        A.G32.ddz = grid->dz;
+    }
     A.cams = dcams;
     A.n_cams = n_cams;
     A.wsx = (Real)(-std::sin(prm->sun_zenith) * std::cos(prm->sun_azimuth));
@@ -1442,7 +1467,7 @@ int mc_render_moments(const mc_grid* grid, const void* beta, int n_cams, const m
     if (!is_device_ptr(beta) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
     if (images_m2 && !is_device_ptr(images_m2)) return MC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (params->transport == MC_FP64)
+    if (params->transport != MC_FP32)
         return run<double>(MODE_RENDER, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats,
                            0, 0, 0, nullptr, nullptr, nullptr, s);
     return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, images_m2, nullptr, nullptr, stats, 0,
@@ -1459,7 +1484,7 @@ int mc_render_noalloc(const mc_grid* grid, const void* beta, int n_cams, const m
     void* fixed = nullptr;
     if ((rc = map_err(noalloc_scratch(&fixed))) != MC_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (params->transport == MC_FP64)
+    if (params->transport != MC_FP32)
         return run<double>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats,
                            0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, nullptr, fixed);
     return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0,
@@ -1474,7 +1499,7 @@ int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_cam
     if ((rc = precheck_device()) != MC_OK) return rc;
     if (!is_device_ptr(beta) || !is_device_ptr(dl_dimages) || !is_device_ptr(grad_beta)) return MC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (params->transport == MC_FP64)
+    if (params->transport != MC_FP32)
         return run<double>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta,
                            stats, 0, 0, 0, nullptr, nullptr, nullptr, s);
     return run<float>(MODE_GRAD, grid, beta, n_cams, cams, params, nullptr, nullptr, dl_dimages, grad_beta, stats,
@@ -1491,9 +1516,9 @@ int mc_render_tape(const mc_grid* grid, const void* beta, int n_cams, const mc_c
     if ((rc = precheck_device()) != MC_OK) return rc;
     if (!is_device_ptr(beta) || !is_device_ptr(images)) return MC_ERR_INVALID_ARG;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (params->transport == MC_FP64)
+    if (params->transport != MC_FP32)  // (a mixed-precision render keeps no rays)
         return run<double>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats,
-                           0, 0, 0, nullptr, nullptr, nullptr, s, tape);
+                           0, 0, 0, nullptr, nullptr, nullptr, s, params->transport == MC_MIXED ? nullptr : tape);
     return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0,
                       0, 0, nullptr, nullptr, nullptr, s, tape);
 }
@@ -1502,6 +1527,7 @@ int mc_grad_beta_tape(const mc_tape* tape, const mc_grid* grid, const void* beta
                       const mc_camera* cams, const mc_params* params, const double* dl_dimages, double* grad_beta,
                       mc_stats* stats, void* hip_stream) {
     int rc = validate(grid, beta, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!tape || tape->magic != TAPE_MAGIC || !dl_dimages || !grad_beta) return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
@@ -1530,6 +1556,7 @@ int mc_grad_beta_tape(const mc_tape* tape, const mc_grid* grid, const void* beta
 int mc_voxel_scatter(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams,
                      const mc_params* params, double* j, mc_stats* stats, void* hip_stream) {
     int rc = validate(grid, beta, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!j || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
@@ -1545,6 +1572,7 @@ int mc_voxel_scatter(const mc_grid* grid, const void* beta, int n_cams, const mc
 int mc_bmc_render(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams, const mc_params* params,
                   uint32_t n_per_pixel, double* images, double* images_m2, mc_stats* stats, void* hip_stream) {
     int rc = validate(grid, beta, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!images || n_per_pixel < 1 || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
     if ((uint64_t)pixel_count(n_cams, cams) * n_per_pixel >= ((uint64_t)1 << 62)) return MC_ERR_INVALID_ARG;
@@ -1563,6 +1591,7 @@ int mc_render_frozen(const mc_grid* grid, const void* beta_sample, const void* b
                      const mc_camera* cams, const mc_params* params, double* images, mc_stats* stats,
                      void* hip_stream) {
     int rc = validate(grid, beta_sample, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!beta_eval || !images) return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
@@ -1579,6 +1608,7 @@ int mc_render_mixture(const mc_grid* grid, const double* beta_air, const double*
                       int n_cams, const mc_camera* cams, const mc_params* params, double* images, double* images_m2,
                       mc_stats* stats, void* hip_stream) {
     int rc = validate(grid, beta_air, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!beta_aer || !images || !(sigma > 0.0) || !std::isfinite(sigma)) return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
@@ -1597,6 +1627,7 @@ int mc_grad_mixture(const mc_grid* grid, const double* beta_air, const double* b
                     const mc_camera* cams, const mc_params* params, const double* dl_dimages, int full,
                     double* grad_beta_aer, mc_stats* stats, void* hip_stream) {
     int rc = validate(grid, beta_air, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!beta_aer || !dl_dimages || !grad_beta_aer || !(sigma > 0.0) || !std::isfinite(sigma) ||
         (full != 0 && full != 1))
@@ -1756,6 +1787,7 @@ int mc_recover(const mc_grid* grid, double* beta, int n_cams, const mc_camera* c
                int rays_per_side, const double* measured, const double* mask, const double* w_layer, double eta,
                double delta, int n_gd, int n_outer, int conditioned, double* cost, void* hip_stream) {
     int rc = validate(grid, beta, n_cams, cams, params);
+    if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!measured || params->tally != MC_TALLY_F64 || rays_per_side < 1 || rays_per_side > 64 || n_gd < 1 ||
         n_outer < 0 || !std::isfinite(eta) || !std::isfinite(delta))
@@ -1874,7 +1906,7 @@ int mc_trace_paths(const mc_grid* grid, const void* beta, int n_cams, const mc_c
     if (pix && !is_device_ptr(pix)) return MC_ERR_INVALID_ARG;
     if (count == 0) return MC_OK;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    if (params->transport == MC_FP64)
+    if (params->transport != MC_FP32)
         return run<double>(MODE_TRACE, grid, beta, n_cams, cams, params, nullptr, nullptr, nullptr, nullptr,
                            nullptr, first_pid, count, max_rec, events, pix, paths, s);
     return run<float>(MODE_TRACE, grid, beta, n_cams, cams, params, nullptr, nullptr, nullptr, nullptr, nullptr,

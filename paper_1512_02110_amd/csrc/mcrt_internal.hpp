@@ -99,6 +99,11 @@ struct KArgs {
     int frozen;                 // frozen-event render: C *= beta_le / beta at the collision
     const Real* beta;           // the library's copy: n_vox values, then zeros
                                 // (beta[n_vox] is fetched for empty voxels)
+    // mixed precision (Real = double): the connection rays walk beta_w32, a
+    // float copy of beta (then its zeros), on the grid G32 in float
+    int walk32;
+    const float* beta_w32;
+    DevGrid<float> G32;
     const DevCam<Real>* cams;
     int n_cams;
     Real wsx, wsy, wsz;     // sun propagation direction
@@ -143,9 +148,9 @@ struct KArgs {
     mc_path* paths;
 };
 
-// LDS budget of the occupancy bitmask: 16 KB (131072 bits) for FP32
-// transport, so that four 256-thread blocks fit a CU's 160 KB of LDS; 32 KB
-// for FP64 transport (two blocks per CU, register bound).
+// LDS budget of the occupancy bitmask: 16 KB (131072 bits) for FP32 and
+// mixed-precision transport, so that four 256-thread blocks fit a CU's 160 KB
+// of LDS; 32 KB for FP64 transport (two blocks per CU, register bound).
 constexpr int MASK_WORDS_FP32 = 4096;
 constexpr int MASK_WORDS = 8192;
 constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)

@@ -268,11 +268,56 @@ __device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* ma
     return A.beta[k];
 }
 
-// The same value as one unconditional load, so that the loaded register can
-// stay in flight across a step without a select or a copy.
+// What the walk of a connection ray reads: the extinction it walks (the
+// library's copy of beta followed by zeros and, for a mixture, the air
+// column), the grid, both in the walk's precision W, and the occupancy
+// bitmask's run shift.  W is the transport precision, except in mixed
+// precision (photon state in FP64), where the connection rays walk a float
+// copy of beta on the grid in float.
+template <typename W>
+struct WalkCtx {
+    const W* beta;
+    DevGrid<W> G;
+    uint32_t n_vox;
+    int msh;
+    uint32_t air_base, air_step;
+    // where a voxel of an empty run in layer iz reads its extinction
+    __device__ __forceinline__ uint32_t empty(int iz) const { return air_base + (uint32_t)iz * air_step; }
+    __device__ __forceinline__ bool occ(const uint32_t* mask, int k) const {
+        const uint32_t cell = (uint32_t)k >> msh;
+        return (mask[cell >> 5] >> (cell & 31u)) & 1u;
+    }
+    // the extinction of voxel k (layer iz) as one unconditional load, so that
+    // the loaded register can stay in flight across a step without a select
+    __device__ __forceinline__ W load(const uint32_t* mask, int k, int iz) const {
+        return beta[occ(mask, k) ? (uint32_t)k : empty(iz)];
+    }
+};
+
+template <typename Real, bool W32>
+struct WalkPrec {
+    using type = Real;
+};
 template <typename Real>
-__device__ __forceinline__ Real beta_load(const KArgs<Real>& A, const uint32_t* mask, int k, int iz) {
-    return A.beta_le[occupied(A, mask, k) ? (uint32_t)k : empty_index(A, iz)];
+struct WalkPrec<Real, true> {
+    using type = float;
+};
+
+template <typename Real, bool W32>
+__device__ __forceinline__ WalkCtx<typename WalkPrec<Real, W32>::type> walk_ctx(const KArgs<Real>& A) {
+    WalkCtx<typename WalkPrec<Real, W32>::type> C;
+    if constexpr (W32) {
+        C.beta = A.beta_w32;
+        C.G = A.G32;
+    } else {
+        C.beta = A.beta_le;
+        C.G = A.G;
+    }
+    C.n_vox = (uint32_t)A.n_vox;
+    C.msh = A.msh;
+    C.air_base = A.air_base;
+    C.air_step = A.air_step;
+    return C;
 }
 
 // ---------------------------------------------------------------------------
@@ -625,7 +670,7 @@ struct Job {
 // AIRZ: the empty runs read the air column by layer (a mixture whose air
 // depends on the height only), so the walk tracks its layer.
 template <typename Real, int PH, bool AIRZ>
-__device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* mask, uint32_t msh5, Job<Real>& J) {
+__device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t* mask, uint32_t msh5, Job<Real>& J) {
     Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
     Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
     Real& Ln = PH == 0 ? J.L0 : (PH == 1 ? J.L1 : J.L2);  // slot n
@@ -647,21 +692,21 @@ __device__ __forceinline__ bool job_step3(const KArgs<Real>& A, const uint32_t* 
     W.tx = W.rx * W.gx;
     W.ty = W.ry * W.gy;
     W.tz = W.rz * W.gz;
-    const bool done = last || (uint32_t)W.k >= (uint32_t)A.n_vox;
+    const bool done = last || (uint32_t)W.k >= C.n_vox;
     J.r = done ? tend : J.r;
     // branch free: voxel 0 is a valid index to test when the ray is done
     const uint32_t kk = done ? 0u : (uint32_t)W.k;
-    const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> A.msh, 1u) != 0u;
+    const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> C.msh, 1u) != 0u;
     if (AIRZ)
-        bo = A.beta_le[done ? (uint32_t)A.n_vox : (occ ? kk : empty_index(A, W.iz))];
+        bo = C.beta[done ? C.n_vox : (occ ? kk : C.empty(W.iz))];
     else
-        bo = A.beta_le[(done || !occ) ? (uint32_t)A.n_vox : kk];
+        bo = C.beta[(done || !occ) ? C.n_vox : kk];
     return done;
 }
 
 template <typename Real>
-__device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* mask, Job<Real>& J) {
-    const Real texit = conn_begin(J.W, A.G, J.i0x, J.i0y, J.i0z, J.f0x, J.f0y, J.f0z, J.vx, J.vy, J.vz);
+__device__ __forceinline__ void job_begin(const WalkCtx<Real>& C, const uint32_t* mask, Job<Real>& J) {
+    const Real texit = conn_begin(J.W, C.G, J.i0x, J.i0y, J.i0z, J.f0x, J.f0y, J.f0z, J.vx, J.vy, J.vz);
     if (texit < (Real)0) {
         // cannot start: the first step ends the walk with zero length
         J.r = (Real)0;
@@ -669,7 +714,7 @@ __device__ __forceinline__ void job_begin(const KArgs<Real>& A, const uint32_t* 
     } else {
         J.r = fmin(J.r, texit);
     }
-    J.b0 = J.phase == 2 ? (Real)0 : beta_load(A, mask, J.W.k, J.W.iz);
+    J.b0 = J.phase == 2 ? (Real)0 : C.load(mask, J.W.k, J.W.iz);
     J.b1 = J.b2 = (Real)0;
     J.L0 = J.L1 = J.L2 = J.lp = (Real)0;
     J.tau = 0.0;
@@ -713,9 +758,9 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
 // Tally of a finished ray.  For the gradient, a finished first walk with a
 // non-zero weight starts the second walk (returns true: the lane stays busy);
 // for the tape, such a ray is marked for the tape (rec) instead.
-template <typename Real, int MODE, int TALLY>
-__device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad, Job<Real>& J,
-                                           uint64_t& vconn, bool& rec) {
+template <typename Real, typename W, int MODE, int TALLY>
+__device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const WalkCtx<W>& C, const uint32_t* mask,
+                                           double* lds_grad, Job<W>& J, uint64_t& vconn, bool& rec) {
     if (MODE == MODE_GRAD && J.phase == 2) return false;
     if (MODE == MODE_GRAD) {
         vconn += J.steps;
@@ -729,31 +774,33 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
     }
     // (the tape replay of a mixture queues an air collision's estimates with
     // pre negated, the mark its ray record carries)
-    const Real pre = MODE == MODE_TAPE ? (Real)fabs(J.pre) : J.pre;
-    const double C = (double)pre * (double)m_exp((Real)(-J.tau));
+    const W pre = MODE == MODE_TAPE ? (W)fabs(J.pre) : J.pre;
+    // (mixed precision: the transmittance in FP64, as the FP64 kernel has it)
+    const double tr = sizeof(W) < sizeof(Real) ? exp(-J.tau) : (double)m_exp((W)(-J.tau));
+    const double ce = (double)pre * tr;
     if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
-        tally_f64<TALLY>(A.img, A.img32, J.pix, C);
-        if (A.img_m2) unsafeAtomicAdd(A.img_m2 + J.pix, C * C);
+        tally_f64<TALLY>(A.img, A.img32, J.pix, ce);
+        if (A.img_m2) unsafeAtomicAdd(A.img_m2 + J.pix, ce * ce);
         if (MODE == MODE_RTAPE) {
-            J.a = C;
-            rec = C != 0.0;
+            J.a = ce;
+            rec = ce != 0.0;
         }
         return false;
     } else if (MODE == MODE_TAPE) {
-        J.a = J.gwp * C;
+        J.a = J.gwp * ce;
         // full gradient of a mixture: a = gw C summed per collision
         if (A.mix_rows && J.a != 0.0) unsafeAtomicAdd(A.mix_rows + J.evi, J.a);
         if (A.mix_aer) J.a = A.mix_sig * J.a;  // the aerosol field's derivative of beta
         rec = J.a != 0.0;
         return false;
     } else {
-        const double a = A.gw[J.pix] * C;
+        const double a = A.gw[J.pix] * ce;
         if (a == 0.0) return false;
         const int ke = J.i0x + A.G.nx * J.i0y + A.G.nxy * J.i0z;
         grad_add<Real, TALLY>(A, lds_grad, ke, a / (double)A.beta[ke]);
         J.a = a;
         J.phase = 2;
-        job_begin(A, mask, J);
+        job_begin(C, mask, J);
         return true;
     }
 }
@@ -763,8 +810,8 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const uint32_t*
 // a later load also waits for these stores, so they are made once per
 // batch, not per tile).  w_used counts the wavefront's rays, also past the
 // end of its slice (the host then replays the chunk smaller).
-template <typename Real>
-__device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>& J, bool rec, uint32_t& w_used,
+template <typename Real, typename W>
+__device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<W>& J, bool rec, uint32_t& w_used,
                                            uint32_t w_first) {
     const unsigned long long m = __ballot(rec);
     if (!m) return;
@@ -787,18 +834,18 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<Real>
 
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
-template <typename Real, int MODE, int TALLY, bool AIRZ>
-__device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask, double* lds_grad,
-                                      JobQueue<Real, MODE>& Q, uint32_t& qhead, uint32_t qtail, Job<Real>& J, bool& busy,
-                                      bool& fin, bool final_pass, uint64_t& vconn, uint64_t& vconn_w,
-                                      uint32_t& w_used, uint32_t w_first) {
+template <typename Real, typename W, int MODE, int TALLY, bool AIRZ>
+__device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C, const uint32_t* mask,
+                                      double* lds_grad, JobQueue<W, MODE>& Q, uint32_t& qhead, uint32_t qtail,
+                                      Job<W>& J, bool& busy, bool& fin, bool final_pass, uint64_t& vconn,
+                                      uint64_t& vconn_w, uint32_t& w_used, uint32_t w_first) {
     for (;;) {
         bool rec = false;
         if (fin) {
             fin = false;
-            busy = job_finish<Real, MODE, TALLY>(A, mask, lds_grad, J, vconn, rec);
+            busy = job_finish<Real, W, MODE, TALLY>(A, C, mask, lds_grad, J, vconn, rec);
         }
-        if (MODE == MODE_TAPE || MODE == MODE_RTAPE) tape_write(A, J, rec, w_used, w_first);
+        if constexpr (MODE == MODE_TAPE || MODE == MODE_RTAPE) tape_write(A, J, rec, w_used, w_first);
         const uint32_t count = qtail - qhead;
         const uint32_t nbusy = (uint32_t)__popcll(__ballot(busy));
         if (final_pass ? (count + nbusy == 0) : (count + nbusy < (uint32_t)WAVE)) break;
@@ -827,7 +874,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
                         if (A.mix_rows) J.evi = Q.evi[slot];
                     }
                     J.phase = 1;
-                    job_begin(A, mask, J);
+                    job_begin(C, mask, J);
                     busy = true;
                 }
             }
@@ -837,7 +884,7 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
         // queued), in pairs (gradient) or triples of steps (a job always
         // starts with step 0)
         const uint32_t keep = (qtail - qhead) > 0 ? (uint32_t)WAVE - REFILL_IDLE : 0u;
-        if (MODE == MODE_GRAD) {
+        if constexpr (MODE == MODE_GRAD) {
             while ((uint32_t)__popcll(__ballot(busy)) > keep) {
                 if (busy) {
                     const bool d = job_step<Real, MODE, TALLY, 0>(A, mask, lds_grad, J);
@@ -852,20 +899,20 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
             }
         } else {
             // voxel steps are counted per wavefront: the busy lanes of each step
-            const uint32_t msh5 = (uint32_t)A.msh + 5u;
+            const uint32_t msh5 = (uint32_t)C.msh + 5u;
             bool b = busy, f = fin;  // (local copies stay lane masks)
             for (;;) {
                 const uint32_t n0 = (uint32_t)__popcll(__ballot(b));
                 if (n0 <= keep) break;
-                const bool d0 = job_step3<Real, 0, AIRZ>(A, mask, msh5, J);
+                const bool d0 = job_step3<W, 0, AIRZ>(C, mask, msh5, J);
                 f = f || (b && d0);
                 b = b && !d0;
                 const uint32_t n1 = (uint32_t)__popcll(__ballot(b));
-                const bool d1 = job_step3<Real, 1, AIRZ>(A, mask, msh5, J);
+                const bool d1 = job_step3<W, 1, AIRZ>(C, mask, msh5, J);
                 f = f || (b && d1);
                 b = b && !d1;
                 const uint32_t n2 = (uint32_t)__popcll(__ballot(b));
-                const bool d2 = job_step3<Real, 2, AIRZ>(A, mask, msh5, J);
+                const bool d2 = job_step3<W, 2, AIRZ>(C, mask, msh5, J);
                 f = f || (b && d2);
                 b = b && !d2;
                 vconn_w += n0 + n1 + n2;
@@ -877,12 +924,14 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const uint32_t* mask
 }
 
 // Wavefronts per SIMD the compiler must leave room for: 4 (at most 128
-// VGPRs) for the FP32 kernels, which are latency bound and gain more from a
-// fourth wavefront than they lose to the tighter register budget; the FP64
-// kernels keep their registers.
-template <typename Real, int MODE>
+// VGPRs) for the FP32 kernels and the mixed-precision render, which are
+// latency bound and gain more from a fourth wavefront than they lose to the
+// tighter register budget (the mixed render then spills some of its FP64
+// photon state in the photon phase and is still 2% faster than with three);
+// the FP64 kernels keep their registers.
+template <typename Real, int MODE, bool W32 = false>
 struct RenderWaves {
-    static constexpr int value = sizeof(Real) == 4 && MODE != MODE_TRACE && MODE != MODE_BMC ? 4 : 1;
+    static constexpr int value = (sizeof(Real) == 4 && MODE != MODE_TRACE && MODE != MODE_BMC) || W32 ? 4 : 1;
 };
 
 // Threads per block: 512 for the gradient, whose privatised copy of the
@@ -895,12 +944,17 @@ struct RenderThreads {
 
 // Dynamic LDS of k_render: the occupancy bitmask (mask_words), then, when
 // the gradient is privatised, one double per voxel.
-template <typename Real, int MODE, int TALLY, bool AIRZ = false>
-__global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Real, MODE>::value))
+//
+// W32 (mixed precision, Real = double): the photons fly, collide and
+// scatter in FP64 exactly as in the FP64 kernel, while the connection rays
+// walk a float copy of beta in FP32 (optical depths still summed in FP64).
+template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false>
+__global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Real, MODE, W32>::value))
     k_render(KArgs<Real> A) {
+    using W = typename WalkPrec<Real, W32>::type;
     constexpr int NT = RenderThreads<MODE>::value;
     constexpr int NW = NT / WAVE;
-    __shared__ JobQueue<Real, MODE> s_q[NW];
+    __shared__ JobQueue<W, MODE> s_q[NW];
     __shared__ unsigned long long s_st[ST_N];
     extern __shared__ uint32_t s_dyn[];
     uint32_t* s_mask = s_dyn;
@@ -913,10 +967,11 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     for (int i = threadIdx.x; i < A.mask_words; i += NT) s_mask[i] = A.mask[i];
     __syncthreads();
     const uint32_t* mask = s_mask;
-    JobQueue<Real, MODE>& Q = s_q[threadIdx.x / WAVE];
+    JobQueue<W, MODE>& Q = s_q[threadIdx.x / WAVE];
+    const WalkCtx<W> C = walk_ctx<Real, W32>(A);
 
     Photon<Real> ph;
-    Job<Real> J{};
+    Job<W> J{};
     bool alive = false, exhausted = false, busy = false, fin = false;
     uint64_t pool_next = 0, pool_end = 0;
     uint32_t qhead = 0, qtail = 0;
@@ -962,7 +1017,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 if (A.mix_air) ph.air = mix_particle(A, ph);
             }
         }
-        if (MODE == MODE_VOXEL) {
+        if constexpr (MODE == MODE_VOXEL) {
             const unsigned long long cm = __ballot(collided);
             if (cm && A.n_cams > 0) voxel_tally<Real, MODE>(A, Q, ph, collided, cm, v_e0, v_c0, v_estep, v_cstep, n_le);
         } else if (__ballot(collided)) {
@@ -998,7 +1053,8 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
+                    drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn,
+                                                      vconn_w, w_used, w_first);
             }
         }
         if (collided) {
@@ -1008,9 +1064,11 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 alive = false;
             }
         }
-        drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w, w_used, w_first);
+        drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w,
+                                          w_used, w_first);
     }
-    drain<Real, MODE, TALLY, AIRZ>(A, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used, w_first);
+    drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used,
+                                      w_first);
 
     if ((MODE == MODE_TAPE || MODE == MODE_RTAPE) && __lane_id() == 0) {
         A.tp.wave_count[wave_id] = w_used;
@@ -2049,11 +2107,11 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
     return bytes;
 }
 
-template <typename Real, int MODE, int TALLY, bool AIRZ = false>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false>
 static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
     const size_t dyn = render_dyn_lds(a, MODE);
-    hipLaunchKernelGGL((k_render<Real, MODE, TALLY, AIRZ>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn, s,
-                       a);
+    hipLaunchKernelGGL((k_render<Real, MODE, TALLY, AIRZ, W32>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn,
+                       s, a);
     return hipGetLastError();
 }
 
@@ -2065,6 +2123,11 @@ hipError_t launch_mix_path(const KArgs<Real>& a, int grid, hipStream_t s) {
 
 template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s) {
+    if constexpr (sizeof(Real) == 8) {
+        if (mode == MODE_RENDER && a.walk32)
+            return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, false, true>(a, grid, s)
+                                      : launch_r<Real, MODE_RENDER, TALLY_K32, false, true>(a, grid, s);
+    }
     if (mode == MODE_RENDER && a.air_step) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, true>(a, grid, s)
                                   : launch_r<Real, MODE_RENDER, TALLY_K32, true>(a, grid, s);
@@ -2097,14 +2160,19 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
     return hipGetLastError();
 }
 
-template <typename Real, int MODE, int TALLY, bool AIRZ = false>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false>
 static hipError_t occ_r(const KArgs<Real>& a, int* b) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY, AIRZ>,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(b, (const void*)k_render<Real, MODE, TALLY, AIRZ, W32>,
                                                         RenderThreads<MODE>::value, render_dyn_lds(a, MODE));
 }
 
 template <typename Real>
 hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b) {
+    if constexpr (sizeof(Real) == 8) {
+        if (mode == MODE_RENDER && a.walk32)
+            return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, false, true>(a, b)
+                                      : occ_r<Real, MODE_RENDER, TALLY_K32, false, true>(a, b);
+    }
     if (mode == MODE_RENDER && a.air_step)
         return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, true>(a, b)
                                   : occ_r<Real, MODE_RENDER, TALLY_K32, true>(a, b);

@@ -26,9 +26,10 @@ LIB_PATH = os.path.join(PKG, "libmcrt.so")
 
 MC_OK, MC_ERR_INVALID_ARG, MC_ERR_NO_DEVICE, MC_ERR_HIP, MC_ERR_OUT_OF_MEMORY = 0, -1, -2, -3, -4
 MC_ERR_SCRATCH_LIMIT = -5
-MC_FP32, MC_FP64 = 0, 1
+MC_FP32, MC_FP64, MC_MIXED = 0, 1, 2
 MC_TALLY_F64, MC_TALLY_KAHAN32 = 0, 1
-TRANSPORTS = {"fp32": MC_FP32, "fp64": MC_FP64}
+# "mixed": photons in FP64, connection rays walked in FP32 (beta given in FP64)
+TRANSPORTS = {"fp32": MC_FP32, "fp64": MC_FP64, "mixed": MC_MIXED}
 TALLIES = {"f64": MC_TALLY_F64, "kahan32": MC_TALLY_KAHAN32}
 
 
@@ -213,7 +214,7 @@ def beta_tensor(s, transport="fp32", beta=None, device="cuda"):
     """Device copy of the scene's extinction in the dtype the transport reads."""
     torch = _torch()
     b = s.beta if beta is None else beta
-    dt = torch.float32 if transport == "fp32" else torch.float64
+    dt = torch.float32 if transport == "fp32" else torch.float64  # (mixed: FP64 beta)
     if isinstance(b, torch.Tensor):
         return b.detach().to(device=device, dtype=dt).contiguous().reshape(-1)
     return torch.as_tensor(np.ascontiguousarray(b).reshape(-1), dtype=dt, device=device)

@@ -1,0 +1,134 @@
+"""Transport precisions against each other and the oracle, through the C ABI.
+
+Mixed precision (photons in FP64, connection rays walked in FP32 over a float
+copy of beta): its photon paths, counters and pixel choices are those of the
+FP64 transport, so against the FP64 oracle and the FP64 GPU render the only
+difference is the FP32 rounding of the connection rays' optical depths
+(relative error of a local estimate about 1e-7 times its optical depth);
+every pixel is held to 1e-4 relative, the metric's bound, on the full
+64^3 / 9-camera / 1e8-photon launch of the benchmark, and to 1e-5 on the
+small scenes.
+
+All-FP32 transport on the same full launch: paths diverge from the FP64 ones
+for about 2e-4 of the photons and a local estimate lands in a neighbouring
+pixel about once per 1e5 estimates (FP32 drift of the photon state), which
+the per-pixel bound max(1e-4, 3 sigma_MC) covers, sigma from both renders'
+second moments."""
+import numpy as np
+import pytest
+
+from paper_1512_02110_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+COUNTERS = ("photons", "events", "le_jobs", "vox_free", "esc_top", "esc_bottom", "esc_side", "rr_killed", "capped")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1512_02110_amd import mcrt
+    mcrt.load_library()
+    return mcrt
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+@pytest.mark.parametrize("n", [1, 5003, 40000])
+def test_mixed_matches_oracle_config1(M, oracle, n):
+    s = scenes.config1(n_photons=n)
+    print(f"case mixed vs oracle c1 n={n}", flush=True)
+    img, st = M.mc_render(s, M.beta_tensor(s, "mixed"), transport="mixed")
+    ref, rst = oracle.render(s)
+    for k in COUNTERS:
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    # lattice cameras on voxel corners: zero-length end voxels are rounding's call
+    assert abs(st["vox_conn"] - rst["vox_conn"]) <= 2 * rst["le_jobs"]
+    img = img.cpu().numpy()
+    nz = np.abs(ref) > 0
+    assert not (np.abs(img) > 0)[~nz].any()
+    assert _rel(img[nz], ref[nz]).max(initial=0.0) <= 1e-5
+
+
+def test_mixed_matches_oracle_random_scenes(M, oracle):
+    rng = np.random.default_rng(77)
+    for i in range(5):
+        s = scenes.random_scene(rng, n_photons=int(rng.integers(1, 4000)))
+        print(f"case mixed random scene {i}: {s.nx}x{s.ny}x{s.nz} cams={s.n_cams} n={s.n_photons}", flush=True)
+        img, st = M.mc_render(s, M.beta_tensor(s, "mixed"), transport="mixed")
+        ref, rst = oracle.render(s)
+        for k in COUNTERS:
+            assert st[k] == rst[k], (i, k, st[k], rst[k])
+        img = img.cpu().numpy()
+        nz = np.abs(ref) > 0
+        assert _rel(img[nz], ref[nz]).max(initial=0.0) <= 1e-5, i
+        assert np.abs(img[~nz]).max(initial=0.0) <= 1e-12 * np.abs(ref).max(initial=1.0)
+
+
+def test_mixed_paths_are_the_fp64_paths(M):
+    s = scenes.config2(n_photons=1)
+    print("case mixed traces = fp64 traces (c2, 20000 photons)", flush=True)
+    b = M.beta_tensor(s, "fp64")
+    ev_m, p_m, pix_m = M.mc_trace_paths(s, b, 0, 20000, 12, transport="mixed")
+    ev_d, p_d, pix_d = M.mc_trace_paths(s, b, 0, 20000, 12, transport="fp64")
+    assert np.array_equal(p_m, p_d)
+    assert np.array_equal(ev_m, ev_d)
+    assert np.array_equal(pix_m, pix_d)
+
+
+def test_mixed_gradient_is_the_fp64_gradient(M):
+    import torch
+    s = scenes.config2(n_photons=30000)
+    print("case mixed gradient = fp64 gradient (c2, 3e4 photons)", flush=True)
+    b = M.beta_tensor(s, "fp64")
+    dl = torch.as_tensor(np.random.default_rng(1).normal(size=M.n_pixels(s)), device="cuda")
+    gm, sm = M.mc_grad_beta(s, b, dl, transport="mixed")
+    gd, sd = M.mc_grad_beta(s, b, dl, transport="fp64")
+    assert sm == sd
+    gm, gd = gm.cpu().numpy(), gd.cpu().numpy()
+    assert np.allclose(gm, gd, rtol=1e-10, atol=1e-13 * np.abs(gd).max())
+    # a mixed-precision render keeps no rays; the noalloc render takes it too
+    img, _, tape = M.mc_render_tape(s, b, transport="mixed")
+    assert tape is None
+    img2, _ = M.mc_render_noalloc(s, b, transport="mixed")
+    assert torch.allclose(img, img2, rtol=1e-12, atol=1e-15 * img.abs().max().item())
+
+
+def test_mixed_rejected_where_unsupported(M):
+    s = scenes.config1(n_photons=100)
+    b = M.beta_tensor(s, "fp64")
+    with pytest.raises(M.McError) as e:
+        M.mc_bmc_render(s, b, 2, transport="mixed")
+    assert e.value.code == M.MC_ERR_INVALID_ARG
+    with pytest.raises(M.McError):
+        M.mc_voxel_scatter(s, b, transport="mixed")
+
+
+def test_full_size_config2_precisions(M):
+    """The benchmark's launch (1e8 photons on the 64^3 grid with 9 cameras of
+    128^2): mixed precision within 1e-4 of FP64 in every pixel, with the FP64
+    counters; all-FP32 within max(1e-4, 3 sigma) in every pixel."""
+    s = scenes.config2()
+    print("case c2 full size: fp64, mixed, fp32 (1e8 photons each)", flush=True)
+    b64 = M.beta_tensor(s, "fp64")
+    i64, m64, s64 = M.mc_render_moments(s, b64, transport="fp64", seed=1000)
+    imx, smx = M.mc_render(s, b64, transport="mixed", seed=1000)
+    for k in COUNTERS:
+        assert smx[k] == s64[k], (k, smx[k], s64[k])
+    i64n, imx = i64.cpu().numpy(), imx.cpu().numpy()
+    nz = np.abs(i64n) > 0
+    assert not (np.abs(imx) > 0)[~nz].any()
+    rel = _rel(imx[nz], i64n[nz])
+    print(f"mixed vs fp64: max rel {rel.max():.3e}, median {np.median(rel):.3e}", flush=True)
+    assert rel.max() <= 1e-4
+    del imx
+    i32, m32, _ = M.mc_render_moments(s, M.beta_tensor(s, "fp32"), transport="fp32", seed=1000)
+    i32, m32, m64 = i32.cpu().numpy(), m32.cpu().numpy(), m64.cpu().numpy()
+    sig = np.sqrt(np.maximum(m32 + m64 - 2 * i64n ** 2 / s.n_photons, 0.0))
+    bad = np.abs(i32 - i64n) > np.maximum(1e-4 * np.abs(i64n), 3 * sig)
+    print(f"fp32 vs fp64: {(_rel(i32[nz], i64n[nz]) <= 1e-4).mean():.4f} of pixels within 1e-4", flush=True)
+    assert not bad.any(), np.flatnonzero(bad)[:10]
