@@ -63,39 +63,63 @@ def measured_traffic():
     return float(b.group(1))
 
 
-def _cpu_worker(args):
-    cfg, n, offset = args
-    from oracle import oracle as O
-    from paper_1512_02110_amd import scenes
-    s = scenes.CONFIGS[cfg](n_photons=n)
-    t0 = time.perf_counter()
-    _, st = O.render(s, n_photons=n, photon_offset=offset)
-    return st["events"], time.perf_counter() - t0
+# one CPU worker: the oracle over a photon range; prints "events seconds"
+_CPU_WORKER = """
+import sys, time
+sys.path.insert(0, {root!r})
+from oracle import oracle as O
+from paper_1512_02110_amd import scenes
+s = scenes.CONFIGS[{cfg!r}](n_photons={n})
+t0 = time.perf_counter()
+_, st = O.render(s, n_photons={n}, photon_offset={off})
+print(st["events"], time.perf_counter() - t0)
+"""
 
 
 def _cpu_model():
-    """The host CPU's model name (Linux), or None."""
+    """The host CPU as lscpu (or /proc/cpuinfo) describes it."""
+    import subprocess
+    info = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Vendor ID", "CPU family", "Model", "CPU(s)", "Thread(s) per core",
+                             "Core(s) per socket", "Socket(s)", "CPU max MHz", "Hypervisor vendor"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return None
+    if "Model name" not in info:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return info
 
 
 def cpu_baseline(cfg, per_proc, procs):
-    """The oracle as it stands, P independent processes over disjoint photon
-    ranges (one thread each)."""
-    from concurrent.futures import ProcessPoolExecutor
-    import multiprocessing as mp
+    """The oracle as it stands, P independent single-threaded processes over
+    disjoint photon ranges (plain child processes, all ended before the GPU
+    work starts)."""
+    import subprocess
     from oracle import oracle as O
     O.lib()  # build if needed, before the workers start
-    jobs = [(cfg, per_proc, i * per_proc) for i in range(procs)]
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as ex:
-        res = list(ex.map(_cpu_worker, jobs))
+    kids = [subprocess.Popen([sys.executable, "-c", _CPU_WORKER.format(root=ROOT, cfg=cfg, n=per_proc,
+                                                                      off=i * per_proc)],
+                             stdout=subprocess.PIPE, text=True, env=dict(os.environ, OMP_NUM_THREADS="1"))
+            for i in range(procs)]
+    res = []
+    for k in kids:
+        o, _ = k.communicate()
+        if k.returncode != 0:
+            raise RuntimeError(f"CPU oracle worker failed ({k.returncode})")
+        ev, sec = o.split()
+        res.append((int(ev), float(sec)))
     wall = time.perf_counter() - t0
     events = sum(r[0] for r in res)
     cpu_s = sum(r[1] for r in res)
@@ -103,7 +127,130 @@ def cpu_baseline(cfg, per_proc, procs):
             "sample": f"{cfg} workload, photon ids 0..{procs * per_proc - 1} split over {procs} "
                       f"single-threaded processes ({per_proc} photons each), FP64",
             "events": events, "wall_s": round(wall, 3), "cpu_s": round(cpu_s, 3),
-            "per_core": events / cpu_s, "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
+            "cpu_s_per_process_min": round(min(r[1] for r in res), 3),
+            "per_core": events / cpu_s, "cpu": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def _pixel_errors(np, img, ref, sig=None):
+    """Per-pixel relative errors of img against ref (pixels where ref > 0)."""
+    diff = np.abs(img - ref)
+    nz = np.abs(ref) > 0
+    rel = diff[nz] / np.abs(ref)[nz]
+    out = {"frac_pixels_within_1e-4_rel": float((rel <= 1e-4).mean()) if rel.size else 1.0,
+           "pixels_over_1e-4_rel": int((rel > 1e-4).sum()),
+           "pixel_rel_err_median": float(np.median(rel)) if rel.size else 0.0,
+           "pixel_rel_err_max": float(rel.max()) if rel.size else 0.0,
+           "image_rel_l1": float(diff.sum() / max(np.abs(ref).sum(), 1e-300)),
+           "nonzero_where_ref_zero": int((np.abs(img) > 0)[~nz].sum())}
+    if sig is not None:
+        out["frac_pixels_within_max_1e-4_rel_3sigma"] = float((diff <= np.maximum(1e-4 * np.abs(ref), 3 * sig)).mean())
+    return out
+
+
+def precisions(M, torch, np, s, classes=True, seed=1000):
+    """FP32, mixed and FP64 transport on the same photons (seed 1000): kernel
+    times (HIP events on the launch stream, one warm-up each) and per-pixel
+    errors against FP64; sigma of a pixel from both renders' second moments.
+    With `classes`, the FP32 differences are split by photon: photons whose
+    path differs from FP64 (collisions, fate or exit point; traced for all N),
+    photons with the same path but a local estimate in another pixel (the
+    first 64 collisions of each traced; photons with more are counted as
+    unchecked), and the rest: both images without the first two kinds (and the
+    unchecked) are compared again."""
+    b32, b64 = M.beta_tensor(s, "fp32"), M.beta_tensor(s, "fp64")
+    N = s.n_photons
+    res = {}
+    for t, b in (("fp32", b32), ("mixed", b64), ("fp64", b64)):
+        M.mc_render(s, b, transport=t, seed=7, n_photons=min(N, 10_000_000), stats=False)
+        img, st = M.mc_render(s, b, transport=t, seed=seed)
+        res[t] = (img, st, st.timing["transport_ms"])
+    _, m2_32, _ = M.mc_render_moments(s, b32, transport="fp32", seed=seed, stats=False)
+    _, m2_64, _ = M.mc_render_moments(s, b64, transport="fp64", seed=seed, stats=False)
+    i64 = res["fp64"][0].cpu().numpy()
+    i32 = res["fp32"][0].cpu().numpy()
+    sig = np.sqrt(np.maximum(m2_32.cpu().numpy() + m2_64.cpu().numpy() - 2 * i64 ** 2 / N, 0.0))
+    del m2_32, m2_64
+    t64 = res["fp64"][2]
+    out = {"workload": f"same launch as the forward ({N:.0e} photons, seed {seed}), kernel times",
+           "fp64": {"kernel_ms": round(t64, 3), "events_per_s": res["fp64"][1]["events"] / (t64 * 1e-3)}}
+    counters = ("events", "le_jobs", "vox_free", "esc_top", "esc_bottom", "esc_side", "rr_killed", "capped")
+    for t in ("fp32", "mixed"):
+        img, st, ms = res[t]
+        r = {"kernel_ms": round(ms, 3), "events_per_s": st["events"] / (ms * 1e-3),
+             "speedup_over_fp64": round(t64 / ms, 4),
+             "counters_equal_fp64": all(st[k] == res["fp64"][1][k] for k in counters),
+             "events_minus_fp64": int(st["events"] - res["fp64"][1]["events"])}
+        r.update(_pixel_errors(np, img.cpu().numpy(), i64, sig))
+        out[t] = r
+    out["mixed"]["precision"] = "photons FP64, connection rays walked in FP32, optical depths and tallies FP64"
+    out["fp32"]["precision"] = "photons and connection rays FP32, projection, optical depths and tallies FP64"
+    if classes:
+        out["fp32"]["classes"] = fp32_classes(M, torch, np, s, b32, b64, i32, i64, sig, seed)
+    return out
+
+
+def fp32_classes(M, torch, np, s, b32, b64, i32, i64, sig, seed, chunk=2_000_000, max_rec=64):
+    N = s.n_photons
+    tol = 1e-3 * min(s.dx, s.dy, s.dz)
+    diverged, flipped, unchecked = [], [], []
+    n_est = n_flip_est = 0
+    for first in range(0, N, chunk):
+        n = min(chunk, N - first)
+        _, a, pa = M.mc_trace_paths(s, b32, first, n, max_rec, transport="fp32", seed=seed, device=True)
+        _, c, pc = M.mc_trace_paths(s, b64, first, n, max_rec, transport="fp64", seed=seed, device=True)
+        d = (a["n_events"] != c["n_events"]) | (a["fate"] != c["fate"]) | \
+            ((a["exit_pos"] - c["exit_pos"]).abs().amax(dim=1) > tol)
+        rec = (pa > -2) & (pc > -2)
+        fl = ((pa != pc) & rec)
+        f = fl.flatten(1).any(dim=1) & ~d
+        u = (c["n_events"] > max_rec) & ~d & ~f
+        n_est += int(((pc >= 0) & rec)[~d].sum())
+        n_flip_est += int(fl[~d].sum())
+        for lst, m in ((diverged, d), (flipped, f), (unchecked, u)):
+            lst += (torch.nonzero(m).flatten() + first).tolist()
+        del a, c, pa, pc, d, rec, fl, f, u
+    part = {}
+    for name, ids in (("diverged", diverged), ("flipped", flipped), ("unchecked", unchecked)):
+        acc = {t: torch.zeros(i64.size, dtype=torch.float64, device="cuda") for t in ("fp32", "fp64")}
+        for pid in ids:
+            for t, b in (("fp32", b32), ("fp64", b64)):
+                img, _ = M.mc_render(s, b, transport=t, seed=seed, n_photons=1, photon_offset=pid, n_photons_norm=N,
+                                     stats=False)
+                acc[t] += img
+        part[name] = {t: v.cpu().numpy() for t, v in acc.items()}
+    total = np.abs(i32 - i64).sum()
+    share = lambda k: float(np.abs(part[k]["fp32"] - part[k]["fp64"]).sum() / max(total, 1e-300))
+    r32 = i32 - part["diverged"]["fp32"]
+    r64 = i64 - part["diverged"]["fp64"]
+    out = {"photons": N, "diverged_photons": len(diverged), "flipped_photons": len(flipped),
+           "unchecked_photons": len(unchecked), "estimates_checked": n_est, "flipped_estimates": n_flip_est,
+           "flips_per_estimate": n_flip_est / max(n_est, 1),
+           "share_of_abs_diff": {k: share(k) for k in part},
+           "without_diverged": _pixel_errors(np, r32, r64, sig)}
+    for k in ("flipped", "unchecked"):
+        r32 = r32 - part[k]["fp32"]
+        r64 = r64 - part[k]["fp64"]
+    out["without_diverged_flipped_unchecked"] = _pixel_errors(np, r32, r64, sig)
+    return out
+
+
+def forward_c1(M, np):
+    """The 16^3 Gaussian blob (4 cameras of 32^2, 1e5 photons): the forward's
+    events/s in each transport precision (FP64 is the workload's own); kernel
+    times, the fastest of three after a warm-up."""
+    from paper_1512_02110_amd import scenes
+    s = scenes.config1()
+    out = {"workload": f"c1: 16^3 blob, 4 cameras 32x32, {s.n_photons:.0e} photons"}
+    for t in ("fp64", "mixed", "fp32"):
+        b = M.beta_tensor(s, t)
+        M.mc_render(s, b, transport=t, stats=False)
+        best = None
+        for _ in range(3):
+            _, st = M.mc_render(s, b, transport=t)
+            ms = st.timing["transport_ms"]
+            best = ms if best is None or ms < best else best
+        out[t] = {"kernel_ms": round(best, 4), "events_per_s": st["events"] / (best * 1e-3), "events": st["events"]}
+    return out
 
 
 def adjoint_c3(M, torch, np, stream, n_photons):
@@ -354,9 +501,12 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--photons", type=int, default=None)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP32 / mixed / FP64 comparison")
+    ap.add_argument("--no-precision-classes", action="store_true",
+                    help="skip the per-photon classification of the FP32 differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-photons", type=int, default=120000, help="photons per CPU process")
+    ap.add_argument("--cpu-photons", type=int, default=1_100_000,
+                    help="photons per CPU process (about 10 s of one core on the 64^3 workload)")
     ap.add_argument("--cpu-procs", type=int, default=None)
     ap.add_argument("--c3-photons", type=int, default=100_000_000)
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxelised-model section")
@@ -503,30 +653,10 @@ def main():
                                 "fwd_plus_adj_over_fwd": round((fwd_ms[0] + t_rep) / fwd_ms[0], 4)}
 
     if not args.no_fp64:
-        beta64 = M.beta_tensor(s, "fp64")
-        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a0.record(stream)
-        img64, st64 = M.mc_render(s, beta64, transport="fp64", seed=1000, stats=True)
-        a1.record(stream)
-        torch.cuda.synchronize()
-        t64 = a0.elapsed_time(a1)
-        # error bars of the same FP64 render (second moments, untimed)
-        _, m2_64, _ = M.mc_render_moments(s, beta64, transport="fp64", seed=1000, stats=False)
-        i32 = recs[0][0].cpu().numpy()
-        i64 = img64.cpu().numpy()
-        sig = np.sqrt(np.maximum(m2_64.cpu().numpy() - i64 ** 2 / s.n_photons, 0.0))
-        diff = np.abs(i32 - i64)
-        nz = np.abs(i64) > 0
-        rel = diff[nz] / np.abs(i64)[nz]
-        ok = diff <= np.maximum(1e-4 * np.abs(i64), 3 * sig)
-        out["fp64"] = {"fwd_ms": round(t64, 3), "events_per_s": st64["events"] / (t64 / 1e3),
-                       "speedup_fp32_over_fp64": round(t64 / fwd_ms[0], 3),
-                       "frac_pixels_within_max_1e-4_rel_3sigma": float(ok.mean()),
-                       "frac_pixels_within_1e-4_rel": float((rel <= 1e-4).mean()) if rel.size else 1.0,
-                       "pixel_rel_err_median": float(np.median(rel)) if rel.size else 0.0,
-                       "pixel_rel_err_max": float(rel.max()) if rel.size else 0.0,
-                       "image_rel_l1": float(diff.sum() / np.abs(i64).sum()),
-                       "events_fp32_minus_fp64": int(recs[0][1]["events"] - st64["events"])}
+        out["precision"] = precisions(M, torch, np, s, classes=not args.no_precision_classes)
+        print(f"[bench] precisions: {json.dumps(out['precision'])}", flush=True)
+    if args.config == "c2":
+        out["forward_c1"] = forward_c1(M, np)
     if not args.no_adjoint and args.config == "c2":
         out["fwd_adjoint_c3"] = adjoint_c3(M, torch, np, stream, args.c3_photons)
     if not args.no_large and not args.no_adjoint and args.config == "c2":

@@ -447,6 +447,24 @@ int mc_trace_paths(const mc_grid* grid, const void* beta, int n_cams, const mc_c
                    const mc_params* params, uint64_t first_pid, uint32_t count, uint32_t max_rec,
                    mc_event* events, int32_t* pix, mc_path* paths, void* hip_stream);
 
+/* Diagnostic export: the gather capture.  mc_render with FP32 transport and
+ * FP64 tallies (images as there) on at most max_waves wavefronts (a multiple
+ * of 4; the launch may use fewer: *n_waves, host, gets the number), in which
+ * wavefront w also stores, for its connection-walk steps first_step ..
+ * first_step + n_steps - 1, the index into the library's copy of beta that
+ * each of its 64 lanes loads on that step (lanes with no ray, or in an empty
+ * run of voxels, load the zero word after the last voxel, index nx*ny*nz):
+ * indices (device, max_waves * n_steps * 64 uint32) at
+ * [(w * n_steps + step) * 64 + lane], left untouched where a wavefront took
+ * fewer steps; wave_steps (device, max_waves uint32) gets each wavefront's
+ * number of steps.  For measuring the walk's gathers against a replay of the
+ * same addresses without the walk.  Waits for the stream when stats is
+ * non-NULL. */
+int mc_capture_gathers(const mc_grid* grid, const float* beta, int n_cams, const mc_camera* cams,
+                       const mc_params* params, double* images, uint32_t first_step, uint32_t n_steps,
+                       uint32_t max_waves, uint32_t* indices, uint32_t* wave_steps, uint32_t* n_waves,
+                       mc_stats* stats, void* hip_stream);
+
 /* Static description of a status code. */
 const char* mc_error_string(int code);
 

@@ -133,6 +133,14 @@ size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 // An air + aerosol mixture: device fields of the reference channel and the
 // channel's aerosol cross-section ratio (Eq. channelBeta).
+// The gather capture (mc_capture_gathers): where the walks' loaded indices go.
+struct CaptureArgs {
+    uint32_t* idx;
+    uint32_t* steps;
+    uint32_t first, n_steps, max_waves;
+    uint32_t n_waves;  // out: wavefronts of the launch
+};
+
 struct MixIn {
     const double* air;
     const double* aer;
@@ -397,10 +405,27 @@ struct MixPath {
     int grid;            // blocks of k_mix_path
 };
 
+// The rays per photon of the busiest wavefront last measured on this device
+// for workload key `key` (a kept render or a replay), 0 if none.
+double tape_hint(uint64_t key) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 0.0;
+    std::lock_guard<std::mutex> lock(g_mu);
+    return g_tape_key[dev] == key ? g_tape_rate[dev] : 0.0;
+}
+
+void set_tape_hint(uint64_t key, double rate) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES || !(rate > 0.0)) return;
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_tape_rate[dev] = rate;
+    g_tape_key[dev] = key;
+}
+
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
-             double* t_tape, hipStream_t stream, const MixPath* mp = nullptr) {
+             double* t_tape, hipStream_t stream, uint64_t wkey, const MixPath* mp = nullptr) {
     int rc = MC_OK;
     // device times: replay (r0, r1), binning + deposit of the last chunk (b0, b1)
     hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr;
@@ -422,10 +447,13 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     uint32_t h_over = 0;
     uint64_t P = 0, r_cap = 0, r_min = 0, done = 0, chunk = 0;
     int max_nw = 0;
+    const double hint = tape_hint(wkey);
+    double max_rate = 0.0;
 
     CHECK_HIP(available_bytes(&free_b));
     {
-        const uint64_t lim = std::min<uint64_t>(free_b / 4, (uint64_t)32 << 30) / rec;
+        // (slots are 32-bit indices: at most 2^31 - 1 records)
+        const uint64_t lim = std::min<uint64_t>(free_b / 8 * 3, (uint64_t)96 << 30) / rec;
         P = std::max<uint64_t>(n_photons * 48, (uint64_t)1 << 20);
         P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
         if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
@@ -461,8 +489,14 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         A.mix_rows = mp->rows;
         A.mix_evcap = mp->cap;
     }
-    // first chunk: a guess of 64 rays per photon
-    chunk = std::min<uint64_t>(n_photons, std::max<uint64_t>(256, r_cap / 64));
+    // first chunk: from the rays per photon measured on this workload before
+    // (busiest wavefront, with a fifth to spare, and four tile crossings per
+    // ray for the bins), else a guess of 64 rays per photon
+    if (hint > 0.0)
+        chunk = (uint64_t)std::max(256.0, std::min(0.8 * (double)r_cap / hint, (double)(P - r_cap) / (4.5 * hint)));
+    else
+        chunk = std::max<uint64_t>(256, r_cap / 64);
+    chunk = std::min<uint64_t>(n_photons, chunk);
     while (done < n_photons) {
         if (mp) chunk = std::min<uint64_t>(chunk, mp->max_chunk);
         const uint64_t n = std::min<uint64_t>(chunk, n_photons - done);
@@ -502,6 +536,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         uint32_t busiest = 0;
         for (int w = 0; w < nw; ++w) busiest = std::max(busiest, h_wave[w]);
         const double rate = (double)busiest * nw / (double)n;  // rays per photon, busiest wavefront
+        max_rate = std::max(max_rate, rate);
         uint64_t crossings = 0;
         bool too_big = h_over != 0;
         for (int i = 0; i < nt; ++i) {
@@ -545,6 +580,8 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(hipEventElapsedTime(&ms, b0, b1));
         *t_tape += ms;
     }
+    // (chunks of very few photons measure noisy rates: only large calls set the hint)
+    if (n_photons >= 65536) set_tape_hint(wkey, max_rate);
 
 done:
     for (void* p : {(void*)ditems, (void*)meta}) {
@@ -777,7 +814,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         uint64_t first_pid, uint32_t trace_count, uint32_t max_rec, mc_event* ev, int32_t* pix,
         mc_path* paths, hipStream_t stream, mc_tape** keep = nullptr, const mc_tape* src = nullptr,
         uint32_t n_pp = 0, const MixIn* mix = nullptr, const void* beta_eval = nullptr,
-        void* fixed_scratch = nullptr) {
+        void* fixed_scratch = nullptr, CaptureArgs* cap = nullptr) {
     // fixed_scratch: the no-allocation render; its scratch is the library's
     // fixed device array (NOALLOC_SCRATCH_BYTES) and the call allocates
     // nothing and creates no events
@@ -1187,7 +1224,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                 // replay (weight sig * gw * C), binned by tile
                 rc = run_tape<Real>(A, TALLY_F64, prm->n_photons, prm->photon_offset, prm->tape_limit,
                                     (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
-                                    stats ? &t_transport : nullptr, &t_tape, stream, A.mix_full ? &mp : nullptr);
+                                    stats ? &t_transport : nullptr, &t_tape, stream,
+                                    workload_key(grid, n_cams, cams, prm) ^ 0x6d6978ull, A.mix_full ? &mp : nullptr);
                 if (rc == TAPE_FALLBACK) {
                     // too little room for the records: one photon per lane,
                     // device atomics
@@ -1222,7 +1260,7 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
         std::memset(host_counters, 0, sizeof(host_counters));
         rc = run_tape<Real>(A, tally, prm->n_photons, prm->photon_offset, prm->tape_limit,
                             (int)((int64_t)n_cu * (per_cu > 0 ? per_cu : 1)), n_cu, counters, host_counters,
-                            stats ? &t_transport : nullptr, &t_tape, stream);
+                            stats ? &t_transport : nullptr, &t_tape, stream, workload_key(grid, n_cams, cams, prm));
         if (rc == TAPE_FALLBACK) {
             // tape too small even for one block: device atomics
             rc = MC_OK;
@@ -1248,7 +1286,23 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
             CHECK_HIP(hipEventCreate(&ev1));
             CHECK_HIP(hipEventRecord(ev0, stream));
         }
-        CHECK_HIP(launch_transport<Real>(A, launch_mode, tally, grid_blocks, stream));
+        if constexpr (sizeof(Real) == 4) {
+            if (cap) {
+                // the gather capture: at most max_waves wavefronts
+                grid_blocks = std::min<int>(grid_blocks, (int)(cap->max_waves / (BLOCK / 64)));
+                cap->n_waves = (uint32_t)grid_blocks * (BLOCK / 64);
+                A.capture = cap->idx;
+                A.capture_steps = cap->steps;
+                A.cap_first = cap->first;
+                A.cap_steps = cap->n_steps;
+                if (grid_blocks < 1) {
+                    rc = MC_ERR_INVALID_ARG;
+                    goto done;
+                }
+                CHECK_HIP(launch_capture(A, grid_blocks, stream));
+            }
+        }
+        if (!cap) CHECK_HIP(launch_transport<Real>(A, launch_mode, tally, grid_blocks, stream));
         if (ev1) CHECK_HIP(hipEventRecord(ev1, stream));
     }
 
@@ -1489,6 +1543,26 @@ int mc_render_noalloc(const mc_grid* grid, const void* beta, int n_cams, const m
                            0, 0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, nullptr, fixed);
     return run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0,
                       0, 0, nullptr, nullptr, nullptr, s, nullptr, nullptr, 0, nullptr, nullptr, fixed);
+}
+
+int mc_capture_gathers(const mc_grid* grid, const float* beta, int n_cams, const mc_camera* cams,
+                       const mc_params* params, double* images, uint32_t first_step, uint32_t n_steps,
+                       uint32_t max_waves, uint32_t* indices, uint32_t* wave_steps, uint32_t* n_waves,
+                       mc_stats* stats, void* hip_stream) {
+    int rc = validate(grid, beta, n_cams, cams, params);
+    if (rc != MC_OK) return rc;
+    if (params->transport != MC_FP32 || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
+    if (!images || !indices || !wave_steps || !n_waves || n_steps < 1 || max_waves < (uint32_t)(BLOCK / 64))
+        return MC_ERR_INVALID_ARG;
+    if ((rc = precheck_device()) != MC_OK) return rc;
+    if (!is_device_ptr(beta) || !is_device_ptr(images) || !is_device_ptr(indices) || !is_device_ptr(wave_steps))
+        return MC_ERR_INVALID_ARG;
+    CaptureArgs cap{indices, wave_steps, first_step, n_steps, max_waves, 0u};
+    rc = run<float>(MODE_RENDER, grid, beta, n_cams, cams, params, images, nullptr, nullptr, nullptr, stats, 0, 0, 0,
+                    nullptr, nullptr, nullptr, static_cast<hipStream_t>(hip_stream), nullptr, nullptr, 0, nullptr,
+                    nullptr, nullptr, &cap);
+    *n_waves = cap.n_waves;
+    return rc;
 }
 
 int mc_grad_beta(const mc_grid* grid, const void* beta, int n_cams, const mc_camera* cams, const mc_params* params,

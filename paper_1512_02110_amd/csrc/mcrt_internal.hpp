@@ -111,6 +111,7 @@ struct KArgs {
     uint32_t max_events;
     uint64_t seed, pid0, n_photons;
     unsigned long long* work;   // photon counter (zeroed before launch)
+    uint32_t fetch_block;       // photon ids a wavefront takes per fetch (set at launch)
     unsigned long long* stats;  // ST_N counters (zeroed before launch)
     double* img;                // raw local-estimate sums (F64 tally)
     double* img_m2;             // optional: raw sums of squared local estimates
@@ -140,6 +141,14 @@ struct KArgs {
     int grad_lds;               // gradient privatised in LDS (small grids)
     int tape;                   // gradient through the tape (large grids)
     Tape<Real> tp;
+    // gather capture (a diagnostic of the FP32 render): wavefront w stores the
+    // extinction index each lane loads on connection-walk steps
+    // cap_first .. cap_first + cap_steps - 1 of the wavefront at
+    // capture[(w cap_steps + step) 64 + lane], and its number of steps at
+    // capture_steps[w]
+    uint32_t* capture;
+    uint32_t* capture_steps;
+    uint32_t cap_first, cap_steps;
     // trace
     uint64_t first_pid;
     uint32_t trace_count, max_rec;
@@ -177,6 +186,7 @@ template <typename Real>
 hipError_t launch_write_cams(const CamChunk& chunk, DevCam<Real>* dev, NormCam* norm, hipStream_t s);
 template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s);
+hipError_t launch_capture(const KArgs<float>& a, int grid, hipStream_t s);
 template <typename Real>
 hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* blocks_per_cu);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);

@@ -73,14 +73,18 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
 }
 
 // Photon ids for the lanes in `need`, in order, from the wavefront's pool
-// [pool_next, pool_end), which is refilled FETCH_BLOCK ids at a time with
-// one atomic on the global counter (a returning device atomic takes
+// [pool_next, pool_end), which is refilled `block` ids at a time with one
+// atomic on the global counter (a returning device atomic takes
 // microseconds; one per photon phase would stall every phase).  Called by
-// the whole wavefront, so that the pool stays uniform.
-constexpr uint32_t FETCH_BLOCK = 256;
+// the whole wavefront, so that the pool stays uniform.  One refill must
+// cover every lane that still needs an id, so a block holds at least WAVE
+// ids; within that, the launch sets it so that every wavefront fetches about
+// 32 times (at most 256 ids): a launch ends with its slowest wavefront, and
+// a few large blocks per wavefront leave the others idle at the end.
+constexpr uint32_t FETCH_BLOCK_MAX = 256;
 
-__device__ __forceinline__ uint64_t wave_fetch(unsigned long long* work, unsigned long long need, uint64_t& pool_next,
-                                               uint64_t& pool_end) {
+__device__ __forceinline__ uint64_t wave_fetch(unsigned long long* work, uint32_t block, unsigned long long need,
+                                               uint64_t& pool_next, uint64_t& pool_end) {
     const uint32_t n = (uint32_t)__popcll(need);
     const uint32_t rank = lanes_below(need);
     const uint64_t left = pool_end - pool_next;
@@ -88,11 +92,11 @@ __device__ __forceinline__ uint64_t wave_fetch(unsigned long long* work, unsigne
     uint64_t id = pool_next + rank;
     if (avail < n) {
         unsigned long long base = 0;
-        if (__lane_id() == 0) base = atomicAdd(work, (unsigned long long)FETCH_BLOCK);
+        if (__lane_id() == 0) base = atomicAdd(work, (unsigned long long)block);
         const unsigned lo = __shfl((unsigned)base, 0);
         const unsigned hi = __shfl((unsigned)(base >> 32), 0);
         pool_next = ((uint64_t)hi << 32) | lo;
-        pool_end = pool_next + FETCH_BLOCK;
+        pool_end = pool_next + block;
         if (rank >= avail) id = pool_next + (rank - avail);
         pool_next += n - avail;
     } else {
@@ -670,7 +674,8 @@ struct Job {
 // AIRZ: the empty runs read the air column by layer (a mixture whose air
 // depends on the height only), so the walk tracks its layer.
 template <typename Real, int PH, bool AIRZ>
-__device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t* mask, uint32_t msh5, Job<Real>& J) {
+__device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t* mask, uint32_t msh5, Job<Real>& J,
+                                          uint32_t& ld) {
     Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
     Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
     Real& Ln = PH == 0 ? J.L0 : (PH == 1 ? J.L1 : J.L2);  // slot n
@@ -697,10 +702,8 @@ __device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t
     // branch free: voxel 0 is a valid index to test when the ray is done
     const uint32_t kk = done ? 0u : (uint32_t)W.k;
     const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> C.msh, 1u) != 0u;
-    if (AIRZ)
-        bo = C.beta[done ? C.n_vox : (occ ? kk : C.empty(W.iz))];
-    else
-        bo = C.beta[(done || !occ) ? C.n_vox : kk];
+    ld = AIRZ ? (done ? C.n_vox : (occ ? kk : C.empty(W.iz))) : ((done || !occ) ? C.n_vox : kk);
+    bo = C.beta[ld];
     return done;
 }
 
@@ -834,11 +837,14 @@ __device__ __forceinline__ void tape_write(const KArgs<Real>& A, const Job<W>& J
 
 // Job phase of one wavefront.  Not final: return once fewer jobs are queued
 // or in flight than there are lanes.  Final: run until everything is done.
-template <typename Real, typename W, int MODE, int TALLY, bool AIRZ>
+// CAP: every step of the walks stores its loaded index for the gather
+// capture (wstep counts the wavefront's steps).
+template <typename Real, typename W, int MODE, int TALLY, bool AIRZ, bool CAP = false>
 __device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C, const uint32_t* mask,
                                       double* lds_grad, JobQueue<W, MODE>& Q, uint32_t& qhead, uint32_t qtail,
                                       Job<W>& J, bool& busy, bool& fin, bool final_pass, uint64_t& vconn,
-                                      uint64_t& vconn_w, uint32_t& w_used, uint32_t w_first) {
+                                      uint64_t& vconn_w, uint32_t& w_used, uint32_t w_first, uint32_t& wstep,
+                                      uint32_t wave_id) {
     for (;;) {
         bool rec = false;
         if (fin) {
@@ -901,18 +907,29 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C,
             // voxel steps are counted per wavefront: the busy lanes of each step
             const uint32_t msh5 = (uint32_t)C.msh + 5u;
             bool b = busy, f = fin;  // (local copies stay lane masks)
+            auto capture = [&](uint32_t ld) {
+                if constexpr (CAP) {
+                    const uint32_t j = wstep - A.cap_first;
+                    if (j < A.cap_steps) A.capture[((size_t)wave_id * A.cap_steps + j) * WAVE + __lane_id()] = ld;
+                    ++wstep;
+                }
+            };
             for (;;) {
+                uint32_t ld0, ld1, ld2;
                 const uint32_t n0 = (uint32_t)__popcll(__ballot(b));
                 if (n0 <= keep) break;
-                const bool d0 = job_step3<W, 0, AIRZ>(C, mask, msh5, J);
+                const bool d0 = job_step3<W, 0, AIRZ>(C, mask, msh5, J, ld0);
+                capture(ld0);
                 f = f || (b && d0);
                 b = b && !d0;
                 const uint32_t n1 = (uint32_t)__popcll(__ballot(b));
-                const bool d1 = job_step3<W, 1, AIRZ>(C, mask, msh5, J);
+                const bool d1 = job_step3<W, 1, AIRZ>(C, mask, msh5, J, ld1);
+                capture(ld1);
                 f = f || (b && d1);
                 b = b && !d1;
                 const uint32_t n2 = (uint32_t)__popcll(__ballot(b));
-                const bool d2 = job_step3<W, 2, AIRZ>(C, mask, msh5, J);
+                const bool d2 = job_step3<W, 2, AIRZ>(C, mask, msh5, J, ld2);
+                capture(ld2);
                 f = f || (b && d2);
                 b = b && !d2;
                 vconn_w += n0 + n1 + n2;
@@ -948,7 +965,9 @@ struct RenderThreads {
 // W32 (mixed precision, Real = double): the photons fly, collide and
 // scatter in FP64 exactly as in the FP64 kernel, while the connection rays
 // walk a float copy of beta in FP32 (optical depths still summed in FP64).
-template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false>
+//
+// CAP (FP32 render only): the gather capture, a diagnostic.
+template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false, bool CAP = false>
 __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Real, MODE, W32>::value))
     k_render(KArgs<Real> A) {
     using W = typename WalkPrec<Real, W32>::type;
@@ -982,6 +1001,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     const uint32_t wave_id = blockIdx.x * NW + threadIdx.x / WAVE;
     const uint32_t w_first = MODE == MODE_TAPE || MODE == MODE_RTAPE ? wave_id * A.tp.rw : 0u;
     uint32_t w_used = 0;
+    uint32_t wstep = 0;  // the wavefront's walk steps (gather capture)
     // voxel tally: this lane's first (collision, camera) pair and the step
     const uint32_t n_c = A.n_cams > 0 ? (uint32_t)A.n_cams : 1u;
     const uint32_t v_e0 = __lane_id() / n_c, v_c0 = __lane_id() % n_c;
@@ -990,7 +1010,7 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
     for (;;) {
         const unsigned long long need = __ballot(!alive && !exhausted);
         if (need) {
-            const uint64_t k = wave_fetch(A.work, need, pool_next, pool_end);
+            const uint64_t k = wave_fetch(A.work, A.fetch_block, need, pool_next, pool_end);
             if (!alive && !exhausted) {
                 if (k < A.n_photons) {
                     launch_photon(A, A.pid0 + k, ph);
@@ -1053,8 +1073,8 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 }
                 qtail += (uint32_t)__popcll(m);
                 if (qtail - qhead > QCAP - (uint32_t)WAVE)
-                    drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn,
-                                                      vconn_w, w_used, w_first);
+                    drain<Real, W, MODE, TALLY, AIRZ, CAP>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false,
+                                                           vconn, vconn_w, w_used, w_first, wstep, wave_id);
             }
         }
         if (collided) {
@@ -1064,11 +1084,12 @@ __global__ void __launch_bounds__((RenderThreads<MODE>::value), (RenderWaves<Rea
                 alive = false;
             }
         }
-        drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn, vconn_w,
-                                          w_used, w_first);
+        drain<Real, W, MODE, TALLY, AIRZ, CAP>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, false, vconn,
+                                               vconn_w, w_used, w_first, wstep, wave_id);
     }
-    drain<Real, W, MODE, TALLY, AIRZ>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w, w_used,
-                                      w_first);
+    drain<Real, W, MODE, TALLY, AIRZ, CAP>(A, C, mask, lds_grad, Q, qhead, qtail, J, busy, fin, true, vconn, vconn_w,
+                                           w_used, w_first, wstep, wave_id);
+    if (CAP && __lane_id() == 0) A.capture_steps[wave_id] = wstep;
 
     if ((MODE == MODE_TAPE || MODE == MODE_RTAPE) && __lane_id() == 0) {
         A.tp.wave_count[wave_id] = w_used;
@@ -2107,12 +2128,19 @@ size_t render_dyn_lds(const KArgs<Real>& a, int mode) {
     return bytes;
 }
 
-template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false>
+template <typename Real, int MODE, int TALLY, bool AIRZ = false, bool W32 = false, bool CAP = false>
 static hipError_t launch_r(const KArgs<Real>& a, int grid, hipStream_t s) {
     const size_t dyn = render_dyn_lds(a, MODE);
-    hipLaunchKernelGGL((k_render<Real, MODE, TALLY, AIRZ, W32>), dim3(grid), dim3(RenderThreads<MODE>::value), dyn,
-                       s, a);
+    KArgs<Real> b = a;
+    const uint64_t waves = (uint64_t)std::max(grid, 1) * (RenderThreads<MODE>::value / WAVE);
+    b.fetch_block = (uint32_t)std::min<uint64_t>(FETCH_BLOCK_MAX, std::max<uint64_t>(WAVE, a.n_photons / (32 * waves)));
+    hipLaunchKernelGGL((k_render<Real, MODE, TALLY, AIRZ, W32, CAP>), dim3(grid), dim3(RenderThreads<MODE>::value),
+                       dyn, s, b);
     return hipGetLastError();
+}
+
+hipError_t launch_capture(const KArgs<float>& a, int grid, hipStream_t s) {
+    return launch_r<float, MODE_RENDER, TALLY_F64, false, false, true>(a, grid, s);
 }
 
 template <typename Real>

@@ -118,6 +118,37 @@ __global__ void k_gather_write(const float* __restrict__ data, uint32_t n, uint3
     if (acc == 1234.5f) sink[tid] = acc;
 }
 
+// Replay of captured gather addresses (the walk's own address stream):
+// wavefront w loads, lane by lane, the NS indices that captured wavefront w
+// of the render loaded on NS consecutive walk steps (idx[(w NS + j) 64 +
+// lane], clamped into data) and gathers data at them, `reps` times over.
+// No walk arithmetic, and no load depends on another: the loads issue as
+// fast as the vector-memory pipeline takes them, so the rate bounds what the
+// walk can reach on the same addresses with the same wavefronts per CU.
+template <int NS>
+__global__ void __launch_bounds__(256, 4)
+    k_gather_replay(const float* __restrict__ data, uint32_t n, const uint32_t* __restrict__ idx, uint32_t reps,
+                    float* sink) {
+    const size_t w = (size_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t r[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) r[j] = min(idx[(w * NS + j) * 64 + lane], n - 1u);
+    float acc = 0.f;
+    for (uint32_t k = 0; k < reps; ++k) {
+        // a zero offset that counts as changed on every pass, so that the
+        // loads stay in the loop (an empty statement: no instruction)
+        uint32_t z = 0u;
+        asm volatile("" : "+s"(z));
+        float v[NS];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v[j] = data[r[j] + z];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) acc += v[j];
+    }
+    if (acc == 1234.5f) sink[blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
 __global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -173,6 +204,21 @@ int mc_micro_gather_write(const float* data, uint32_t n, uint32_t blocks, uint32
         case 2: hipLaunchKernelGGL(k_gather_write<2>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
         default: hipLaunchKernelGGL(k_gather_write<3>, dim3(blocks), dim3(256), 0, s, data, n, iters, period, o, n_out, sink); break;
     }
+    return (int)hipGetLastError();
+}
+
+// Replay of n_waves captured wavefronts of n_steps (32 or 48) walk steps
+// each: blocks of 4 wavefronts; indices are clamped into [0, n).
+int mc_micro_gather_replay(const float* data, uint32_t n, const uint32_t* idx, uint32_t n_waves, uint32_t n_steps,
+                           uint32_t reps, float* sink, void* stream) {
+    if (!data || n == 0 || !idx || !sink || n_waves < 4 || n_waves % 4 != 0) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_steps == 32)
+        hipLaunchKernelGGL(k_gather_replay<32>, dim3(n_waves / 4), dim3(256), 0, s, data, n, idx, reps, sink);
+    else if (n_steps == 48)
+        hipLaunchKernelGGL(k_gather_replay<48>, dim3(n_waves / 4), dim3(256), 0, s, data, n, idx, reps, sink);
+    else
+        return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
 }
 

@@ -92,7 +92,8 @@ EXPORTS = ["mc_render", "mc_render_moments", "mc_grad_beta", "mc_trace_paths", "
            "mc_device_count", "mc_render_tape", "mc_grad_beta_tape", "mc_tape_free", "mc_release_memory",
            "mc_voxel_scatter", "mc_voxel_render", "mc_voxel_grad", "mc_voxel_conditioning", "mc_regularizer",
            "mc_image_residual", "mc_gd_step", "mc_camera_noise", "mc_recovery_error", "mc_recover",
-           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen", "mc_render_noalloc"]
+           "mc_bmc_render", "mc_render_mixture", "mc_grad_mixture", "mc_render_frozen", "mc_render_noalloc",
+           "mc_capture_gathers"]
 
 
 class McError(RuntimeError):
@@ -114,6 +115,9 @@ def load_library(path: str = LIB_PATH):
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         L.mc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
                                 C.POINTER(McParams), vp, C.POINTER(McStats), vp]
+        L.mc_capture_gathers.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera), C.POINTER(McParams),
+                                         vp, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp, C.POINTER(C.c_uint32),
+                                         C.POINTER(McStats), vp]
         L.mc_render_noalloc.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
                                         C.POINTER(McParams), vp, C.POINTER(McStats), vp]
         L.mc_render_moments.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),
@@ -258,6 +262,26 @@ def mc_render_noalloc(s, beta, transport="fp32", tally="f64", stats=True, out=No
                                           C.c_void_p(_stream(torch, stream)))
     _check("mc_render_noalloc", rc)
     return img, (_stats(st) if stats else None)
+
+
+def mc_capture_gathers(s, beta, first_step, n_steps, max_waves, stream=None, **kw):
+    """The gather capture (a diagnostic of the FP32 render): returns (indices
+    [max_waves, n_steps, 64] int32 tensor, steps per wavefront [max_waves], the
+    launch's wavefronts, stats); see include/mcrt.h."""
+    torch = _torch()
+    _check_beta(torch, s, beta, "fp32")
+    img = torch.empty(n_pixels(s), dtype=torch.float64, device=beta.device)
+    idx = torch.full((max_waves, n_steps, 64), -1, dtype=torch.int32, device=beta.device)
+    steps = torch.zeros(max_waves, dtype=torch.int32, device=beta.device)
+    nw = C.c_uint32(0)
+    st = McStats()
+    rc = load_library().mc_capture_gathers(C.byref(make_grid(s)), C.c_void_p(beta.data_ptr()), len(s.cameras),
+                                           make_cameras(s.cameras), C.byref(make_params(s, **kw)),
+                                           C.c_void_p(img.data_ptr()), int(first_step), int(n_steps), int(max_waves),
+                                           C.c_void_p(idx.data_ptr()), C.c_void_p(steps.data_ptr()), C.byref(nw),
+                                           C.byref(st), C.c_void_p(_stream(torch, stream)))
+    _check("mc_capture_gathers", rc)
+    return idx, steps, int(nw.value), _stats(st)
 
 
 def mc_render_moments(s, beta, transport="fp32", tally="f64", stats=True, stream=None, **kw):
@@ -620,9 +644,12 @@ def mc_recover(s, beta0, measured, delta, n_gd, n_outer, rays_per_side=2, eta=0.
 
 
 def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pix=True,
-                   stream=None, **kw):
+                   stream=None, device=False, **kw):
     """Per-photon event records.  Returns numpy (events[count, max_rec], paths[count],
-    pix[count, max_rec, n_cams] or None); unrecorded slots hold zeros / -2."""
+    pix[count, max_rec, n_cams] or None); unrecorded slots hold zeros / -2.  With
+    device=True the records stay on the GPU: (events as raw bytes, a dict of path fields
+    n_events, fate [count] int32, exit_pos [count, 3], exit_w [count] float64, and pix
+    [count, max_rec, n_cams] int32 or None), all torch tensors."""
     torch = _torch()
     _check_beta(torch, s, beta, transport)
     dev = beta.device
@@ -638,6 +665,12 @@ def mc_trace_paths(s, beta, first_pid, count, max_rec, transport="fp32", with_pi
                                        C.c_void_p(pix.data_ptr() if with_pix else 0),
                                        C.c_void_p(paths.data_ptr()), C.c_void_p(_stream(torch, stream)))
     _check("mc_trace_paths", rc)
+    if device:
+        pi = paths[:count * PATH_DTYPE.itemsize].view(torch.int32).reshape(count, PATH_DTYPE.itemsize // 4)
+        pf = paths[:count * PATH_DTYPE.itemsize].view(torch.float64).reshape(count, PATH_DTYPE.itemsize // 8)
+        fields = {"n_events": pi[:, 0], "fate": pi[:, 1], "exit_pos": pf[:, 1:4], "exit_w": pf[:, 7]}
+        px = pix[:count * max_rec * len(s.cameras)].reshape(count, max_rec, len(s.cameras)) if with_pix else None
+        return ev, fields, px
     ev_np = ev.cpu().numpy()[:count * max_rec * EVENT_DTYPE.itemsize].view(EVENT_DTYPE)
     p_np = paths.cpu().numpy()[:count * PATH_DTYPE.itemsize].view(PATH_DTYPE)
     pix_np = (pix.cpu().numpy()[:count * max_rec * len(s.cameras)].reshape(count, max_rec, len(s.cameras))

@@ -24,9 +24,62 @@ def _lib():
     L.mc_micro_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]
     L.mc_micro_gather_write.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                         C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
-    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_gather_write):
+    L.mc_micro_gather_replay.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
+                                         C.c_void_p, C.c_void_p]
+    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_gather_write,
+              L.mc_micro_gather_replay):
         f.restype = C.c_int
     return L
+
+
+def gather_ceiling(s, n_photons, first_step=2000, n_steps=48, reps=20, seed=1000):
+    """The render's connection-walk gathers against a replay of the same
+    addresses: a capture render (FP32) stores what every lane of every
+    wavefront loads on n_steps walk steps from first_step on; the replay
+    kernel issues exactly those loads, with the same wavefronts per CU and no
+    walk arithmetic, `reps` times over (the rate the vector-memory pipeline
+    sustains on this address stream and working set).  The render's own rate
+    comes from a plain render of the same photons: loads issued by its walks
+    (64 per wavefront step, the idle lanes' loads of the zero word included)
+    plus its free-flight loads, per second of kernel time."""
+    import torch
+    from paper_1512_02110_amd import mcrt as M
+    L = _lib()
+    dev = torch.device("cuda:0")
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    st_ = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    sc = s.replace(n_photons=n_photons)
+    beta = M.beta_tensor(sc, "fp32")
+    max_waves = n_cu * 4 * 4  # four 256-thread blocks per CU, as the render runs
+    idx, steps, nw, cst = M.mc_capture_gathers(sc, beta, first_step, n_steps, max_waves, seed=seed)
+    full = torch.nonzero(steps[:nw] >= first_step + n_steps).flatten()
+    nf = (full.numel() // 4) * 4
+    if nf < 4:
+        raise RuntimeError("no wavefront took enough walk steps for the capture window")
+    sel = idx[full[:nf]].contiguous()
+    # the library's copy of beta: the voxels, then zeros (the zero word and the padding), then one per layer
+    data = torch.cat([beta, torch.zeros(64 + sc.nz, dtype=torch.float32, device=dev)])
+    sink = torch.zeros(nf * 64, dtype=torch.float32, device=dev)
+
+    def run():
+        rc = L.mc_micro_gather_replay(C.c_void_p(data.data_ptr()), data.numel(), C.c_void_p(sel.data_ptr()), nf,
+                                      n_steps, reps, C.c_void_p(sink.data_ptr()), st_)
+        assert rc == 0, rc
+    ms = _time(torch, run)
+    replay = nf * 64 * n_steps * reps / (ms * 1e-3)
+    M.mc_render(sc, beta, seed=seed + 1, n_photons=max(1, n_photons // 10), stats=False)
+    _, rst = M.mc_render(sc, beta, seed=seed)
+    t = rst.timing["transport_ms"] * 1e-3
+    wave_steps = int(steps[:nw].sum().item())
+    issued = (64.0 * wave_steps + rst["vox_free"]) / t
+    useful = (rst["vox_conn"] + rst["vox_free"]) / t
+    return {"working_set_bytes": 4 * sc.n_vox, "photons": n_photons, "waves_replayed": nf,
+            "window_steps": [first_step, first_step + n_steps], "replay_reps": reps, "replay_ms": ms,
+            "replay_gloads_per_s": replay / 1e9,
+            "render_kernel_ms": rst.timing["transport_ms"],
+            "render_issued_gloads_per_s": issued / 1e9, "frac_issued_of_replay": issued / replay,
+            "render_algorithmic_gloads_per_s": useful / 1e9, "frac_algorithmic_of_replay": useful / replay,
+            "lane_occupancy_of_walk_steps": cst["vox_conn"] / max(64.0 * wave_steps, 1.0)}
 
 
 def _time(torch, fn, reps=3):
