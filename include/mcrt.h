@@ -393,8 +393,9 @@ int mc_voxel_grad(const mc_grid* grid, const double* beta, int n_cams, const mc_
  *   computes j with mc_voxel_scatter at the current beta and seed
  *   params->seed + q, then n_gd steps beta = max(beta - delta grad, 0) of
  *   E = sum |mask (i(beta | j) - measured)|^2 + eta Psi(beta), grad =
- *   2 sum_c Q_c J_c^T mask^2 (i - measured) + eta dPsi, Q_c from
- *   mc_voxel_conditioning when conditioned != 0 (else 1).  cost (HOST,
+ *   2 sum_c Q_c J_c^T mask^2 (i - measured) + eta dPsi, Q_c = q of
+ *   mc_voxel_conditioning (1/count) when conditioned = 1, the counts
+ *   themselves (the passage's wording taken literally) when 2, 1 when 0.  cost (HOST,
  *   nullable, n_outer n_gd doubles) gets E before every step (one wait for
  *   the stream per step).  tally must be MC_TALLY_F64. */
 int mc_voxel_conditioning(const mc_grid* grid, int n_cams, const mc_camera* cams, int rays_per_side,

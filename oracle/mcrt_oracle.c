@@ -1260,7 +1260,8 @@ void oracle_recovery_error(int64_t n, const double* beta_hat, const double* beta
  *                  + eta Psi(beta),
  * beta <- max(beta - delta * grad, 0) (the non-negative set), grad =
  * 2 sum_c Q_c J_c^T M_c^2 (i_c - measured_c) + eta dPsi/dbeta, Q_c the
- * conditioning (conditioned != 0) or 1.  beta (in) is the start, (out) the
+ * conditioning: 1 / count (conditioned = 1), the count of rays itself as the
+ * passage words it (conditioned = 2), or 1 (0).  beta (in) is the start, (out) the
  * result; cost[q * n_gd + d] gets E before step d of iteration q. */
 int oracle_recover(const orc_grid* grid, double* beta, int n_cams, const orc_camera* cams,
                    const orc_params* P, int n, const double* measured, const double* mask,
@@ -1279,7 +1280,7 @@ int oracle_recover(const orc_grid* grid, double* beta, int n_cams, const orc_cam
     double* dl = (double*)malloc((size_t)npix * sizeof(double));
     double* g = (double*)malloc((size_t)nv * sizeof(double));
     double* gr = (double*)malloc((size_t)nv * sizeof(double));
-    if (q) oracle_voxel_conditioning(grid, n_cams, cams, n, NULL, q);
+    if (q) oracle_voxel_conditioning(grid, n_cams, cams, n, conditioned == 2 ? q : NULL, conditioned == 2 ? NULL : q);
     for (int it = 0; it < n_outer; ++it) {
         orc_params Pq = *P;
         Pq.seed = P->seed + (uint64_t)it;

@@ -154,7 +154,8 @@ int oracle_voxel_grad(const orc_grid* grid, const double* beta, int n_cams, cons
  * oracle_camera_noise: Eq. (noise) with the caller's N(0,1) draws; returns
  *   the grey-level scale.
  * oracle_recovery_error: out = {delta_mass, eps} of Sec. 7.
- * oracle_recover: the surrogate gradient-descent loop (see the source). */
+ * oracle_recover: the surrogate gradient-descent loop (see the source);
+ *   conditioned: 0 none, 1 Q_c = 1/counts, 2 Q_c = counts. */
 /* Backward Monte Carlo (Sec. 2.1.4, Eq. ble): n_pp packets per pixel;
  * images in the units of oracle_render's (see the source for the steps and
  * the photon ids).  prm->n_photons and photon_offset are not used. */

@@ -446,7 +446,8 @@ def recovery_error(beta_hat, beta_true):
 
 def recover(s, beta0, measured, n_rays_side, delta, n_gd, n_outer, eta=0.0, w_layer=None, mask=None,
             conditioned=True, **kw):
-    """The surrogate gradient-descent loop; returns (beta, cost[n_outer * n_gd])."""
+    """The surrogate gradient-descent loop; returns (beta, cost[n_outer * n_gd]).
+    conditioned: False/0 none, True/1 Q_c = 1/count, 2 Q_c = count."""
     b = np.array(beta0, dtype=np.float64).reshape(-1).copy()
     meas = np.ascontiguousarray(measured, dtype=np.float64).reshape(-1)
     m = None if mask is None else np.ascontiguousarray(mask, dtype=np.float64).reshape(-1)
@@ -455,7 +456,7 @@ def recover(s, beta0, measured, n_rays_side, delta, n_gd, n_outer, eta=0.0, w_la
     rc = lib().oracle_recover(C.byref(make_grid(s)), _dptr(b), len(s.cameras), make_cams(s.cameras),
                               C.byref(make_params(s, **kw)), int(n_rays_side), _dptr(meas),
                               _dptr(m) if m is not None else None, _dptr(w) if w is not None else None,
-                              float(eta), float(delta), int(n_gd), int(n_outer), int(bool(conditioned)),
+                              float(eta), float(delta), int(n_gd), int(n_outer), int(conditioned),
                               _dptr(cost))
     if rc != 0:
         raise OracleError(f"oracle_recover failed: {rc}")

@@ -1864,7 +1864,7 @@ int mc_recover(const mc_grid* grid, double* beta, int n_cams, const mc_camera* c
     if (params->transport == MC_MIXED) return MC_ERR_INVALID_ARG;
     if (rc != MC_OK) return rc;
     if (!measured || params->tally != MC_TALLY_F64 || rays_per_side < 1 || rays_per_side > 64 || n_gd < 1 ||
-        n_outer < 0 || !std::isfinite(eta) || !std::isfinite(delta))
+        n_outer < 0 || !std::isfinite(eta) || !std::isfinite(delta) || conditioned < 0 || conditioned > 2)
         return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
     if (!is_device_ptr(beta) || !is_device_ptr(measured) || (mask && !is_device_ptr(mask)) ||
@@ -1896,7 +1896,7 @@ int mc_recover(const mc_grid* grid, double* beta, int n_cams, const mc_camera* c
         rc = run_voxel(grid, nullptr, n_cams, cams, rays_per_side, nullptr, nullptr, nullptr, nullptr, stream,
                        nullptr, q);
         if (rc != MC_OK) goto done;
-        CHECK_HIP(launch_vox_invert(q, n_cv, stream));
+        if (conditioned == 1) CHECK_HIP(launch_vox_invert(q, n_cv, stream));
     }
     for (int it = 0; it < n_outer; ++it) {
         // j at the current beta, with the photons of seed + it

@@ -638,7 +638,7 @@ def mc_recover(s, beta0, measured, delta, n_gd, n_outer, rays_per_side=2, eta=0.
     rc = load_library().mc_recover(C.byref(make_grid(s)), _ptr(b), len(s.cameras), make_cameras(s.cameras),
                                    C.byref(make_params(s, transport=transport, **kw)), int(rays_per_side),
                                    _ptr(m), _ptr(k), _ptr(w), float(eta), float(delta), int(n_gd), int(n_outer),
-                                   int(bool(conditioned)), cost, C.c_void_p(_stream(torch, stream)))
+                                   int(conditioned), cost, C.c_void_p(_stream(torch, stream)))
     _check("mc_recover", rc)
     return b, np.array(cost[:n_outer * n_gd])
 

@@ -100,6 +100,23 @@ def test_recover_loop_matches_oracle(M, oracle, transport):
     assert b.min() >= 0.0
 
 
+@pytest.mark.parametrize("conditioned,delta", [(0, 0.2), (2, 1e-3)])
+def test_recover_loop_other_conditionings(M, oracle, conditioned, delta):
+    """The loop without conditioning, and with Q_c = the ray counts (the
+    passage's wording taken literally), against the oracle (FP64)."""
+    s = _recovery_scene()
+    print(f"case recover loop, conditioning {conditioned}", flush=True)
+    meas = oracle.voxel_render(s, oracle.voxel_scatter(s, seed=99)[0], 2)
+    b0 = 0.7 * s.beta
+    ref, rcost = oracle.recover(s, b0, meas, 2, delta, 3, 2, eta=0.01, seed=21, conditioned=conditioned)
+    b, cost = M.mc_recover(s, _cuda(b0), _cuda(meas), delta, 3, 2, transport="fp64", eta=0.01, seed=21,
+                           conditioned=conditioned)
+    b = b.cpu().numpy()
+    assert np.abs(ref - b0).max() > 1e-4 * b0.max()
+    assert np.allclose(b, ref, rtol=1e-8, atol=1e-12 * ref.max())
+    assert np.allclose(cost, rcost, rtol=1e-9)
+
+
 def test_recover_edge_cases(M):
     import torch
     s = _recovery_scene()
@@ -112,3 +129,5 @@ def test_recover_edge_cases(M):
         M.mc_recover(s, b0, meas, 1e-3, 0, 1)
     with pytest.raises(M.McError):
         M.mc_recover(s, b0, meas, 1e-3, 1, 1, rays_per_side=0)
+    with pytest.raises(M.McError):
+        M.mc_recover(s, b0, meas, 1e-3, 1, 1, conditioned=3)

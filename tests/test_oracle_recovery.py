@@ -105,21 +105,25 @@ def _recovery_scene():
                         math.radians(30.0), 0.0, 4000, 0)
 
 
-def test_recover_first_step_is_the_composition():
+@pytest.mark.parametrize("conditioned", [1, 2, 0])
+def test_recover_first_step_is_the_composition(conditioned):
     """One outer iteration, one step: j from the scatter pass, E and the step
-    from the pinned render, weighted gradient, regulariser and clipping."""
+    from the pinned render, weighted gradient, regulariser and clipping; the
+    weights are 1/count (conditioned 1), the ray counts (2) or none (0)."""
     s = _recovery_scene()
     b0 = 0.7 * s.beta
     meas = O.voxel_render(s, O.voxel_scatter(s)[0], 2) * 1.05
     mask = (np.arange(s.n_pix_total) % 7 != 0).astype(float)
     w = np.linspace(0.5, 1.5, s.nz)
     eta, delta = 0.01, 1e-3
-    beta, cost = O.recover(s, b0, meas, 2, delta, 1, 1, eta=eta, w_layer=w, mask=mask, seed=11)
+    beta, cost = O.recover(s, b0, meas, 2, delta, 1, 1, eta=eta, w_layer=w, mask=mask, seed=11,
+                           conditioned=conditioned)
     j, _ = O.voxel_scatter(s, beta=b0, seed=11)
     img = O.voxel_render(s, j, 2, beta=b0)
     r = mask * (img - meas)
-    _, q = O.voxel_conditioning(s, 2)
-    g = O.voxel_grad(s, j, 2 * mask * r, 2, beta=b0, q=q)
+    counts, q = O.voxel_conditioning(s, 2)
+    weights = {1: q, 2: counts.astype(np.float64), 0: None}[conditioned]
+    g = O.voxel_grad(s, j, 2 * mask * r, 2, beta=b0, q=weights)
     psi, gpsi = O.laplacian_reg(s, beta=b0, w_layer=w)
     assert cost[0] == pytest.approx(float(np.sum(r * r)) + eta * psi, rel=1e-12)
     ref = np.maximum(b0 - delta * (g + eta * gpsi), 0.0)
