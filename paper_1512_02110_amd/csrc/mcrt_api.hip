@@ -321,6 +321,16 @@ void tape_tiles(const mc_grid* g, int& shx, int& shy, int& shz) {
     shx = std::min(ceil_log2(g->nx), (rest + 1) / 2);
     shy = std::min(ceil_log2(g->ny), rest - shx);
     if (shy < rest - shx) shx = std::min(ceil_log2(g->nx), rest - shy);
+    // the deposit's padded LDS copy of a tile must fit (flat tiles of a thin
+    // grid have the most padding)
+    while (((1 << shx) + 1) * ((1 << shy) + 1) * (1 << shz) > TILE_LDS) {
+        if (shx >= shy && shx > 0)
+            --shx;
+        else if (shy > 0)
+            --shy;
+        else
+            --shz;
+    }
 }
 
 constexpr int TAPE_FALLBACK = 1;

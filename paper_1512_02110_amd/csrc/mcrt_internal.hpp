@@ -162,13 +162,19 @@ struct KArgs {
 // of LDS; 32 KB for FP64 transport (two blocks per CU, register bound).
 constexpr int MASK_WORDS_FP32 = 4096;
 constexpr int MASK_WORDS = 8192;
-constexpr int TILE_VOX = 16384;   // voxels of a gradient tile (128 KB of FP64 LDS)
+constexpr int TILE_VOX = 16384;   // voxels of a gradient tile
+// LDS slots of a tile in the deposit kernel: the tile with one padding
+// column after every row and one padding row after every layer,
+// (nx + 1)(ny + 1)nz <= TILE_LDS (145 KB for 16 x 16 x 64).  A walk step that
+// rounding carries across the tile's x or y face lands in a padding slot,
+// which is never flushed, instead of in another voxel of the tile.
+constexpr int TILE_LDS = 18560;
 constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: up to 104 KB of LDS
 constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS
 constexpr int BIN_GROUP_TILES = 4096; // tiles per scatter pass (3 LDS words each)
 constexpr int SCAN_BLOCK = 256;
 constexpr int DEPOSIT_BLOCK = 1024;
-constexpr int DEP_LDS_CAMS = 512;     // camera centres the deposit keeps in LDS
+constexpr int DEP_LDS_CAMS = 256;     // camera centres the deposit keeps in LDS
 
 // Work item of the deposit kernel: slots [lo, hi) of one tile's range.
 struct DepositItem {

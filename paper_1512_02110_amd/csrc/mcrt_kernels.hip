@@ -1324,9 +1324,9 @@ struct alignas(16) CamCentre {
 // with selects: the lanes that start a record do so together, and branches
 // would cost more in mask handling than the arithmetic they skip.
 template <typename Real, bool CAMS_LDS>
-__device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int b0x, int b0y, int b0z,
-                                              const CamCentre<Real>* s_cam, const TapeRec<Real>& R, double* s_g,
-                                              DepWalk<Real>& D, double& a) {
+__device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGrid<Real>& L, int px, int pxy, int b0x,
+                                              int b0y, int b0z, const CamCentre<Real>* s_cam, const TapeRec<Real>& R,
+                                              double* s_g, DepWalk<Real>& D, double& a) {
     a = (double)R.a;
     const int i0x = (int)(R.vox & 2047u), i0y = (int)((R.vox >> 11) & 2047u), i0z = (int)(R.vox >> 22);
     // (bitwise operators: no short-circuit branches)
@@ -1355,7 +1355,7 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     const Real vx = -dx * ir, vy = -dy * ir, vz = -dz * ir;
     const int jx = i0x - b0x, jy = i0y - b0y, jz = i0z - b0z;
     if (ok && (unsigned)jx < (unsigned)L.nx && (unsigned)jy < (unsigned)L.ny && (unsigned)jz < (unsigned)L.nz)
-        atomicAdd(s_g + (jx + L.nx * jy + L.nxy * jz), (double)R.ab);
+        atomicAdd(s_g + (jx + px * jy + pxy * jz), (double)R.ab);
     // clip [0, r] to the tile box; o = start in tile-local voxel units,
     // w = km per voxel along each axis.  An axis the ray does not move along
     // (|v| <= tiny) does not clip; the ray must then lie within the tile's
@@ -1367,7 +1367,7 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     const Real d[3] = {A.G.dx, A.G.dy, A.G.dz};
     const Real id[3] = {A.G.idx, A.G.idy, A.G.idz};
     const int e[3] = {L.nx, L.ny, L.nz};
-    const int stride[3] = {1, L.nx, L.nxy};
+    const int stride[3] = {1, px, pxy};
     bool mov[3];
     Real w[3];
     Real t0 = (Real)0, t1 = r;
@@ -1428,7 +1428,9 @@ __device__ __forceinline__ void dep_step(DepWalk<Real>& D, double* s_g, double a
     D.tz += (!cx && !cy) ? D.dtz : (Real)0;
     D.t = tn;
     // a crossing that rounding put just before the end of the clipped ray
-    // must not leave the tile's LDS copy
+    // must not leave the tile's LDS copy: across a z face the index leaves
+    // [0, nloc), across an x or y face it enters a padding slot (the next
+    // crossing of that axis is a voxel further on, past the end)
     busy = busy && !(last || (unsigned)D.k >= (unsigned)nloc);
 }
 
@@ -1436,7 +1438,7 @@ __device__ __forceinline__ void dep_step(DepWalk<Real>& D, double* s_g, double a
 // refill ahead, so that a refill does not wait for memory.
 template <typename Real, int TALLY, bool CAMS_LDS>
 __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const DepositItem* items) {
-    __shared__ double s_g[TILE_VOX];
+    __shared__ double s_g[TILE_LDS];
     __shared__ CamCentre<Real> s_cam[CAMS_LDS ? DEP_LDS_CAMS : 1];
     __shared__ uint32_t s_next;
     const Tape<Real>& P = A.tp;
@@ -1448,7 +1450,9 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     L.ny = min(1 << P.shy, A.G.ny - b0y);
     L.nz = min(1 << P.shz, A.G.nz - b0z);
     L.nxy = L.nx * L.ny;
-    const int nloc = L.nxy * L.nz;
+    // padded LDS layout: slot x + px y + pxy z, x <= nx, y <= ny
+    const int px = L.nx + 1, pxy = px * (L.ny + 1);
+    const int nloc = pxy * L.nz;
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
     for (int i = threadIdx.x; CAMS_LDS && i < A.n_cams; i += DEPOSIT_BLOCK) {
         const DevCam<Real>& cam = A.cams[i];
@@ -1473,7 +1477,7 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     for (;;) {
         // idle lanes start their prefetched record
         if (!busy && has) {
-            busy = deposit_begin<Real, CAMS_LDS>(A, L, b0x, b0y, b0z, s_cam, nxt, s_g, D, a);
+            busy = deposit_begin<Real, CAMS_LDS>(A, L, px, pxy, b0x, b0y, b0z, s_cam, nxt, s_g, D, a);
             has = false;
         }
         // lanes without a prefetched record take the next slots of the range
@@ -1511,11 +1515,10 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     __syncthreads();
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) {
         const double v = s_g[i];
-        if (v != 0.0) {
-            const int x = i % L.nx, y = (i / L.nx) % L.ny, z = i / L.nxy;
+        const int x = i % px, y = (i / px) % (L.ny + 1), z = i / pxy;
+        if (v != 0.0 && x < L.nx && y < L.ny)
             tally_f64<TALLY>(A.grad, A.grad32, (int64_t)(b0x + x) + (int64_t)A.G.nx * (b0y + y) +
                                                    (int64_t)A.G.nxy * (b0z + z), v);
-        }
     }
 }
 
