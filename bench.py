@@ -35,9 +35,6 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32, dense
 PEAK_HBM_GBPS = 8000.0
-# random 4-byte gathers from a 1 MiB working set (the 64^3 FP32 grid) at
-# full occupancy, 4 useful bytes per load: paper_1512_02110_amd/micro.py
-GATHER_CEILING_GBPS = 1006.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1512_02110_amd", "csrc", "mcrt_kernels.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_render_c2_hbm_traffic.md")
 
@@ -290,6 +287,134 @@ def adjoint_c3(M, torch, np, stream, n_photons):
             "independent_seed_cosine": float(np.dot(a, c) / (np.linalg.norm(a) * np.linalg.norm(c)))}
 
 
+def c4_full_replay(M, torch, np, stream, n_photons=1_000_000_000):
+    """The 128^3 cloud with 25 cameras at its own 1e9 photons: the forward,
+    and the gradient by photon replay (a render's rays at this count, ~1.2e11
+    records, do not fit in memory), one timed call each."""
+    from paper_1512_02110_amd import scenes
+    s = scenes.config4(n_photons=n_photons)
+    beta = M.beta_tensor(s, "fp32")
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+    # warm-up (also gives the replay its rays-per-photon hint for this workload)
+    img0, _ = M.mc_render(s, beta, n_photons=2_000_000, stats=False)
+    dl0 = torch.as_tensor(np.random.default_rng(2).normal(size=img0.numel()), device=img0.device)
+    M.mc_grad_beta(s, beta, dl0, n_photons=2_000_000, stats=False)
+    print("[bench] c4 full: forward", flush=True)
+    (img, st), t_fwd = timed(lambda: M.mc_render(s, beta))
+    print(f"[bench] c4 full: forward {t_fwd:.0f} ms; gradient by replay", flush=True)
+    (g, gst), t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl0))
+    print(f"[bench] c4 full: gradient {t_adj:.0f} ms", flush=True)
+    return {"workload": f"c4: 128^3 cloud, 25 cameras 256x256, {n_photons:.0e} photons, FP32 transport + FP64 "
+                        f"tallies; gradient by photon replay (no kept rays)",
+            "fwd_ms": round(t_fwd, 1), "fwd_kernel_ms": round(st.timing["transport_ms"], 1),
+            "events_per_s": st["events"] / (t_fwd * 1e-3), "events": st["events"], "le_jobs": st["le_jobs"],
+            "adj_ms": round(t_adj, 1), "adj_replay_kernel_ms": round(gst.timing["transport_ms"], 1),
+            "adj_bin_deposit_ms": round(gst.timing["tape_ms"], 1),
+            "fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 4)}
+
+
+def descent_c5(M, torch, np, n_photons=25_000_000, n_iter=3, n_outer_voxel=4):
+    """A few iterations of both recovery loops on the 256x256x128 multi-cloud
+    field with 36 cameras (paper_1512_02110_amd.descent): projected gradient
+    descent with the local-estimation surrogate gradient (measured images: the
+    truth rendered at photon seed 1), with where its largest gradient sits, and
+    the voxelised model with conditioning Q_c = 1/count, 5 steps per photon
+    pass (measured images: the voxelised model of the truth with camera noise).
+    The 50-iteration runs at 2.5e8 photons per pass are
+    `python -m paper_1512_02110_amd.descent [--model voxel]`."""
+    from paper_1512_02110_amd import scenes
+    from paper_1512_02110_amd.descent import mc_descent, mc_voxel_descent
+    truth = scenes.config5(n_photons=n_photons)
+    t64 = torch.as_tensor(truth.beta, dtype=torch.float64, device="cuda")
+    meas, _ = M.mc_render(truth, M.beta_tensor(truth, "fp32"), seed=1, stats=False)
+    b0 = torch.as_tensor(0.7 * scenes.smooth(truth.beta3d(), 1.0).reshape(-1), dtype=torch.float64, device="cuda")
+    _, recs, delta = mc_descent(truth, b0, meas, n_iter, truth=t64)
+    out = {"workload": f"c5 recovery loops: 256x256x128, 36 cameras 256x256, {n_photons:.1e} photons per render "
+                       f"and per gradient (per photon pass), FP32 transport",
+           "local_estimation": {
+               "delta": delta, "iterations": [{k: r[k] for k in ("iter", "loss", "residual", "eps", "delta_mass",
+                                                                "grad_max", "grad_max_voxel", "grad_p999",
+                                                                "seconds")} for r in recs],
+               "eps_after": recs[-1]["eps_after"], "delta_mass_after": recs[-1]["delta_mass_after"]}}
+    del meas
+    jt, _ = M.mc_voxel_scatter(truth, M.beta_tensor(truth, "fp32"), seed=99, stats=False)
+    clean = M.mc_voxel_render(truth, t64, jt, 2)
+    del jt
+    normals = torch.as_tensor(np.random.default_rng(5).normal(size=clean.numel()), device="cuda")
+    grey, scale = M.mc_camera_noise(clean, normals)
+    _, vrecs, vdelta = mc_voxel_descent(truth, b0, grey / scale, n_outer_voxel, truth=t64)
+    out["voxel_model_q_1_over_count"] = {
+        "delta_last": vdelta, "eps_start": M.mc_recovery_error(b0, t64)[1],
+        "iterations": [{k: r[k] for k in ("iter", "cost", "eps", "delta_mass", "delta", "halvings", "seconds")}
+                       for r in vrecs]}
+    return out
+
+
+def gradient_statistics(M, torch, np, n_photons=100_000_000, parts=16, seeds=8):
+    """Monte Carlo statistics of the surrogate gradient on the 16^3 adjoint
+    workload (beta0 = 0.7 x smoothed truth; L2 loss against images of the
+    truth at photon seed 1; FP32 transport): the gradient on the render's own
+    photons (seed 0, the frozen-event derivative of the render) as the sum of
+    `parts` disjoint photon ranges, whose spread gives per-voxel standard
+    errors; gradients with the same image residual on `seeds` independent
+    photon streams; the same-stream gradient with the residual of an
+    independent render (seed 2) instead; and the voxelised model's gradient
+    (Sec. 3) with the same residual."""
+    from paper_1512_02110_amd import scenes
+    truth = scenes.config3_truth(n_photons=n_photons, seed=1)
+    s = scenes.config3_initial(n_photons=n_photons, seed=0)
+    b32 = M.beta_tensor(s, "fp32")
+    meas, _ = M.mc_render(truth, M.beta_tensor(truth, "fp32"), stats=False)
+    i0, _ = M.mc_render(s, b32, stats=False)
+    i1, _ = M.mc_render(s, b32, seed=2, stats=False)
+    dl0, dl1 = 2.0 * (i0 - meas), 2.0 * (i1 - meas)
+    n = n_photons // parts
+    gp = [M.mc_grad_beta(s, b32, dl0, n_photons=n, photon_offset=k * n, n_photons_norm=n_photons, stats=False)[0]
+          .cpu().numpy() for k in range(parts)]
+    gp = np.array(gp)
+    g_same = gp.sum(axis=0)
+    se_same = np.sqrt(parts * gp.var(axis=0, ddof=1))
+    gi = np.array([M.mc_grad_beta(s, b32, dl0, seed=100 + j, stats=False)[0].cpu().numpy() for j in range(seeds)])
+    g_ind = gi.mean(axis=0)
+    se_ind = gi.std(axis=0, ddof=1) / np.sqrt(seeds)
+    g_x = M.mc_grad_beta(s, b32, dl1, stats=False)[0].cpu().numpy()  # seed-0 events, independent residual
+    j, _ = M.mc_voxel_scatter(s, b32, seed=3, stats=False)
+    g_vox = M.mc_voxel_grad(s, M.beta_tensor(s, "fp64"), j, dl0, 2).cpu().numpy()
+
+    def cos(a, b):
+        return float(np.dot(a, b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
+    pair = [cos(gi[a], gi[b]) for a in range(seeds) for b in range(a + 1, seeds)]
+    sig = np.abs(g_ind) > 3 * se_ind
+    bias = g_same - g_ind
+    iz = np.arange(s.n_vox) // (s.nx * s.ny)
+    return {"workload": f"c3: 16^3 blob, 4 cameras 32x32 on the floor, {n_photons:.0e} photons, FP32 transport",
+            "same_stream_vs_independent_mean_cosine": cos(g_same, g_ind),
+            "independent_streams_pairwise_cosine_mean": float(np.mean(pair)),
+            "independent_streams_pairwise_cosine_min": float(np.min(pair)),
+            "same_stream_events_independent_residual_vs_independent_mean_cosine": cos(g_x, g_ind),
+            "voxel_model_vs_independent_mean_cosine": cos(g_vox, g_ind),
+            "median_snr_same_stream": float(np.median(np.abs(g_same) / np.maximum(se_same, 1e-300))),
+            "median_snr_one_independent_stream": float(np.median(np.abs(g_ind) / np.maximum(se_ind * np.sqrt(seeds),
+                                                                                          1e-300))),
+            "frac_voxels_significant_independent_mean": float(sig.mean()),
+            "frac_significant_voxels_sign_disagrees_same_stream": float((np.sign(g_same) != np.sign(g_ind))[sig].mean())
+            if sig.any() else 0.0,
+            "same_minus_independent_rel_l2": float(np.linalg.norm(bias) / max(np.linalg.norm(g_ind), 1e-300)),
+            "same_minus_independent_in_sigmas_median": float(np.median(np.abs(bias) / np.maximum(
+                np.sqrt(se_same ** 2 + se_ind ** 2), 1e-300))),
+            "share_of_same_minus_independent_in_bottom_two_layers": float(
+                np.abs(bias)[iz < 2].sum() / max(np.abs(bias).sum(), 1e-300)),
+            "share_of_independent_gradient_in_bottom_two_layers": float(
+                np.abs(g_ind)[iz < 2].sum() / max(np.abs(g_ind).sum(), 1e-300))}
+
+
 def large_grids(M, torch, np, stream, n_photons):
     """The 128^3 cloud (25 cameras of 256^2) and the 256x256x128 multi-cloud
     field (36 cameras of 256^2), whose extinction copies (8 and 34 MB) sit in
@@ -320,6 +445,10 @@ def large_grids(M, torch, np, stream, n_photons):
              "fwd_ms": round(t_fwd, 3), "events_per_s": st["events"] / (t_fwd * 1e-3),
              "events": st["events"], "le_jobs": st["le_jobs"], "voxel_steps_per_s": steps / (t_fwd * 1e-3),
              "gather_GBps": 4.0 * steps / (t_fwd * 1e-3) / 1e9}
+        # warm-up of the kept render: the first one of a workload allocates its ray buffer
+        _, _, tape = M.mc_render_tape(s, beta, n_photons=min(n_photons, 1_000_000), stats=False)
+        if tape is not None:
+            tape.free()
         (_, _, tape), t_tape = timed(lambda: M.mc_render_tape(s, beta, stats=False))
         if tape is None:
             # a kept tape that overflowed (sized from an earlier kept render
@@ -339,6 +468,7 @@ def large_grids(M, torch, np, stream, n_photons):
                       "fwd_plus_adj_over_fwd": round((t_fwd + t_adj) / t_fwd, 4)})
         out[name] = r
         del tape, img, beta
+        M.mc_release_memory()
     return out
 
 
@@ -435,16 +565,20 @@ def mixture(M, torch, np, stream, s, n_grad=10_000_000):
     return out
 
 
-def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=3, n_gd=5, n_side=2):
+def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=10, n_gd=5, n_side=2):
     """The surrogate recovery loop (Secs. 5.2, 6, 7) on the same grid and
-    cameras: measured images of the truth from the voxelised model (seed 99,
-    Eq. (noise) grey levels with seeded read noise, back to radiance), start
-    0.7 x the truth smoothed over a voxel, conditioned steps with a small
-    Laplacian weight; the step size is the largest of 5% of max beta over the
-    largest first gradient, halved until every step decreases its
-    surrogate's cost and the loop ends below its start.  Reports the time per surrogate iteration (the photon pass
-    for j) and per gradient step, the cost and delta_mass / eps."""
+    cameras, with each reading of the conditioning Q_c of Sec. 6: 1/count
+    (this build's reading), the count itself (the passage's wording taken
+    literally) and none.  Measured images of the truth from the voxelised
+    model (seed 99, Eq. (noise) grey levels with seeded read noise, back to
+    radiance); start 0.7 x the truth smoothed over a voxel; a small Laplacian
+    weight.  paper_1512_02110_amd.descent.mc_voxel_descent: step size from
+    5% of max beta over the largest first gradient, halved whenever an outer
+    iteration's steps do not all lower its cost.  eps and delta_mass after
+    every outer iteration (a photon pass for j, then n_gd steps), and the
+    time per photon pass."""
     from paper_1512_02110_amd import scenes
+    from paper_1512_02110_amd.descent import mc_voxel_descent
     truth = s.with_beta(s.beta)
     t32 = M.beta_tensor(truth, "fp32")
     t64 = M.beta_tensor(truth, "fp64")
@@ -456,41 +590,31 @@ def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=3, n_gd=5, n
     b0 = 0.7 * scenes.smooth(truth.beta3d(), 1.0).reshape(-1)
     s0 = truth.replace(n_photons=n_photons)
     b0t = torch.as_tensor(b0, device="cuda")
-    j0, _ = M.mc_voxel_scatter(s0, b0t.float(), seed=1000, stats=False)
-    img0 = M.mc_voxel_render(s0, b0t, j0, n_side)
-    dl0, _ = M.mc_image_residual(img0, meas)
-    _, q = M.mc_voxel_conditioning(s0, n_side)
-    g0 = M.mc_voxel_grad(s0, b0t, j0, dl0, n_side, cam_weights=q)
-    delta = 0.05 * float(b0.max()) / float(g0.abs().max())
     eta = 1e-3
-    # backtracking: the largest of delta, delta/2, ... for which every step
-    # of the whole loop decreases the cost of its surrogate and the last cost
-    # is below the first (these runs are also the warm-up)
-    for _ in range(16):
-        _, c = M.mc_recover(s0, b0t, meas, delta, n_gd, n_outer, rays_per_side=n_side, eta=eta, seed=1000)
-        inner = np.diff(c.reshape(n_outer, n_gd), axis=1)
-        if np.all(inner < 0) and c[-1] < c[0]:
-            break
-        delta *= 0.5
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    beta, cost = M.mc_recover(s0, b0t, meas, delta, n_gd, n_outer, rays_per_side=n_side, eta=eta, seed=1000)
-    b.record(stream)
-    torch.cuda.synchronize()
-    t_loop = a.elapsed_time(b)
+    e0 = M.mc_recovery_error(b0t, t64)
+    out = {"workload": f"same grid and cameras; {n_photons:.0e} photons per surrogate iteration, {n_outer} "
+                       f"iterations x {n_gd} steps, {n_side}x{n_side} rays per pixel",
+           "delta_mass_start": e0[0], "eps_start": e0[1], "readings": {}}
+    for name, cond in (("q_1_over_count", 1), ("q_count", 2), ("none", 0)):
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        _, recs, delta = mc_voxel_descent(s0, b0t, meas, n_outer, n_gd=n_gd, conditioned=cond, rays_per_side=n_side,
+                                          eta=eta, truth=t64)
+        e.record(stream)
+        torch.cuda.synchronize()
+        eps = [e0[1]] + [r["eps"] for r in recs]
+        out["readings"][name] = {"delta_last": delta, "halvings": [r["halvings"] for r in recs],
+                                 "loop_ms": round(a.elapsed_time(e), 3), "eps": eps,
+                                 "delta_mass": [e0[0]] + [r["delta_mass"] for r in recs],
+                                 "cost_first": recs[0]["cost"][0], "cost_last": recs[-1]["cost"][-1],
+                                 "eps_end_below_start": eps[-1] < eps[0]}
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     M.mc_voxel_scatter(s0, b0t.float(), seed=1000, stats=False)
-    b.record(stream)
+    e.record(stream)
     torch.cuda.synchronize()
-    t_j = a.elapsed_time(b)
-    e0 = M.mc_recovery_error(b0t, t64)
-    e1 = M.mc_recovery_error(beta, t64)
-    return {"workload": f"same grid and cameras; {n_photons:.0e} photons per surrogate iteration, "
-                        f"{n_outer} iterations x {n_gd} steps, {n_side}x{n_side} rays per pixel",
-            "delta": delta, "loop_ms": round(t_loop, 3), "photon_pass_ms": round(t_j, 3),
-            "gd_step_ms": round((t_loop - n_outer * t_j) / (n_outer * n_gd), 3),
-            "cost_first": float(cost[0]), "cost_last": float(cost[-1]),
-            "delta_mass_start": e0[0], "eps_start": e0[1], "delta_mass_end": e1[0], "eps_end": e1[1]}
+    out["photon_pass_ms"] = round(a.elapsed_time(e), 3)
+    return out
 
 
 def main():
@@ -512,6 +636,8 @@ def main():
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxelised-model section")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 and 256x256x128 section")
     ap.add_argument("--large-photons", type=int, default=20_000_000)
+    ap.add_argument("--no-c4-full", action="store_true",
+                    help="skip the 128^3 workload at its own 1e9 photons (about three minutes)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -595,15 +721,31 @@ def main():
     gbytes = 4.0 * steps + 16.0 * st["le_jobs"]
     achieved_gbps = gbytes / k_s / 1e9
     traffic = measured_traffic()
+    # the ceiling of the walk's gathers on its own address stream (a capture
+    # of the render's loads replayed without the walk, micro.gather_ceiling)
+    from paper_1512_02110_amd import micro
+    ceil = micro.gather_ceiling(s, min(s.n_photons, 20_000_000))
     roofline = {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": PEAK_HBM_GBPS,
                 "unit": "GB/s", "frac": round(achieved_gbps / PEAK_HBM_GBPS, 4),
+                "achieved_is": "algorithmic bytes of the launch (4 B per voxel step read from the extinction grid, "
+                               "16 B per FP64 image tally) per second of kernel time; the 1 MiB grid is served by "
+                               "L1/L2, so this is not HBM traffic (that is `traffic`)",
                 "traffic": traffic,
                 "kernel": "k_render<float, MODE_RENDER, TALLY_F64>",
                 "kernel_ms_avg": round(sum(k_ms) / len(k_ms), 3),
                 "algorithmic_bytes_per_launch": gbytes / len(recs),
-                "binding_unit": "vector-memory gather pipeline (TA/TD busy; profiles/k_render_fwd_c2_counters.md)",
-                "gather_ceiling_GBps_measured": GATHER_CEILING_GBPS,
-                "frac_of_gather_ceiling": round(achieved_gbps / GATHER_CEILING_GBPS, 3),
+                "binding_unit": "the vector-memory gather pipeline (address and data units busy, "
+                                "profiles/k_render_fwd_c2_counters.md)",
+                "gather_ceiling": {
+                    "what": "loads/s of the render's own connection-walk loads (captured per wavefront and lane) "
+                            "replayed with no walk arithmetic, same wavefronts per CU",
+                    "ceiling_gloads_per_s": round(ceil["replay_gloads_per_s"], 1),
+                    "render_issued_gloads_per_s": round(ceil["render_issued_gloads_per_s"], 1),
+                    "frac_issued": round(ceil["frac_issued_of_replay"], 4),
+                    "render_algorithmic_gloads_per_s": round(ceil["render_algorithmic_gloads_per_s"], 1),
+                    "frac_algorithmic": round(ceil["frac_algorithmic_of_replay"], 4),
+                    "target_frac": 0.5, "met": ceil["frac_algorithmic_of_replay"] >= 0.5,
+                    "photons": ceil["photons"], "working_set_bytes": ceil["working_set_bytes"]},
                 "alu_tflops": round(flops / k_s / 1e12, 3),
                 "alu_frac_of_fp32_peak": round(flops / k_s / 1e12 / PEAK_FP32_TFLOPS, 4),
                 "voxel_steps_per_s": steps / k_s}
@@ -659,8 +801,18 @@ def main():
         out["forward_c1"] = forward_c1(M, np)
     if not args.no_adjoint and args.config == "c2":
         out["fwd_adjoint_c3"] = adjoint_c3(M, torch, np, stream, args.c3_photons)
+        out["gradient_statistics_c3"] = gradient_statistics(M, torch, np, args.c3_photons)
+        print(f"[bench] gradient statistics: {json.dumps(out['gradient_statistics_c3'])}", flush=True)
     if not args.no_large and not args.no_adjoint and args.config == "c2":
         out["large_grids"] = large_grids(M, torch, np, stream, args.large_photons)
+        from paper_1512_02110_amd import micro
+        out["large_grids"]["gather_ceiling"] = {
+            name: micro.gather_ceiling(make(), n)
+            for name, make, n in (("c4", scenes.config4, 4_000_000), ("c5", scenes.config5, 10_000_000))}
+        out["recovery_c5"] = descent_c5(M, torch, np)
+        print(f"[bench] c5 descent: {json.dumps(out['recovery_c5'])}", flush=True)
+        if not args.no_c4_full:
+            out["large_grids"]["c4_full"] = c4_full_replay(M, torch, np, stream)
     if not args.no_voxel:
         out["voxel_model"] = voxel_model(M, torch, np, stream, s)
         out["recovery"] = recovery(M, torch, np, stream, s)

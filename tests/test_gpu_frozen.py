@@ -93,17 +93,19 @@ def test_frozen_argument_errors(M):
         M.mc_render_frozen(s, b, b[:-1].contiguous(), transport="fp32")
 
 
-@pytest.mark.parametrize("transport,tally", [("fp64", "f64"), ("fp32", "kahan32")])
-def test_gradient_finite_differences_64_voxels(M, transport, tally):
+@pytest.mark.parametrize("transport,tally,n", [("fp64", "f64", 100_003), ("fp32", "kahan32", 100_003),
+                                               ("fp32", "kahan32", 100_000_000), ("fp32", "f64", 100_000_000)])
+def test_gradient_finite_differences_64_voxels(M, transport, tally, n):
     """The adjoint workload's check: the L2 loss of the 16^3 initial estimate
     against the truth's images, the GPU gradient against central differences
     (h = 1e-3 beta0(m)) of the GPU's frozen-event images on 64 random voxels
-    (default_rng(3)); FP64 transport to the differencing error, FP32 with
-    Kahan tallies to 1e-3."""
+    (default_rng(3)); FP64 transport to the differencing error, FP32 (Kahan
+    or FP64 tallies) to 1e-3; at 1e5 photons and at the workload's own 1e8
+    (128 frozen renders of 1e8 photons each)."""
     import torch
-    s = scenes.config3_initial(n_photons=100_003)
-    truth = scenes.config3_truth(n_photons=100_003, seed=1)
-    print(f"case fd 64 voxels {transport} {tally}", flush=True)
+    s = scenes.config3_initial(n_photons=n)
+    truth = scenes.config3_truth(n_photons=n, seed=1)
+    print(f"case fd 64 voxels {transport} {tally} n={n}", flush=True)
     meas, _ = M.mc_render(truth, M.beta_tensor(truth, transport), transport=transport, tally=tally)
     b = M.beta_tensor(s, transport)
     img, _ = M.mc_render(s, b, transport=transport, tally=tally)
