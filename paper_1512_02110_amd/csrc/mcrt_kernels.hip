@@ -735,10 +735,15 @@ __device__ __forceinline__ bool job_step(const KArgs<Real>& A, const uint32_t* m
     const Real tend = last ? J.r : tn;
     const Real l = tend - J.W.t;
     if (MODE == MODE_GRAD && J.phase == 2) {
-        // second walk of the gradient: only the deposit
-        grad_add<Real, TALLY>(A, lds_grad, J.W.k, -J.a * (double)l);
+        // second walk of the gradient: only the deposit.  A crossing within
+        // a few ulps of the clipped end is taken as the end: past a side face
+        // of the domain the linear index would wrap into another voxel, which
+        // would receive the ray's last sliver
+        const Real near_end = J.r * (Real)(sizeof(Real) == 4 ? 1.0 - 0x1p-18 : 1.0 - 0x1p-44);
+        const bool end = last || tn >= near_end;
+        grad_add<Real, TALLY>(A, lds_grad, J.W.k, -J.a * (double)((end ? J.r : tn) - J.W.t));
         conn_cross(J.W, tn, cx, cy, cz);
-        return last || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
+        return end || (uint32_t)J.W.k >= (uint32_t)A.n_vox;
     }
     J.tau += (double)prev * (double)J.lp;
     J.lp = l;

@@ -111,6 +111,9 @@ def load_library(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise OSError(f"{path} is missing: build it with `python -m paper_1512_02110_amd.build`")
+        # torch first: its HIP runtime is then the one the library binds to
+        # (a second copy loaded ahead of torch's is not safe in one process)
+        import torch  # noqa: F401
         L = C.CDLL(path)
         vp, dp = C.c_void_p, C.POINTER(C.c_double)
         L.mc_render.argtypes = [C.POINTER(McGrid), vp, C.c_int, C.POINTER(McCamera),

@@ -17,6 +17,7 @@ LIB = os.path.join(PKG, "libmcrt_micro.so")
 
 
 def _lib():
+    import torch  # noqa: F401  (torch's HIP runtime first, as in mcrt.load_library)
     L = C.CDLL(LIB)
     L.mc_micro_gather.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p,
                                   C.c_void_p]
