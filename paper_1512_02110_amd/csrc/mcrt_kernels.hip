@@ -1513,6 +1513,15 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
         // last prefetched records), and at the very end until all are
         const uint32_t keep = more ? (uint32_t)WAVE - DEP_REFILL_IDLE : (pending && nbusy > 0 ? nbusy - 1 : 0u);
         while ((uint32_t)__popcll(__ballot(busy)) > keep) {
+            // eight voxels per check of the busy count (measured: 4-5% less
+            // deposit time than two per check on the 64^3 and 256x256x128
+            // workloads; a finished lane steps on with nothing to add)
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc, busy);
             dep_step(D, s_g, a, nloc, busy);
             dep_step(D, s_g, a, nloc, busy);
         }
