@@ -42,9 +42,10 @@ namespace mcrt {
 
 constexpr int WAVE = 64;
 constexpr uint32_t QCAP = 128;     // local-estimate jobs per wavefront queue
-constexpr uint32_t REFILL_IDLE = 16;
-// The deposit refills later: its per-record set-up is long and runs on the
-// refilled lanes only.
+// A wavefront's connection walks are refilled from its queue once this many
+// lanes are idle (measured on the 64^3 and 128^3 workloads: 32 is 2% faster
+// than 16 or 24, 8 and 12 are slower); the deposit of the gradient likewise.
+constexpr uint32_t REFILL_IDLE = 32;
 constexpr uint32_t DEP_REFILL_IDLE = 32;
 
 // Photon packet: voxel-local position (voxel i, fraction f of the voxel
