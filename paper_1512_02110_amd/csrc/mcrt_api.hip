@@ -465,6 +465,10 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         // (slots are 32-bit indices: at most 2^31 - 1 records)
         const uint64_t lim = std::min<uint64_t>(free_b / 8 * 3, (uint64_t)96 << 30) / rec;
         P = std::max<uint64_t>(n_photons * 48, (uint64_t)1 << 20);
+        // a workload measured before gets room for all its rays and their
+        // bins at once where memory allows: every chunk is a launch of the
+        // replay with its own tail (the last, longest photons)
+        if (hint > 0.0) P = std::max<uint64_t>(P, (uint64_t)std::min(5.8 * hint * (double)n_photons, 4.0e18));
         P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
         if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
     }
