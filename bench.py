@@ -565,19 +565,19 @@ def mixture(M, torch, np, stream, s, n_grad=10_000_000):
     return out
 
 
-def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=10, n_gd=5, n_side=2):
+def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=40, n_gd=5, n_side=2):
     """The surrogate recovery loop (Secs. 5.2, 6, 7) on the same grid and
     cameras, with each reading of the conditioning Q_c of Sec. 6: 1/count
     (this build's reading), the count itself (the passage's wording taken
     literally) and none.  Measured images of the truth from the voxelised
     model (seed 99, Eq. (noise) grey levels with seeded read noise, back to
-    radiance); start 0.7 x the truth smoothed over a voxel; a small Laplacian
-    weight.  paper_1512_02110_amd.descent.mc_voxel_descent: step size from
-    5% of max beta over the largest first gradient, halved whenever an outer
-    iteration's steps do not all lower its cost.  eps and delta_mass after
-    every outer iteration (a photon pass for j, then n_gd steps), and the
-    time per photon pass."""
-    from paper_1512_02110_amd import scenes
+    radiance); start: a uniform field at the truth's mean extinction; no
+    regulariser.  paper_1512_02110_amd.descent.mc_voxel_descent: step size
+    from 5% of max beta over the largest first gradient, halved whenever an
+    outer iteration's steps do not all lower its cost and grown by 1.25
+    after one that needed no halving.  eps and delta_mass after every outer
+    iteration (a photon pass for j, then n_gd steps), and the time per
+    photon pass."""
     from paper_1512_02110_amd.descent import mc_voxel_descent
     truth = s.with_beta(s.beta)
     t32 = M.beta_tensor(truth, "fp32")
@@ -587,19 +587,18 @@ def recovery(M, torch, np, stream, s, n_photons=10_000_000, n_outer=10, n_gd=5, 
     normals = torch.as_tensor(np.random.default_rng(5).normal(size=clean.numel()), device="cuda")
     grey, scale = M.mc_camera_noise(clean, normals)
     meas = grey / scale
-    b0 = 0.7 * scenes.smooth(truth.beta3d(), 1.0).reshape(-1)
     s0 = truth.replace(n_photons=n_photons)
-    b0t = torch.as_tensor(b0, device="cuda")
-    eta = 1e-3
+    b0t = torch.full((s.n_vox,), float(truth.beta.mean()), dtype=torch.float64, device="cuda")
     e0 = M.mc_recovery_error(b0t, t64)
     out = {"workload": f"same grid and cameras; {n_photons:.0e} photons per surrogate iteration, {n_outer} "
-                       f"iterations x {n_gd} steps, {n_side}x{n_side} rays per pixel",
+                       f"iterations x {n_gd} steps, {n_side}x{n_side} rays per pixel; start: uniform at the "
+                       f"truth's mean extinction",
            "delta_mass_start": e0[0], "eps_start": e0[1], "readings": {}}
     for name, cond in (("q_1_over_count", 1), ("q_count", 2), ("none", 0)):
         a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
         _, recs, delta = mc_voxel_descent(s0, b0t, meas, n_outer, n_gd=n_gd, conditioned=cond, rays_per_side=n_side,
-                                          eta=eta, truth=t64)
+                                          truth=t64, grow=1.25)
         e.record(stream)
         torch.cuda.synchronize()
         eps = [e0[1]] + [r["eps"] for r in recs]

@@ -98,7 +98,7 @@ def mc_voxel_descent(s, beta0, measured, n_outer, n_gd=5, delta=None, conditione
     record holds the outer iteration's costs before each of its steps, the
     step size used and the halvings it took, and, with truth, delta_mass
     and eps after its last step."""
-    import numpy as np
+
     import torch
     from paper_1512_02110_amd import mcrt as M
     b = beta0.detach().to(device="cuda", dtype=torch.float64).contiguous().reshape(-1).clone()
