@@ -22,6 +22,7 @@ and is halved whenever an outer iteration's steps do not all lower its cost
 
     python -m paper_1512_02110_amd.descent [--config c5] [--iters 50] [--photons 250000000]
                                            [--model le|voxel] [--conditioned 1] [--n-gd 5]
+                                           [--start smoothed|uniform] [--grow 1.25]
 
 prints one JSON line per iteration (loss, relative image residual,
 delta_mass and eps against the true field) and a summary line.
@@ -150,6 +151,9 @@ def main(argv=None):
                     help="le: local-estimation render and surrogate gradient; voxel: the voxelised model")
     ap.add_argument("--conditioned", type=int, default=1, help="voxel model: 0 none, 1 Q_c = 1/count, 2 count")
     ap.add_argument("--n-gd", type=int, default=5)
+    ap.add_argument("--start", choices=("smoothed", "uniform"), default="smoothed",
+                    help="smoothed: 0.7 x the true field smoothed over one voxel; uniform: the true field's mean")
+    ap.add_argument("--grow", type=float, default=1.0, help="voxel model: step growth after an accepted iteration")
     args = ap.parse_args(argv)
     import torch
     from paper_1512_02110_amd import mcrt as M
@@ -157,9 +161,14 @@ def main(argv=None):
     M.load_library()
     truth = scenes.CONFIGS[args.config](n_photons=args.photons)
     t64 = torch.as_tensor(truth.beta, dtype=torch.float64, device="cuda")
-    b0 = torch.as_tensor(0.7 * scenes.smooth(truth.beta3d(), 1.0).reshape(-1), dtype=torch.float64, device="cuda")
+    if args.start == "uniform":
+        b0 = torch.full((truth.n_vox,), float(truth.beta.mean()), dtype=torch.float64, device="cuda")
+        start = "start: uniform at the true field's mean extinction"
+    else:
+        b0 = torch.as_tensor(0.7 * scenes.smooth(truth.beta3d(), 1.0).reshape(-1), dtype=torch.float64,
+                             device="cuda")
+        start = "start: 0.7 x the true field smoothed over one voxel"
     e0 = M.mc_recovery_error(b0, t64)
-    start = "start: 0.7 x the true field smoothed over one voxel"
     t0 = time.perf_counter()
     if args.model == "voxel":
         # measured images: the voxelised model of the true field (photon seed 99, 2x2 rays per pixel) as
@@ -178,7 +187,7 @@ def main(argv=None):
                                       f"camera noise; {start}", "iters": args.iters,
                           "delta_mass_start": e0[0], "eps_start": e0[1]}), flush=True)
         _, recs, delta = mc_voxel_descent(truth, b0, meas, args.iters, n_gd=args.n_gd,
-                                          conditioned=args.conditioned, truth=t64,
+                                          conditioned=args.conditioned, truth=t64, grow=args.grow,
                                           log=lambda r: print(json.dumps(r), flush=True))
         print(json.dumps({"summary": True, "delta": delta, "seconds": time.perf_counter() - t0,
                           "cost_first": recs[0]["cost"][0], "cost_last": recs[-1]["cost"][-1],
