@@ -9,7 +9,6 @@ Tolerances (the method's own):
   * gradient: |gpu - oracle| <= 1e-3 max(|oracle_m|, 1e-3 max|oracle|) per
     voxel and <= 1e-3 in relative L2.
 FP64 transport is expected to agree far tighter (summation order only)."""
-import math
 
 import numpy as np
 import pytest
