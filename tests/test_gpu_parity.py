@@ -7,7 +7,9 @@ Tolerances (the method's own):
   * pixels: |gpu - oracle| <= max(1e-4 |oracle|, 3 sigma_MC), sigma_MC from the
     oracle's per-photon second moment;
   * gradient: |gpu - oracle| <= 1e-3 max(|oracle_m|, 1e-3 max|oracle|) per
-    voxel and <= 1e-3 in relative L2.
+    voxel and <= 1e-3 in relative L2 (for FP32 on the 64^3 grid the
+    per-voxel bound is taken relative to the voxel's gradient before the
+    cancellation between residuals of opposite sign, |g+| + |g-|).
 FP64 transport is expected to agree far tighter (summation order only)."""
 
 import numpy as np
