@@ -132,3 +132,26 @@ def test_full_size_config2_precisions(M):
     bad = np.abs(i32 - i64n) > np.maximum(1e-4 * np.abs(i64n), 3 * sig)
     print(f"fp32 vs fp64: {(_rel(i32[nz], i64n[nz]) <= 1e-4).mean():.4f} of pixels within 1e-4", flush=True)
     assert not bad.any(), np.flatnonzero(bad)[:10]
+
+
+def test_mixed_and_fp32_on_the_multi_cloud_crop(M, oracle):
+    """The multi-cloud workload's 32^3 crop about its densest column with its
+    36 cameras (most of them outside the crop, some inside): mixed precision
+    follows the oracle's photons (equal counters, pixels within 1e-5), FP32
+    within max(1e-4, 3 sigma)."""
+    from .test_gpu_descent import _crop5
+    s = _crop5(n_photons=3000)
+    print("case mixed / fp32 on the c5 crop (3000 photons, 36 cameras)", flush=True)
+    ref, rst, m2 = oracle.render(s, with_m2=True)
+    img, st = M.mc_render(s, M.beta_tensor(s, "mixed"), transport="mixed")
+    for k in COUNTERS:
+        assert st[k] == rst[k], (k, st[k], rst[k])
+    img = img.cpu().numpy()
+    nz = np.abs(ref) > 0
+    assert _rel(img[nz], ref[nz]).max(initial=0.0) <= 1e-5
+    assert np.abs(img[~nz]).max(initial=0.0) <= 1e-12 * np.abs(ref).max(initial=1.0)
+    i32, g2, _ = M.mc_render_moments(s, M.beta_tensor(s, "fp32"), transport="fp32")
+    i32, g2 = i32.cpu().numpy(), g2.cpu().numpy()
+    sig = np.sqrt(np.maximum(m2 + g2 - 2 * ref ** 2 / s.n_photons, 0.0))
+    bad = np.abs(i32 - ref) > np.maximum(1e-4 * np.abs(ref), 3 * sig)
+    assert not bad.any(), np.flatnonzero(bad)[:10]
