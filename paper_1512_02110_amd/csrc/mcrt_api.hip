@@ -432,10 +432,303 @@ void set_tape_hint(uint64_t key, double rate) {
     g_tape_key[dev] = key;
 }
 
+// Two library streams per device for the overlapped replay (created once,
+// default priority, kept until the process ends).
+hipStream_t g_rstream[MAX_DEVICES][2] = {};
+
+bool replay_streams(hipStream_t out[2]) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return false;
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (int i = 0; i < 2; ++i) {
+        if (!g_rstream[dev][i] && hipStreamCreateWithFlags(&g_rstream[dev][i], hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            g_rstream[dev][i] = nullptr;
+            return false;
+        }
+        out[i] = g_rstream[dev][i];
+    }
+    return true;
+}
+
+// The gradient replay of run_tape with two ray buffers, so that the replay
+// of one chunk (on a library stream) overlaps the binning and deposits of
+// the previous one (on the caller's stream) and, above all, the tail of the
+// previous replay: every replay launch ends with a few wavefronts on the
+// last, longest photons, and the next launch's wavefronts fill the compute
+// units they leave.  The tape space holds two ray regions of r_cap slots and
+// the bins (b_cap slots); the split is fixed for the call (from the
+// workload's measured rays per photon when there is one), the chunk sizes
+// adapt to what each counted chunk measured.  A chunk whose rays overflowed
+// a slice, or with a bin larger than the bin space, goes back to the queue
+// of ranges and is replayed in halves; photon ranges may complete out of
+// order (the gradient is a sum).
+template <typename Real>
+int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit,
+                     int max_blocks, int n_cu, unsigned long long* counters, unsigned long long* host_sum,
+                     double* t_transport, double* t_tape, hipStream_t stream, uint64_t wkey,
+                     const hipStream_t rs[2]) {
+    int rc = MC_OK;
+    const int nt = A.tp.n_tiles;
+    const size_t rec = sizeof(TapeRec<Real>);
+    const int wpb = BLOCK / 64;  // wavefronts per block
+    size_t free_b = 0;
+    char* pool = nullptr;
+    // per buffer: tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
+    uint32_t* meta[2] = {nullptr, nullptr};
+    unsigned long long* ctr1 = nullptr;  // counters of buffer 1 (buffer 0 uses the caller's)
+    DepositItem* ditems = nullptr;
+    const int max_items = nt + 4 * n_cu + 1;
+    std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
+    std::vector<DepositItem> h_items;
+    // pinned host copies per buffer: tile counts, overflow flag, wave counts, counters
+    char* hpin[2] = {nullptr, nullptr};
+    size_t hpin_bytes = 0, off_over = 0, off_wave = 0, off_ctr = 0;
+    hipEvent_t ev_start = nullptr, counted[2] = {nullptr, nullptr}, deposited[2] = {nullptr, nullptr};
+    hipEvent_t r0[2] = {nullptr, nullptr}, r1[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> dep_ev;  // begin, end of every chunk's binning and deposits (timed calls)
+    struct Slot {
+        bool used = false;
+        uint64_t start = 0, n = 0;
+        int nw = 0;
+    };
+    Slot slot[2];
+    KArgs<Real> ka[2] = {A, A};
+    std::vector<std::pair<uint64_t, uint64_t>> pending;  // ranges to replay again, smaller
+    std::vector<int> order;                             // buffers in flight, in issue order
+    uint64_t P = 0, r_cap = 0, b_cap = 0, next = 0, chunk = 0;
+    int max_nw = 0;
+    const double hint = tape_hint(wkey);
+    double max_rate = 0.0;
+    float ms = 0.f;
+
+    CHECK_HIP(available_bytes(&free_b));
+    {
+        // (slots are 32-bit indices: at most 2^31 - 1 records)
+        const uint64_t lim = std::min<uint64_t>(free_b / 8 * 3, (uint64_t)96 << 30) / rec;
+        P = std::max<uint64_t>(n_photons * 48, (uint64_t)1 << 20);
+        if (hint > 0.0) P = std::max<uint64_t>(P, (uint64_t)std::min(5.8 * hint * (double)n_photons, 4.0e18));
+        P = std::min<uint64_t>(std::min<uint64_t>(P, lim), ((uint64_t)1 << 31) - 1);
+        if (tape_limit > 0) P = std::min<uint64_t>(P, (uint64_t)tape_limit);
+    }
+    {
+        // slots per photon: a wavefront slice 80% full at the busiest
+        // wavefront's rays per photon, four and a half tile crossings per ray
+        const double rays = hint > 0.0 ? hint / 0.8 : 80.0, bins = hint > 0.0 ? 4.5 * hint : 288.0;
+        r_cap = (uint64_t)((double)P * rays / (2.0 * rays + bins));
+        r_cap = std::min(std::max(r_cap, P / 16), P / 8 * 3);
+        b_cap = P - 2 * r_cap;
+        // at least 64 slots per wavefront (fewer resident blocks if the tape is small)
+        if (r_cap < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_cap / (64 * (uint64_t)wpb));
+        if (max_blocks < 1 || b_cap < 64) return TAPE_FALLBACK;
+        chunk = (uint64_t)std::max(256.0, std::min((double)r_cap / rays, (double)b_cap / bins));
+        chunk = std::min<uint64_t>(n_photons, chunk);
+    }
+    max_nw = max_blocks * wpb;
+    // pinned layout: tile counts [nt], overflow flag, (pad), wave counts [max_nw], counters [1 + ST_N]
+    off_over = sizeof(uint32_t) * (size_t)nt;
+    off_wave = sizeof(uint32_t) * ((size_t)nt + 2);
+    off_ctr = (off_wave + sizeof(uint32_t) * (size_t)max_nw + 7) & ~(size_t)7;
+    hpin_bytes = off_ctr + sizeof(unsigned long long) * (1 + ST_N);
+
+    CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
+    for (int b = 0; b < 2; ++b) {
+        CHECK_HIP(lib_alloc((void**)&meta[b],
+                            sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
+        CHECK_HIP(hipHostMalloc((void**)&hpin[b], hpin_bytes, hipHostMallocDefault));
+        CHECK_HIP(hipEventCreateWithFlags(&counted[b], hipEventDisableTiming));
+        CHECK_HIP(hipEventCreateWithFlags(&deposited[b], hipEventDisableTiming));
+        if (t_transport) {
+            CHECK_HIP(hipEventCreate(&r0[b]));
+            CHECK_HIP(hipEventCreate(&r1[b]));
+        }
+    }
+    CHECK_HIP(lib_alloc((void**)&ctr1, sizeof(unsigned long long) * (1 + ST_N), stream));
+    CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
+    for (int b = 0; b < 2; ++b) {
+        KArgs<Real>& a = ka[b];
+        a.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool) + (size_t)b * r_cap;
+        a.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + 2 * r_cap;
+        a.tp.tile_count = meta[b];
+        a.tp.bin_start = meta[b] + nt;
+        a.tp.tile_end = meta[b] + 2 * nt;
+        a.tp.overflow = meta[b] + 3 * nt;
+        a.tp.wave_count = meta[b] + 3 * nt + 1;
+        a.tp.slice = meta[b] + 3 * nt + 1 + max_nw;
+        a.work = b == 0 ? counters : ctr1;
+        a.stats = a.work + 1;
+    }
+    // the replay streams start after what the caller's stream holds (the
+    // tape space's previous users, the allocations above)
+    CHECK_HIP(hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
+    CHECK_HIP(hipEventRecord(ev_start, stream));
+    for (int b = 0; b < 2; ++b) CHECK_HIP(hipStreamWaitEvent(rs[b], ev_start, 0));
+
+    {
+#define TRY_HIP(expr)                          \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+        // replay the next range into buffer b and count its rays per tile
+        auto issue = [&](int b) -> hipError_t {
+            uint64_t st = 0, n = 0;
+            if (!pending.empty()) {
+                st = pending.back().first;
+                n = pending.back().second;
+                if (n > chunk) {
+                    pending.back().first += chunk;
+                    pending.back().second -= chunk;
+                    n = chunk;
+                } else {
+                    pending.pop_back();
+                }
+            } else if (next < n_photons) {
+                st = next;
+                n = std::min<uint64_t>(chunk, n_photons - next);
+                next += n;
+            } else {
+                return hipSuccess;  // nothing left: the buffer stays idle
+            }
+            Slot& S = slot[b];
+            KArgs<Real>& a = ka[b];
+            const hipStream_t s = rs[b];
+            const int grid = (int)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, (uint64_t)max_blocks);
+            S.start = st;
+            S.n = n;
+            S.nw = grid * wpb;
+            a.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / S.nw, 0xffffffffu);
+            a.tp.w0 = 0;
+            a.tp.n_slices = S.nw;
+            a.pid0 = pid0 + st;
+            a.n_photons = n;
+            // the buffer's rays and counts are free once its last chunk is deposited
+            if (S.used) TRY_HIP(hipStreamWaitEvent(s, deposited[b], 0));
+            TRY_HIP(launch_fill_u32(a.tp.tile_count, nt, s));
+            TRY_HIP(launch_fill_u32(a.tp.overflow, 1, s));
+            TRY_HIP(launch_fill_u64(a.work, 1 + ST_N, s));
+            if (r0[b]) TRY_HIP(hipEventRecord(r0[b], s));
+            TRY_HIP(launch_transport<Real>(a, MODE_TAPE, TALLY_F64, grid, s));
+            if (r1[b]) TRY_HIP(hipEventRecord(r1[b], s));
+            TRY_HIP(launch_bin<Real>(a, false, s));
+            char* h = hpin[b];
+            TRY_HIP(hipMemcpyAsync(h, a.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost, s));
+            TRY_HIP(hipMemcpyAsync(h + off_over, a.tp.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            TRY_HIP(hipMemcpyAsync(h + off_wave, a.tp.wave_count, sizeof(uint32_t) * S.nw, hipMemcpyDeviceToHost, s));
+            TRY_HIP(hipMemcpyAsync(h + off_ctr, a.work, sizeof(unsigned long long) * (1 + ST_N),
+                                   hipMemcpyDeviceToHost, s));
+            TRY_HIP(hipEventRecord(counted[b], s));
+            S.used = true;
+            order.push_back(b);
+            return hipSuccess;
+        };
+#undef TRY_HIP
+        CHECK_HIP(issue(0));
+        CHECK_HIP(issue(1));
+        while (!order.empty()) {
+            const int b = order.front();
+            order.erase(order.begin());
+            Slot& S = slot[b];
+            CHECK_HIP(hipEventSynchronize(counted[b]));
+            if (r0[b]) {
+                CHECK_HIP(hipEventElapsedTime(&ms, r0[b], r1[b]));
+                *t_transport += ms;
+            }
+            const char* h = hpin[b];
+            const uint32_t* hc = reinterpret_cast<const uint32_t*>(h);
+            const uint32_t h_over = *reinterpret_cast<const uint32_t*>(h + off_over);
+            const uint32_t* hw = reinterpret_cast<const uint32_t*>(h + off_wave);
+            const unsigned long long* hctr = reinterpret_cast<const unsigned long long*>(h + off_ctr);
+            uint32_t busiest = 0;
+            for (int w = 0; w < S.nw; ++w) busiest = std::max(busiest, hw[w]);
+            const double rate = (double)busiest * S.nw / (double)S.n;  // rays per photon, busiest wavefront
+            uint64_t crossings = 0;
+            bool too_big = h_over != 0;
+            for (int i = 0; i < nt; ++i) {
+                crossings += hc[i];
+                too_big = too_big || hc[i] > b_cap;
+            }
+            if (too_big) {
+                // nothing of it reached the gradient: replay its range in halves
+                if (S.n == 1) {
+                    rc = MC_ERR_OUT_OF_MEMORY;
+                    goto done;
+                }
+                pending.push_back({S.start, S.n});
+                chunk = std::max<uint64_t>(1, S.n / 2);
+                CHECK_HIP(issue(b));
+                continue;
+            }
+            max_rate = std::max(max_rate, rate);
+            for (int i = 1; i < 1 + ST_N; ++i) host_sum[i] += hctr[i];
+            std::copy(hc, hc + nt, h_count.begin());
+            // the host arrays of the previous chunk's deposits must have been read
+            CHECK_HIP(hipStreamSynchronize(stream));
+            if (t_tape) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                CHECK_HIP(hipEventCreate(&e0));
+                dep_ev.push_back(e0);
+                CHECK_HIP(hipEventCreate(&e1));
+                dep_ev.push_back(e1);
+                CHECK_HIP(hipEventRecord(e0, stream));
+            }
+            rc = deposit_groups<Real>(ka[b], tally, h_count, b_cap, n_cu, ditems, max_items, h_bins, h_items, stream);
+            if (rc != MC_OK) goto done;
+            if (t_tape) CHECK_HIP(hipEventRecord(dep_ev.back(), stream));
+            CHECK_HIP(hipEventRecord(deposited[b], stream));
+            // next chunk: the busiest wavefront's slice about 80% full and the
+            // crossings (with 5% to spare) in the bin space
+            if (rate > 0.0) {
+                const double rays = rate / 0.8, bins = 1.05 * (double)crossings / (double)S.n;
+                double nx = std::floor((double)r_cap / rays);
+                if (bins > 0.0) nx = std::min(nx, std::floor((double)b_cap / bins));
+                chunk = (uint64_t)std::max(1.0, nx);
+            }
+            CHECK_HIP(issue(b));
+        }
+    }
+    CHECK_HIP(hipStreamSynchronize(stream));
+    for (size_t i = 0; i + 1 < dep_ev.size(); i += 2) {
+        CHECK_HIP(hipEventElapsedTime(&ms, dep_ev[i], dep_ev[i + 1]));
+        *t_tape += ms;
+    }
+    // (chunks of very few photons measure noisy rates: only large calls set the hint)
+    if (n_photons >= 65536) set_tape_hint(wkey, max_rate);
+
+done:
+    // nothing may still run on the replay streams when the buffers are released
+    for (int b = 0; b < 2; ++b) (void)hipStreamSynchronize(rs[b]);
+    for (void* p : {(void*)ditems, (void*)ctr1, (void*)meta[0], (void*)meta[1]}) {
+        if (!p) continue;
+        hipError_t e = hipFreeAsync(p, stream);
+        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    }
+    if (pool) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        buf_release(dev, BUF_BINS, pool, stream);
+    }
+    // the host arrays above were sources or targets of asynchronous copies
+    (void)hipStreamSynchronize(stream);
+    for (int b = 0; b < 2; ++b)
+        if (hpin[b]) (void)hipHostFree(hpin[b]);
+    for (hipEvent_t e : {ev_start, counted[0], counted[1], deposited[0], deposited[1], r0[0], r0[1], r1[0], r1[1]})
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : dep_ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
 template <typename Real>
 int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit, int max_blocks,
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
              double* t_tape, hipStream_t stream, uint64_t wkey, const MixPath* mp = nullptr) {
+    if (!mp) {
+        hipStream_t rs[2];
+        if (replay_streams(rs))
+            return run_tape_overlap<Real>(A, tally, n_photons, pid0, tape_limit, max_blocks, n_cu, counters,
+                                          host_sum, t_transport, t_tape, stream, wkey, rs);
+    }
     int rc = MC_OK;
     // device times: replay (r0, r1), binning + deposit of the last chunk (b0, b1)
     hipEvent_t r0 = nullptr, r1 = nullptr, b0 = nullptr, b1 = nullptr;
