@@ -357,7 +357,8 @@ int deposit_groups(KArgs<Real>& A, int tally, const std::vector<uint32_t>& h_cou
             h_bins[nt + i] = o + h_count[i];
             o += h_count[i];
         }
-        const uint64_t R = std::max<uint64_t>(8192, (sum + 2 * n_cu - 1) / (2 * (uint64_t)n_cu));
+        const uint64_t per = (uint64_t)DEP_ITEMS_PER_CU * n_cu;
+        const uint64_t R = std::max<uint64_t>(8192, (sum + per - 1) / per);
         h_items.clear();
         for (int i = g0; i < g1; ++i)
             for (uint64_t lo = 0; lo < h_count[i]; lo += R) {
@@ -368,6 +369,11 @@ int deposit_groups(KArgs<Real>& A, int tally, const std::vector<uint32_t>& h_cou
                 d.pad_ = 0;
                 h_items.push_back(d);
             }
+        // blocks start in launch order as CUs free up: the largest items
+        // first, so that the last ones to start are the short remainders
+        std::stable_sort(h_items.begin(), h_items.end(), [](const DepositItem& x, const DepositItem& y) {
+            return x.hi - x.lo > y.hi - y.lo;
+        });
         if ((int)h_items.size() > max_items) return MC_ERR_HIP;
         A.tp.t_lo = g0;
         A.tp.t_hi = g1;
@@ -478,7 +484,7 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     uint32_t* meta[2] = {nullptr, nullptr};
     unsigned long long* ctr1 = nullptr;  // counters of buffer 1 (buffer 0 uses the caller's)
     DepositItem* ditems = nullptr;
-    const int max_items = nt + 4 * n_cu + 1;
+    const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
     std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
     std::vector<DepositItem> h_items;
     // pinned host copies per buffer: tile counts, overflow flag, wave counts, counters
@@ -742,7 +748,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     // tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
     uint32_t* meta = nullptr;
     DepositItem* ditems = nullptr;
-    const int max_items = nt + 4 * n_cu + 1;
+    const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
     std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
     std::vector<uint32_t> h_wave;
     std::vector<DepositItem> h_items;
@@ -944,7 +950,7 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     char* pool = nullptr;
     uint32_t* meta = nullptr;  // tile_count[nt], bin_start[nt], tile_end[nt], slice[nt][nw]
     DepositItem* ditems = nullptr;
-    const int max_items = nt + 4 * n_cu + 1;
+    const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
     std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
     std::vector<uint32_t> h_wave((size_t)T->nw);
     std::vector<DepositItem> h_items;
