@@ -563,6 +563,7 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
         a.tp.slice = meta[b] + 3 * nt + 1 + max_nw;
         a.work = b == 0 ? counters : ctr1;
         a.stats = a.work + 1;
+        a.tp.scale_gw = 1;  // the replay writes C, the binning passes multiply by gw[pixel]
     }
     // the replay streams start after what the caller's stream holds (the
     // tape space's previous users, the allocations above)
@@ -797,6 +798,9 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     A.tp.overflow = meta + 3 * nt;
     A.tp.wave_count = meta + 3 * nt + 1;
     A.tp.slice = meta + 3 * nt + 1 + max_nw;
+    // the replay writes C and the binning passes multiply by gw[pixel], except
+    // for a mixture's full gradient, whose replay sums gw C per collision
+    A.tp.scale_gw = mp ? 0 : 1;
 
     if (mp) {
         A.mix_rows = mp->rows;

@@ -653,7 +653,7 @@ struct Job {
     double tau;    // optical depth so far (FP64)
     double a;      // gradient weight of the second walk
     int pix;
-    double gwp;    // gradient weight of the pixel (loaded when the ray starts)
+    double gwp;    // gradient weight of the pixel (loaded when the ray starts, or 1)
     int phase;     // 1: optical depth, 2: gradient scatter
     uint32_t steps;
     uint32_t evi;  // tape replay of a mixture: slot of the estimate's collision in mix_rows
@@ -882,7 +882,12 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C,
                     J.pre = Q.pre[slot];
                     J.pix = Q.pix[slot];
                     if (MODE == MODE_TAPE) {
-                        J.gwp = A.gw[J.pix];  // needed when the ray finishes
+                        // the weight of the pixel, needed when the ray
+                        // finishes, unless the binning pass applies it
+                        // (scale_gw): a gather that misses L2 would hold up
+                        // the walk's first loads (vector loads complete in
+                        // order)
+                        J.gwp = A.tp.scale_gw ? 1.0 : A.gw[J.pix];
                         if (A.mix_rows) J.evi = Q.evi[slot];
                     }
                     J.phase = 1;
