@@ -1315,7 +1315,7 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_bin_scan(KArgs<Real> A) {
 // dt = inf and are never chosen.
 template <typename Real>
 struct DepWalk {
-    int k, kx, ky, kz;
+    int k, kx, ky, kz;  // LDS byte offset of the voxel, and its step on each axis
     Real tx, ty, tz;
     Real dtx, dty, dtz;
     Real t, len;
@@ -1378,12 +1378,13 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     const Real d[3] = {A.G.dx, A.G.dy, A.G.dz};
     const Real id[3] = {A.G.idx, A.G.idy, A.G.idz};
     const int e[3] = {L.nx, L.ny, L.nz};
-    const int stride[3] = {1, px, pxy};
+    // LDS byte offsets: the walk adds them to the address it deposits at
+    const int stride[3] = {(int)sizeof(double), (int)sizeof(double) * px, (int)sizeof(double) * pxy};
     bool mov[3];
     Real w[3];
     Real t0 = (Real)0, t1 = r;
     for (int ax = 0; ax < 3; ++ax) {
-        mov[ax] = (v[ax] > tiny) | (v[ax] < -tiny);
+        mov[ax] = fabs(v[ax]) > tiny;
         w[ax] = d[ax] * m_rcp(mov[ax] ? v[ax] : (Real)1);
         const Real ta = ((Real)0 - o[ax]) * w[ax], tb = ((Real)e[ax] - o[ax]) * w[ax];
         t0 = mov[ax] ? fmax(t0, fmin(ta, tb)) : t0;
@@ -1397,14 +1398,12 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
     for (int ax = 0; ax < 3; ++ax) {
         // entry voxel and fraction; the first crossing; the increment
         const Real p = o[ax] + t0 * v[ax] * id[ax];
-        Real fl = m_floor(p);
-        fl = fl < (Real)0 ? (Real)0 : (fl > (Real)(e[ax] - 1) ? (Real)(e[ax] - 1) : fl);
-        Real fr = p - fl;
-        fr = fr < (Real)0 ? (Real)0 : (fr > (Real)1 ? (Real)1 : fr);
+        const Real fl = fmin(fmax(m_floor(p), (Real)0), (Real)(e[ax] - 1));
+        const Real fr = fmin(fmax(p - fl, (Real)0), (Real)1);
         D.k += (int)fl * stride[ax];
         const bool up = w[ax] > (Real)0;
         ks[ax] = mov[ax] ? (up ? stride[ax] : -stride[ax]) : 0;
-        dt[ax] = mov[ax] ? (up ? w[ax] : -w[ax]) : (Real)INFINITY;
+        dt[ax] = mov[ax] ? fabs(w[ax]) : (Real)INFINITY;
         tn[ax] = mov[ax] ? (up ? (Real)1 - fr : fr) * dt[ax] : (Real)INFINITY;
     }
     D.kx = ks[0];
@@ -1425,24 +1424,24 @@ __device__ __forceinline__ bool deposit_begin(const KArgs<Real>& A, const DevGri
 // arithmetic (no branch around it); only busy lanes deposit, and an idle
 // lane's walk state is reset by deposit_begin before it is used again.
 template <typename Real>
-__device__ __forceinline__ void dep_step(DepWalk<Real>& D, double* s_g, double a, int nloc, bool& busy) {
+__device__ __forceinline__ void dep_step(DepWalk<Real>& D, double* s_g, double a, uint32_t nloc_b, bool& busy) {
     const int kx = D.kx, ky = D.ky, kz = D.kz;
     const bool cx = (D.tx <= D.ty) && (D.tx <= D.tz);
     const bool cy = !cx && (D.ty <= D.tz);
     const Real tn = fmin(D.tx, fmin(D.ty, D.tz));
     const bool last = tn >= D.len;
     const Real l = (last ? D.len : tn) - D.t;
-    if (busy) atomicAdd(s_g + D.k, -a * (double)l);
+    if (busy) atomicAdd(reinterpret_cast<double*>(reinterpret_cast<char*>(s_g) + D.k), -a * (double)l);
     D.k += cx ? kx : (cy ? ky : kz);
     D.tx += cx ? D.dtx : (Real)0;
     D.ty += cy ? D.dty : (Real)0;
     D.tz += (!cx && !cy) ? D.dtz : (Real)0;
     D.t = tn;
     // a crossing that rounding put just before the end of the clipped ray
-    // must not leave the tile's LDS copy: across a z face the index leaves
-    // [0, nloc), across an x or y face it enters a padding slot (the next
+    // must not leave the tile's LDS copy: across a z face the offset leaves
+    // the copy's nloc_b bytes, across an x or y face it enters a padding slot (the next
     // crossing of that axis is a voxel further on, past the end)
-    busy = busy && !(last || (unsigned)D.k >= (unsigned)nloc);
+    busy = busy && !(last || (uint32_t)D.k >= nloc_b);
 }
 
 // Each lane keeps the next record it will walk in registers, loaded one
@@ -1464,6 +1463,7 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
     // padded LDS layout: slot x + px y + pxy z, x <= nx, y <= ny
     const int px = L.nx + 1, pxy = px * (L.ny + 1);
     const int nloc = pxy * L.nz;
+    const uint32_t nloc_b = (uint32_t)(sizeof(double) * nloc);
     for (int i = threadIdx.x; i < nloc; i += DEPOSIT_BLOCK) s_g[i] = 0.0;
     for (int i = threadIdx.x; CAMS_LDS && i < A.n_cams; i += DEPOSIT_BLOCK) {
         const DevCam<Real>& cam = A.cams[i];
@@ -1522,14 +1522,14 @@ __global__ void __launch_bounds__(DEPOSIT_BLOCK) k_deposit(KArgs<Real> A, const 
             // eight voxels per check of the busy count (measured: 4-5% less
             // deposit time than two per check on the 64^3 and 256x256x128
             // workloads; a finished lane steps on with nothing to add)
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
-            dep_step(D, s_g, a, nloc, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
+            dep_step(D, s_g, a, nloc_b, busy);
         }
     }
     __syncthreads();
