@@ -286,12 +286,11 @@ def adjoint_c3(M, torch, np, stream, n_photons):
             "independent_seed_cosine": float(np.dot(a, c) / (np.linalg.norm(a) * np.linalg.norm(c)))}
 
 
-def c4_full_replay(M, torch, np, stream, n_photons=1_000_000_000):
-    """The 128^3 cloud with 25 cameras at its own 1e9 photons: the forward,
-    and the gradient by photon replay (a render's rays at this count, ~1.2e11
+def full_size_replay(M, torch, np, stream, name, make, n_photons, what):
+    """One large workload at its full photon count: the forward, and the
+    gradient by photon replay (a render's rays at these counts, ~1e10-1e11
     records, do not fit in memory), one timed call each."""
-    from paper_1512_02110_amd import scenes
-    s = scenes.config4(n_photons=n_photons)
+    s = make(n_photons=n_photons)
     beta = M.beta_tensor(s, "fp32")
 
     def timed(fn):
@@ -305,13 +304,15 @@ def c4_full_replay(M, torch, np, stream, n_photons=1_000_000_000):
     img0, _ = M.mc_render(s, beta, n_photons=2_000_000, stats=False)
     dl0 = torch.as_tensor(np.random.default_rng(2).normal(size=img0.numel()), device=img0.device)
     M.mc_grad_beta(s, beta, dl0, n_photons=2_000_000, stats=False)
-    print("[bench] c4 full: forward", flush=True)
+    print(f"[bench] {name} full: forward", flush=True)
     (img, st), t_fwd = timed(lambda: M.mc_render(s, beta))
-    print(f"[bench] c4 full: forward {t_fwd:.0f} ms; gradient by replay", flush=True)
+    print(f"[bench] {name} full: forward {t_fwd:.0f} ms; gradient by replay", flush=True)
     (g, gst), t_adj = timed(lambda: M.mc_grad_beta(s, beta, dl0))
-    print(f"[bench] c4 full: gradient {t_adj:.0f} ms", flush=True)
-    return {"workload": f"c4: 128^3 cloud, 25 cameras 256x256, {n_photons:.0e} photons, FP32 transport + FP64 "
-                        f"tallies; gradient by photon replay (no kept rays)",
+    print(f"[bench] {name} full: gradient {t_adj:.0f} ms", flush=True)
+    del beta, img, g
+    M.mc_release_memory()
+    return {"workload": f"{what}, {n_photons:.1e} photons, FP32 transport + FP64 tallies; gradient by photon "
+                        f"replay (no kept rays)",
             "fwd_ms": round(t_fwd, 1), "fwd_kernel_ms": round(st.timing["transport_ms"], 1),
             "events_per_s": st["events"] / (t_fwd * 1e-3), "events": st["events"], "le_jobs": st["le_jobs"],
             "adj_ms": round(t_adj, 1), "adj_replay_kernel_ms": round(gst.timing["transport_ms"], 1),
@@ -636,8 +637,10 @@ def main():
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxelised-model section")
     ap.add_argument("--no-large", action="store_true", help="skip the 128^3 and 256x256x128 section")
     ap.add_argument("--large-photons", type=int, default=20_000_000)
-    ap.add_argument("--no-c4-full", action="store_true",
-                    help="skip the 128^3 workload at its own 1e9 photons (about three minutes)")
+    ap.add_argument("--no-full-size", "--no-c4-full", dest="no_full_size", action="store_true",
+                    help="skip the gradients by replay at full photon counts: the 256x256x128 workload at "
+                         "its one-GPU share of 2.5e8 photons and the 128^3 workload at its own 1e9 (about three "
+                         "minutes)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -812,8 +815,12 @@ def main():
             for name, make, n in (("c4", scenes.config4, 4_000_000), ("c5", scenes.config5, 10_000_000))}
         out["recovery_c5"] = descent_c5(M, torch, np)
         print(f"[bench] c5 descent: {json.dumps(out['recovery_c5'])}", flush=True)
-        if not args.no_c4_full:
-            out["large_grids"]["c4_full"] = c4_full_replay(M, torch, np, stream)
+        if not args.no_full_size:
+            out["large_grids"]["c5_share"] = full_size_replay(
+                M, torch, np, stream, "c5", scenes.config5, 250_000_000,
+                "c5: 256x256x128 multi-cloud field, 36 cameras 256x256, its one-GPU share of 2e9 photons")
+            out["large_grids"]["c4_full"] = full_size_replay(
+                M, torch, np, stream, "c4", scenes.config4, 1_000_000_000, "c4: 128^3 cloud, 25 cameras 256x256")
     if not args.no_voxel:
         out["voxel_model"] = voxel_model(M, torch, np, stream, s)
         out["recovery"] = recovery(M, torch, np, stream, s)
