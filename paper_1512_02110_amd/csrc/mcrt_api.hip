@@ -335,6 +335,16 @@ void tape_tiles(const mc_grid* g, int& shx, int& shy, int& shz) {
 
 constexpr int TAPE_FALLBACK = 1;
 
+// Binning blocks per wavefront slice for a pass over ns slices (at least
+// BIN_BLOCKS_PER_CU blocks per CU where the slices allow), and the most
+// blocks a pass can have with nw slices at most (the slice matrix's columns).
+int bin_split(int ns, int n_cu) {
+    const int target = BIN_BLOCKS_PER_CU * n_cu;
+    return ns >= target ? 1 : std::min(BIN_SPLIT_MAX, (target + ns - 1) / ns);
+}
+
+size_t bin_blocks_max(int nw, int n_cu) { return (size_t)std::max(nw, 2 * BIN_BLOCKS_PER_CU * n_cu); }
+
 // Bins and deposits the rays of the binning pass set up in A.tp (slices,
 // records, tile counts h_count from its count pass): groups of tiles whose
 // bins fit together in b_cap slots, each turned into bin slots (k_bin_scan),
@@ -540,7 +550,8 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
     for (int b = 0; b < 2; ++b) {
         CHECK_HIP(lib_alloc((void**)&meta[b],
-                            sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
+                            sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu)),
+                            stream));
         CHECK_HIP(hipHostMalloc((void**)&hpin[b], hpin_bytes, hipHostMallocDefault));
         CHECK_HIP(hipEventCreateWithFlags(&counted[b], hipEventDisableTiming));
         CHECK_HIP(hipEventCreateWithFlags(&deposited[b], hipEventDisableTiming));
@@ -606,7 +617,8 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
             S.nw = grid * wpb;
             a.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / S.nw, 0xffffffffu);
             a.tp.w0 = 0;
-            a.tp.n_slices = S.nw;
+            a.tp.split = bin_split(S.nw, n_cu);
+            a.tp.n_slices = S.nw * a.tp.split;
             a.pid0 = pid0 + st;
             a.n_photons = n;
             // the buffer's rays and counts are free once its last chunk is deposited
@@ -789,7 +801,8 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     }
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
     CHECK_HIP(lib_alloc((void**)&meta,
-                        sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * max_nw), stream));
+                        sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu)),
+                            stream));
     CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     A.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool);
     A.tp.tile_count = meta;
@@ -823,7 +836,8 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         A.tp.rw = (uint32_t)std::min<uint64_t>(r_cap / nw, 0xffffffffu);
         A.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + r_cap;
         A.tp.w0 = 0;
-        A.tp.n_slices = nw;  // one binning block per wavefront slice
+        A.tp.split = bin_split(nw, n_cu);
+        A.tp.n_slices = nw * A.tp.split;
         A.pid0 = pid0 + done;
         A.n_photons = n;
         CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
@@ -970,7 +984,8 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     CHECK_HIP(hipEventCreate(&b0));
     CHECK_HIP(hipEventCreate(&b1));
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
-    CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + (size_t)nt * T->nw), stream));
+    CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + (size_t)nt * bin_blocks_max(T->nw, n_cu)),
+                        stream));
     CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     CHECK_HIP(hipMemcpyAsync(h_wave.data(), T->wave_count, sizeof(uint32_t) * T->nw, hipMemcpyDeviceToHost,
                              stream));
@@ -996,7 +1011,8 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
             ++ns;
         }
         A.tp.w0 = w0;
-        A.tp.n_slices = ns;
+        A.tp.split = bin_split(ns, n_cu);
+        A.tp.n_slices = ns * A.tp.split;
         CHECK_HIP(launch_fill_u32(A.tp.tile_count, nt, stream));
         CHECK_HIP(launch_bin<Real>(A, false, stream));
         CHECK_HIP(hipMemcpyAsync(h_count.data(), A.tp.tile_count, sizeof(uint32_t) * nt, hipMemcpyDeviceToHost,

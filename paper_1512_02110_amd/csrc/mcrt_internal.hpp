@@ -78,10 +78,12 @@ struct Tape {
     uint32_t* overflow;       // set when a wavefront ran out of slots
     TapeRec<Real>* brec;      // rays binned by tile
     uint32_t* tile_count;     // [n_tiles] records per tile
-    // [n_tiles][n_slices]: records of tile t from the rays of block (slice)
-    // b of the binning passes; the scan turns them into first bin slots
+    // [n_tiles][n_slices]: records of tile t from the rays of block b of the
+    // binning passes (block b: part b % split of wavefront slice
+    // w0 + b / split); the scan turns them into first bin slots
     uint32_t* slice;
-    int n_slices;
+    int n_slices;             // binning blocks: split per wavefront slice
+    int split;
     const uint32_t* bin_start; // [n_tiles] first slot of each tile's bin
     const uint32_t* tile_end;  // [n_tiles] end of each tile's bin
     int t_lo, t_hi;           // tiles binned by this pass
@@ -172,6 +174,12 @@ constexpr int TILE_LDS = 18560;
 constexpr int MAX_TAPE_TILES = 8192;  // per-tile counters of the binning pass: up to 104 KB of LDS
 constexpr int BIN_LDS_CAMS = 2048;    // camera pixel offsets the binning pass keeps in LDS
 constexpr int BIN_GROUP_TILES = 4096; // tiles per scatter pass (3 LDS words each)
+// Binning blocks of a pass: at least BIN_BLOCKS_PER_CU per compute unit
+// (a slice of the ray tape split over up to BIN_SPLIT_MAX blocks): a pass of
+// a few hundred wavefront slices would otherwise fill a fraction of the GPU,
+// and more, smaller blocks shorten the launch's last round.
+constexpr int BIN_BLOCKS_PER_CU = 32;
+constexpr int BIN_SPLIT_MAX = 64;
 constexpr int SCAN_BLOCK = 256;
 constexpr int DEPOSIT_BLOCK = 1024;
 constexpr int DEP_LDS_CAMS = 256;     // camera centres the deposit keeps in LDS

@@ -1183,16 +1183,19 @@ __device__ __forceinline__ uint32_t camera_of(const KArgs<Real>& A, const int32_
     return (uint32_t)lo;
 }
 
-// Every ray of wavefront slice w0 + blockIdx.x: f(record with its weight and
-// camera index, start voxel, direction, length).  A tape of local estimates
-// (scale_gw) takes the weight gw[pixel] * a here; rays of zero weight are
-// skipped.
+// Every ray of the block's part of its wavefront slice (part
+// blockIdx.x % split of slice w0 + blockIdx.x / split): f(record with its
+// weight and camera index, start voxel, direction, length).  A tape of local
+// estimates (scale_gw) takes the weight gw[pixel] * a here; rays of zero
+// weight are skipped.
 template <typename Real, typename F>
 __device__ __forceinline__ void for_each_block_ray(const KArgs<Real>& A, const int32_t* s_off, F&& f) {
     const Tape<Real>& P = A.tp;
-    const size_t w = (size_t)P.w0 + blockIdx.x;
-    const uint32_t n = min(P.wave_count[w], P.rw);
-    for (uint32_t j = threadIdx.x; j < n; j += BLOCK) {
+    const uint32_t split = (uint32_t)P.split;
+    const size_t w = (size_t)P.w0 + blockIdx.x / split;
+    const uint64_t n = min(P.wave_count[w], P.rw), part = blockIdx.x % split;
+    const uint32_t j0 = (uint32_t)(n * part / split), j1 = (uint32_t)(n * (part + 1) / split);
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += BLOCK) {
         TapeRec<Real> R = P.rec[w * P.rw + j];
         if (P.scale_gw) R.a = (Real)((R.id < (uint32_t)A.n_pix ? A.gw[R.id] : 0.0) * (double)R.a);
         if (R.a == (Real)0) continue;
@@ -2284,7 +2287,7 @@ template hipError_t launch_air_column<double>(const double*, int64_t, int64_t, i
 
 template <typename Real>
 hipError_t launch_bin(const KArgs<Real>& a, bool scatter, hipStream_t s) {
-    const int grid = a.tp.n_slices;  // one wavefront slice per block
+    const int grid = a.tp.n_slices;  // split blocks per wavefront slice
     if (grid <= 0) return hipSuccess;
     const size_t tiles = scatter ? (size_t)(a.tp.t_hi - a.tp.t_lo) : (size_t)a.tp.n_tiles;
     const size_t dyn = sizeof(uint32_t) * ((size_t)std::min(a.n_cams, BIN_LDS_CAMS) + (scatter ? 3 : 1) * tiles);
