@@ -70,7 +70,8 @@ def test_fp64_full_config1_matches_oracle(M, oracle):
     print("case c1 fp64 full", flush=True)
     img, st, ref, rst, m2 = _render_both(M, oracle, s, "fp64")
     assert st["events"] == rst["events"] and st["le_jobs"] == rst["le_jobs"]
-    assert abs(st["vox_conn"] - rst["vox_conn"]) <= 2 * rst["le_jobs"]  # corner cameras
+    # corner cameras: measured +0.68% (0.11 voxels per ray)
+    assert abs(st["vox_conn"] - rst["vox_conn"]) <= min(2 * rst["le_jobs"], 1e-2 * rst["vox_conn"])
     _assert_pixels(img, ref, _sigma(ref, m2, s.n_photons), rel=1e-9)
 
 
@@ -80,6 +81,8 @@ def test_fp32_render_matches_oracle_config2(M, oracle):
     img, st, ref, rst, m2 = _render_both(M, oracle, s, "fp32")
     _assert_pixels(img, ref, _sigma(ref, m2, s.n_photons))
     assert abs(st["events"] - rst["events"]) <= 1e-3 * rst["events"]
+    # the voxel steps of the roofline's numerator: measured +0.17%
+    assert abs(st["vox_conn"] - rst["vox_conn"]) <= 4e-3 * rst["vox_conn"]
     assert abs(img.sum() / ref.sum() - 1) < 1e-4
 
 
@@ -88,8 +91,9 @@ def test_fp64_render_matches_oracle_config2(M, oracle):
     print("case c2 fp64 n=3001 seed 9", flush=True)
     img, st, ref, rst, m2 = _render_both(M, oracle, s, "fp64")
     # the middle camera row/column sits on voxel faces (x or y = 0.64 km):
-    # zero-length end voxels are decided by rounding there
-    assert abs(st["vox_conn"] - rst["vox_conn"]) <= 2 * rst["le_jobs"]
+    # zero-length end voxels are decided by rounding there (measured +0.11%,
+    # 0.09 voxels per ray)
+    assert abs(st["vox_conn"] - rst["vox_conn"]) <= min(2 * rst["le_jobs"], 3e-3 * rst["vox_conn"])
     st.pop("vox_conn"), rst.pop("vox_conn")
     assert st == rst
     assert np.allclose(img, ref, rtol=1e-9, atol=1e-13 * np.abs(ref).max())
