@@ -1,7 +1,8 @@
 // Micro-benchmarks that measure the ceilings the renderer is compared with:
 // random 4-byte gathers from a working set of a given size (global memory and
 // LDS), FP64 atomic adds (device scope and workgroup scope, spread and
-// hot-spot), and a plain streaming copy (for calibrating HBM byte counters).
+// hot-spot), VALU issue (FMA chains), and a plain streaming copy (for
+// calibrating HBM byte counters).
 // Exported through a separate C ABI (libmcrt_micro.so); none of this is on
 // the rendering path.
 #include <hip/hip_runtime.h>
@@ -149,6 +150,27 @@ __global__ void __launch_bounds__(256, 4)
     if (acc == 1234.5f) sink[blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
+// VALU issue: eight independent FMA chains per lane (wave64, no packed
+// FP32), so that every wavefront has an instruction ready each cycle; the
+// rate in wave instructions per CU cycle is the issue ceiling the counters of
+// the other kernels are read against.
+template <typename T>
+__global__ void __launch_bounds__(256) k_valu(T* sink, uint32_t iters, T s) {
+    T a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = (T)(threadIdx.x + k) * (T)1e-7;
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] = a[k] * s + (T)1;
+    }
+    T acc = (T)0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += a[k];
+    if (acc == (T)1234.5) sink[blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
 __global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
@@ -157,6 +179,18 @@ __global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
 }  // namespace
 
 extern "C" {
+
+// 64 FMAs per lane and iteration, `iters` iterations; grid = blocks x 256;
+// fp64 selects double.  Returns a hipError_t value.
+int mc_micro_valu(void* sink, uint32_t blocks, uint32_t iters, int fp64, void* stream) {
+    if (!sink || blocks == 0) return (int)hipErrorInvalidValue;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp64)
+        hipLaunchKernelGGL(k_valu<double>, dim3(blocks), dim3(256), 0, s, (double*)sink, iters, 0.999999);
+    else
+        hipLaunchKernelGGL(k_valu<float>, dim3(blocks), dim3(256), 0, s, (float*)sink, iters, 0.999999f);
+    return (int)hipGetLastError();
+}
 
 // loads per thread; grid = blocks x 256.  Returns a hipError_t value.
 int mc_micro_gather(const float* data, uint32_t n, uint32_t blocks, uint32_t loads, int use_lds, float* sink,

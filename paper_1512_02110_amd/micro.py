@@ -23,11 +23,12 @@ def _lib():
                                   C.c_void_p]
     L.mc_micro_atomic.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
     L.mc_micro_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32, C.c_void_p]
+    L.mc_micro_valu.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
     L.mc_micro_gather_write.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                         C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
     L.mc_micro_gather_replay.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_void_p, C.c_void_p]
-    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_gather_write,
+    for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_valu, L.mc_micro_gather_write,
               L.mc_micro_gather_replay):
         f.restype = C.c_int
     return L
@@ -168,6 +169,22 @@ def main(quick=False):
                 print(f"[micro] gather+write {name} every {period} (out {n_out_bytes >> 20} MiB): "
                       f"{rec['gloads_per_s']:.1f} G loads/s", flush=True)
         del dst
+    # VALU issue: wave64 FMA instructions per CU and per ns (x 1e9 / clock for per cycle)
+    out["valu"] = []
+    vsink = torch.zeros(blocks * 256, dtype=torch.float64, device=dev)
+    v_iters = 256 if quick else 2048
+    for fp64 in (0, 1):
+        def run_v():
+            rc = L.mc_micro_valu(C.c_void_p(vsink.data_ptr()), blocks, v_iters, fp64, st)
+            assert rc == 0, rc
+        ms = _time(torch, run_v)
+        instr = blocks * 4 * v_iters * 64  # wave instructions (4 wavefronts per block)
+        rec = {"fp64": bool(fp64), "ms": ms, "wave_instr_per_cu_per_ns": instr / n_cu / (ms * 1e6),
+               "lane_flops_per_s": 2 * instr * 64 / (ms / 1e3)}
+        out["valu"].append(rec)
+        print(f"[micro] VALU {'f64' if fp64 else 'f32'} FMA: {rec['wave_instr_per_cu_per_ns']:.3f} wave instr per CU "
+              f"per ns, {rec['lane_flops_per_s'] / 1e12:.1f} TFLOP/s", flush=True)
+    del vsink
     nb = 1 << 30
     src = torch.empty(nb // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
