@@ -490,7 +490,8 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     const int wpb = BLOCK / 64;  // wavefronts per block
     size_t free_b = 0;
     char* pool = nullptr;
-    // per buffer: tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
+    // per buffer: tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw],
+    // slice[nt][binning blocks]
     uint32_t* meta[2] = {nullptr, nullptr};
     unsigned long long* ctr1 = nullptr;  // counters of buffer 1 (buffer 0 uses the caller's)
     DepositItem* ditems = nullptr;
@@ -549,9 +550,8 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
 
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
     for (int b = 0; b < 2; ++b) {
-        CHECK_HIP(lib_alloc((void**)&meta[b],
-                            sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu)),
-                            stream));
+        const size_t meta_words = 3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu);
+        CHECK_HIP(lib_alloc((void**)&meta[b], sizeof(uint32_t) * meta_words, stream));
         CHECK_HIP(hipHostMalloc((void**)&hpin[b], hpin_bytes, hipHostMallocDefault));
         CHECK_HIP(hipEventCreateWithFlags(&counted[b], hipEventDisableTiming));
         CHECK_HIP(hipEventCreateWithFlags(&deposited[b], hipEventDisableTiming));
@@ -758,7 +758,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
     const int wpb = BLOCK / 64;  // wavefronts per block
     size_t free_b = 0;
     char* pool = nullptr;
-    // tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][max_nw]
+    // tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw], slice[nt][binning blocks]
     uint32_t* meta = nullptr;
     DepositItem* ditems = nullptr;
     const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
@@ -800,9 +800,10 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
         CHECK_HIP(hipEventCreate(&b1));
     }
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
-    CHECK_HIP(lib_alloc((void**)&meta,
-                        sizeof(uint32_t) * (3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu)),
-                            stream));
+    {
+        const size_t meta_words = 3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu);
+        CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * meta_words, stream));
+    }
     CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     A.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool);
     A.tp.tile_count = meta;
@@ -966,7 +967,7 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     const size_t rec = sizeof(TapeRec<Real>);
     size_t free_b = 0;
     char* pool = nullptr;
-    uint32_t* meta = nullptr;  // tile_count[nt], bin_start[nt], tile_end[nt], slice[nt][nw]
+    uint32_t* meta = nullptr;  // tile_count[nt], bin_start[nt], tile_end[nt], slice[nt][binning blocks]
     DepositItem* ditems = nullptr;
     const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
     std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
@@ -984,8 +985,10 @@ int run_tape_kept(KArgs<Real> A, int tally, const mc_tape* T, int64_t tape_limit
     CHECK_HIP(hipEventCreate(&b0));
     CHECK_HIP(hipEventCreate(&b1));
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
-    CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * (3 * (size_t)nt + (size_t)nt * bin_blocks_max(T->nw, n_cu)),
-                        stream));
+    {
+        const size_t meta_words = 3 * (size_t)nt + (size_t)nt * bin_blocks_max(T->nw, n_cu);
+        CHECK_HIP(lib_alloc((void**)&meta, sizeof(uint32_t) * meta_words, stream));
+    }
     CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
     CHECK_HIP(hipMemcpyAsync(h_wave.data(), T->wave_count, sizeof(uint32_t) * T->nw, hipMemcpyDeviceToHost,
                              stream));
