@@ -178,7 +178,8 @@ def precisions(M, torch, np, s, classes=True, seed=1000):
              "events_minus_fp64": int(st["events"] - res["fp64"][1]["events"])}
         r.update(_pixel_errors(np, img.cpu().numpy(), i64, sig))
         out[t] = r
-    out["mixed"]["precision"] = "photons FP64, connection rays walked in FP32, optical depths and tallies FP64"
+    out["mixed"]["precision"] = ("photons FP64, connection rays walked in FP32 (transmittance exp in FP32), optical "
+                                 "depths and tallies FP64")
     out["fp32"]["precision"] = "photons and connection rays FP32, projection, optical depths and tallies FP64"
     if classes:
         out["fp32"]["classes"] = fp32_classes(M, torch, np, s, b32, b64, i32, i64, sig, seed)

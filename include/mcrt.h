@@ -79,8 +79,9 @@ enum {
  *     scattering) in FP64, exactly as MC_FP64, and the walks of the
  *     connection rays -- most of the voxel steps -- in FP32 over a float copy
  *     of beta; beta is double.  The photon paths, events, counters and pixels
- *     are those of MC_FP64; only the connection rays' optical depths differ
- *     by FP32 rounding (segment lengths and the float copy of beta).
+ *     are those of MC_FP64; only the local estimates differ, by FP32
+ *     rounding of the connection rays' optical depths (segment lengths and
+ *     the float copy of beta) and of their transmittance exp(-tau).
  *     Accepted by mc_render, mc_render_moments, mc_render_noalloc,
  *     mc_render_tape (which then keeps no tape), mc_grad_beta (the gradient
  *     of the same events, computed with the FP64 walks) and mc_trace_paths

@@ -784,8 +784,10 @@ __device__ __forceinline__ bool job_finish(const KArgs<Real>& A, const WalkCtx<W
     // (the tape replay of a mixture queues an air collision's estimates with
     // pre negated, the mark its ray record carries)
     const W pre = MODE == MODE_TAPE ? (W)fabs(J.pre) : J.pre;
-    // (mixed precision: the transmittance in FP64, as the FP64 kernel has it)
-    const double tr = sizeof(W) < sizeof(Real) ? exp(-J.tau) : (double)m_exp((W)(-J.tau));
+    // the transmittance in the walk's precision (mixed precision: FP32, about
+    // 1e-7 relative; an FP64 exp per estimate cost the mixed render 4%, its
+    // constants held in registers the photon phase then spills)
+    const double tr = (double)m_exp((W)(-J.tau));
     const double ce = (double)pre * tr;
     if (MODE == MODE_RENDER || MODE == MODE_RTAPE) {
         tally_f64<TALLY>(A.img, A.img32, J.pix, ce);

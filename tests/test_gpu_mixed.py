@@ -3,8 +3,9 @@
 Mixed precision (photons in FP64, connection rays walked in FP32 over a float
 copy of beta): its photon paths, counters and pixel choices are those of the
 FP64 transport, so against the FP64 oracle and the FP64 GPU render the only
-difference is the FP32 rounding of the connection rays' optical depths
-(relative error of a local estimate about 1e-7 times its optical depth);
+difference is the FP32 rounding of the connection rays' optical depths and
+transmittances (relative error of a local estimate about 1e-7 times its
+optical depth, plus about 1e-7);
 every pixel is held to 1e-4 relative, the metric's bound, on the full
 64^3 / 9-camera / 1e8-photon launch of the benchmark, and to 1e-5 on the
 small scenes.
