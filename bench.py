@@ -802,6 +802,15 @@ def main():
     if not args.no_fp64:
         out["precision"] = precisions(M, torch, np, s, classes=not args.no_precision_classes)
         print(f"[bench] precisions: {json.dumps(out['precision'])}", flush=True)
+        # the metric's "FP32 vs FP64 at <= 1e-4 error": each reduced-precision
+        # render of the same photons against the FP64 one, pixel by pixel
+        pr = out["precision"]
+        out["vs_fp64_at_1e-4"] = {
+            name: {"kernel_ms": pr[name]["kernel_ms"], "speedup_over_fp64": pr[name]["speedup_over_fp64"],
+                   "frac_pixels_within_1e-4_rel": pr[name]["frac_pixels_within_1e-4_rel"],
+                   "frac_pixels_within_max_1e-4_rel_3sigma": pr[name]["frac_pixels_within_max_1e-4_rel_3sigma"],
+                   "counters_equal_fp64": pr[name]["counters_equal_fp64"]}
+            for name in ("fp32", "mixed")}
     if args.config == "c2":
         out["forward_c1"] = forward_c1(M, np)
     if not args.no_adjoint and args.config == "c2":
