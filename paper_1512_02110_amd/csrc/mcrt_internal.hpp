@@ -52,8 +52,8 @@ struct CamChunk {
 };
 
 // Gradient tape of large grids.  The replay (MODE_TAPE) writes every
-// connection ray with a non-zero gradient weight to its wavefront's slice of
-// the ray tape; a binning pass copies each ray into the bin of every
+// connection ray with a non-zero weight to its wavefront's slice of the ray
+// tape; a binning pass copies each ray into the bin of every
 // gradient tile (at most TILE_VOX voxels) it crosses, and the deposit kernel
 // accumulates each tile's bin in LDS.  A record holds the start of the ray
 // and its pixel (ray tape) or camera (bins); direction and length are
@@ -73,7 +73,7 @@ struct Tape {
     TapeRec<Real>* rec;       // rays: wavefront w owns slots [w rw, (w + 1) rw)
     uint32_t rw;              // ray slots per wavefront
     int w0;                   // first wavefront slice of a binning pass (block b: slice w0 + b)
-    int scale_gw;             // records hold local estimates: weight = gw[pixel] * a
+    int scale_gw;             // records hold C (kept rays, replays): the binning passes take gw[pixel] * a
     uint32_t* wave_count;     // [wavefronts] rays written (more than rw: overflow)
     uint32_t* overflow;       // set when a wavefront ran out of slots
     TapeRec<Real>* brec;      // rays binned by tile
