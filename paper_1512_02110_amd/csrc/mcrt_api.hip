@@ -335,6 +335,12 @@ void tape_tiles(const mc_grid* g, int& shx, int& shy, int& shz) {
 
 constexpr int TAPE_FALLBACK = 1;
 
+// Ray buffers of the overlapped gradient replay (each with a library stream).
+// Three were 1-6% slower than two on the 64^3, 128^3 and 256x256x128
+// workloads: a third replay in flight competes with the other two for the
+// compute units and makes every chunk smaller (more chunks, more tails).
+constexpr int REPLAY_BUFFERS = 2;
+
 // Binning blocks per wavefront slice for a pass over ns slices (at least
 // BIN_BLOCKS_PER_CU blocks per CU where the slices allow), and the most
 // blocks a pass can have with nw slices at most (the slice matrix's columns).
@@ -450,13 +456,13 @@ void set_tape_hint(uint64_t key, double rate) {
 
 // Two library streams per device for the overlapped replay (created once,
 // default priority, kept until the process ends).
-hipStream_t g_rstream[MAX_DEVICES][2] = {};
+hipStream_t g_rstream[MAX_DEVICES][REPLAY_BUFFERS] = {};
 
-bool replay_streams(hipStream_t out[2]) {
+bool replay_streams(hipStream_t out[REPLAY_BUFFERS]) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return false;
     std::lock_guard<std::mutex> lock(g_mu);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < REPLAY_BUFFERS; ++i) {
         if (!g_rstream[dev][i] && hipStreamCreateWithFlags(&g_rstream[dev][i], hipStreamNonBlocking) != hipSuccess) {
             (void)hipGetLastError();
             g_rstream[dev][i] = nullptr;
@@ -467,15 +473,16 @@ bool replay_streams(hipStream_t out[2]) {
     return true;
 }
 
-// The gradient replay of run_tape with two ray buffers, so that the replay
-// of one chunk (on a library stream) overlaps the binning and deposits of
-// the previous one (on the caller's stream) and, above all, the tail of the
-// previous replay: every replay launch ends with a few wavefronts on the
-// last, longest photons, and the next launch's wavefronts fill the compute
-// units they leave.  The tape space holds two ray regions of r_cap slots and
-// the bins (b_cap slots); the split is fixed for the call (from the
-// workload's measured rays per photon when there is one), the chunk sizes
-// adapt to what each counted chunk measured.  A chunk whose rays overflowed
+// The gradient replay of run_tape with REPLAY_BUFFERS ray buffers, so that
+// the replay of a chunk (each buffer on a library stream of its own)
+// overlaps the binning and deposits of an earlier one (on the caller's
+// stream) and, above all, the tail of the previous replay: every replay
+// launch ends with a few wavefronts on the last, longest photons, and the
+// next launch's wavefronts fill the compute units they leave.  The tape
+// space holds the ray regions of r_cap slots and the bins (b_cap slots);
+// the split is fixed for the call (from the workload's measured rays per
+// photon when there is one), the chunk sizes adapt to what each counted
+// chunk measured.  A chunk whose rays overflowed
 // a slice, or with a bin larger than the bin space, goes back to the queue
 // of ranges and is replayed in halves; photon ranges may complete out of
 // order (the gradient is a sum).
@@ -483,7 +490,7 @@ template <typename Real>
 int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_t tape_limit,
                      int max_blocks, int n_cu, unsigned long long* counters, unsigned long long* host_sum,
                      double* t_transport, double* t_tape, hipStream_t stream, uint64_t wkey,
-                     const hipStream_t rs[2]) {
+                     const hipStream_t rs[REPLAY_BUFFERS]) {
     int rc = MC_OK;
     const int nt = A.tp.n_tiles;
     const size_t rec = sizeof(TapeRec<Real>);
@@ -492,25 +499,26 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     char* pool = nullptr;
     // per buffer: tile_count[nt], bin_start[nt], tile_end[nt], overflow, wave_count[max_nw],
     // slice[nt][binning blocks]
-    uint32_t* meta[2] = {nullptr, nullptr};
-    unsigned long long* ctr1 = nullptr;  // counters of buffer 1 (buffer 0 uses the caller's)
+    uint32_t* meta[REPLAY_BUFFERS] = {};
+    unsigned long long* ctr1 = nullptr;  // counters of buffers 1.. (buffer 0 uses the caller's)
     DepositItem* ditems = nullptr;
     const int max_items = nt + DEP_ITEMS_PER_CU * n_cu + 1;
     std::vector<uint32_t> h_count(nt), h_bins(2 * (size_t)nt);
     std::vector<DepositItem> h_items;
     // pinned host copies per buffer: tile counts, overflow flag, wave counts, counters
-    char* hpin[2] = {nullptr, nullptr};
+    char* hpin[REPLAY_BUFFERS] = {};
     size_t hpin_bytes = 0, off_over = 0, off_wave = 0, off_ctr = 0;
-    hipEvent_t ev_start = nullptr, counted[2] = {nullptr, nullptr}, deposited[2] = {nullptr, nullptr};
-    hipEvent_t r0[2] = {nullptr, nullptr}, r1[2] = {nullptr, nullptr};
+    hipEvent_t ev_start = nullptr, counted[REPLAY_BUFFERS] = {}, deposited[REPLAY_BUFFERS] = {};
+    hipEvent_t r0[REPLAY_BUFFERS] = {}, r1[REPLAY_BUFFERS] = {};
     std::vector<hipEvent_t> dep_ev;  // begin, end of every chunk's binning and deposits (timed calls)
     struct Slot {
         bool used = false;
         uint64_t start = 0, n = 0;
         int nw = 0;
     };
-    Slot slot[2];
-    KArgs<Real> ka[2] = {A, A};
+    Slot slot[REPLAY_BUFFERS];
+    KArgs<Real> ka[REPLAY_BUFFERS];
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) ka[b] = A;
     std::vector<std::pair<uint64_t, uint64_t>> pending;  // ranges to replay again, smaller
     std::vector<int> order;                             // buffers in flight, in issue order
     uint64_t P = 0, r_cap = 0, b_cap = 0, next = 0, chunk = 0;
@@ -532,9 +540,9 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
         // slots per photon: a wavefront slice 80% full at the busiest
         // wavefront's rays per photon, four and a half tile crossings per ray
         const double rays = hint > 0.0 ? hint / 0.8 : 80.0, bins = hint > 0.0 ? 4.5 * hint : 288.0;
-        r_cap = (uint64_t)((double)P * rays / (2.0 * rays + bins));
-        r_cap = std::min(std::max(r_cap, P / 16), P / 8 * 3);
-        b_cap = P - 2 * r_cap;
+        r_cap = (uint64_t)((double)P * rays / (REPLAY_BUFFERS * rays + bins));
+        r_cap = std::min(std::max(r_cap, P / 16), P / 4 * 3 / REPLAY_BUFFERS);
+        b_cap = P - REPLAY_BUFFERS * r_cap;
         // at least 64 slots per wavefront (fewer resident blocks if the tape is small)
         if (r_cap < 64 * (uint64_t)max_blocks * wpb) max_blocks = (int)(r_cap / (64 * (uint64_t)wpb));
         if (max_blocks < 1 || b_cap < 64) return TAPE_FALLBACK;
@@ -549,7 +557,7 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     hpin_bytes = off_ctr + sizeof(unsigned long long) * (1 + ST_N);
 
     CHECK_HIP(buf_acquire(BUF_BINS, P * rec, stream, (void**)&pool));
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) {
         const size_t meta_words = 3 * (size_t)nt + 1 + (size_t)max_nw + (size_t)nt * bin_blocks_max(max_nw, n_cu);
         CHECK_HIP(lib_alloc((void**)&meta[b], sizeof(uint32_t) * meta_words, stream));
         CHECK_HIP(hipHostMalloc((void**)&hpin[b], hpin_bytes, hipHostMallocDefault));
@@ -560,19 +568,19 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
             CHECK_HIP(hipEventCreate(&r1[b]));
         }
     }
-    CHECK_HIP(lib_alloc((void**)&ctr1, sizeof(unsigned long long) * (1 + ST_N), stream));
+    CHECK_HIP(lib_alloc((void**)&ctr1, sizeof(unsigned long long) * (REPLAY_BUFFERS - 1) * (1 + ST_N), stream));
     CHECK_HIP(lib_alloc((void**)&ditems, sizeof(DepositItem) * max_items, stream));
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) {
         KArgs<Real>& a = ka[b];
         a.tp.rec = reinterpret_cast<TapeRec<Real>*>(pool) + (size_t)b * r_cap;
-        a.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + 2 * r_cap;
+        a.tp.brec = reinterpret_cast<TapeRec<Real>*>(pool) + REPLAY_BUFFERS * r_cap;
         a.tp.tile_count = meta[b];
         a.tp.bin_start = meta[b] + nt;
         a.tp.tile_end = meta[b] + 2 * nt;
         a.tp.overflow = meta[b] + 3 * nt;
         a.tp.wave_count = meta[b] + 3 * nt + 1;
         a.tp.slice = meta[b] + 3 * nt + 1 + max_nw;
-        a.work = b == 0 ? counters : ctr1;
+        a.work = b == 0 ? counters : ctr1 + (size_t)(b - 1) * (1 + ST_N);
         a.stats = a.work + 1;
         a.tp.scale_gw = 1;  // the replay writes C, the binning passes multiply by gw[pixel]
     }
@@ -580,7 +588,7 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
     // tape space's previous users, the allocations above)
     CHECK_HIP(hipEventCreateWithFlags(&ev_start, hipEventDisableTiming));
     CHECK_HIP(hipEventRecord(ev_start, stream));
-    for (int b = 0; b < 2; ++b) CHECK_HIP(hipStreamWaitEvent(rs[b], ev_start, 0));
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) CHECK_HIP(hipStreamWaitEvent(rs[b], ev_start, 0));
 
     {
 #define TRY_HIP(expr)                          \
@@ -642,8 +650,7 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
             return hipSuccess;
         };
 #undef TRY_HIP
-        CHECK_HIP(issue(0));
-        CHECK_HIP(issue(1));
+        for (int b = 0; b < REPLAY_BUFFERS; ++b) CHECK_HIP(issue(b));
         while (!order.empty()) {
             const int b = order.front();
             order.erase(order.begin());
@@ -716,11 +723,15 @@ int run_tape_overlap(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0
 
 done:
     // nothing may still run on the replay streams when the buffers are released
-    for (int b = 0; b < 2; ++b) (void)hipStreamSynchronize(rs[b]);
-    for (void* p : {(void*)ditems, (void*)ctr1, (void*)meta[0], (void*)meta[1]}) {
-        if (!p) continue;
-        hipError_t e = hipFreeAsync(p, stream);
-        if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) (void)hipStreamSynchronize(rs[b]);
+    {
+        std::vector<void*> bufs = {(void*)ditems, (void*)ctr1};
+        for (int b = 0; b < REPLAY_BUFFERS; ++b) bufs.push_back((void*)meta[b]);
+        for (void* p : bufs) {
+            if (!p) continue;
+            hipError_t e = hipFreeAsync(p, stream);
+            if (rc == MC_OK && e != hipSuccess) rc = map_err(e);
+        }
     }
     if (pool) {
         int dev = 0;
@@ -729,10 +740,12 @@ done:
     }
     // the host arrays above were sources or targets of asynchronous copies
     (void)hipStreamSynchronize(stream);
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < REPLAY_BUFFERS; ++b) {
         if (hpin[b]) (void)hipHostFree(hpin[b]);
-    for (hipEvent_t e : {ev_start, counted[0], counted[1], deposited[0], deposited[1], r0[0], r0[1], r1[0], r1[1]})
-        if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {counted[b], deposited[b], r0[b], r1[b]})
+            if (e) (void)hipEventDestroy(e);
+    }
+    if (ev_start) (void)hipEventDestroy(ev_start);
     for (hipEvent_t e : dep_ev)
         if (e) (void)hipEventDestroy(e);
     return rc;
@@ -743,7 +756,7 @@ int run_tape(KArgs<Real> A, int tally, uint64_t n_photons, uint64_t pid0, int64_
              int n_cu, unsigned long long* counters, unsigned long long* host_sum, double* t_transport,
              double* t_tape, hipStream_t stream, uint64_t wkey, const MixPath* mp = nullptr) {
     if (!mp) {
-        hipStream_t rs[2];
+        hipStream_t rs[REPLAY_BUFFERS];
         if (replay_streams(rs))
             return run_tape_overlap<Real>(A, tally, n_photons, pid0, tape_limit, max_blocks, n_cu, counters,
                                           host_sum, t_transport, t_tape, stream, wkey, rs);
