@@ -806,7 +806,8 @@ def main():
         # render of the same photons against the FP64 one, pixel by pixel
         pr = out["precision"]
         out["vs_fp64_at_1e-4"] = {
-            name: {"kernel_ms": pr[name]["kernel_ms"], "speedup_over_fp64": pr[name]["speedup_over_fp64"],
+            name: {"kernel_ms": pr[name]["kernel_ms"], "events_per_s": pr[name]["events_per_s"],
+                   "speedup_over_fp64": pr[name]["speedup_over_fp64"],
                    "frac_pixels_within_1e-4_rel": pr[name]["frac_pixels_within_1e-4_rel"],
                    "frac_pixels_within_max_1e-4_rel_3sigma": pr[name]["frac_pixels_within_max_1e-4_rel_3sigma"],
                    "counters_equal_fp64": pr[name]["counters_equal_fp64"]}
