@@ -50,6 +50,11 @@
  *     (uniforms: polar, azimuth, roulette, free path).  A uniform is
  *     ((word >> 9) + 1/2) * 2^-23.  The same (seed, photon id) gives the same
  *     photon on every run, device and precision, up to rounding.
+ *   - Environment: MC_PLAIN_WALK_LOADS=1 (read at every call) makes the
+ *     connection walks read beta with plain loads, the path that grids too
+ *     large for the walks' buffer (n_vox times the walk's element size of
+ *     2^31 bytes or more) always take; results are the same up to the order
+ *     of the FP64 atomic sums.  Meant for testing that path on small grids.
  */
 #ifndef MCRT_H
 #define MCRT_H
@@ -454,14 +459,16 @@ int mc_trace_paths(const mc_grid* grid, const void* beta, int n_cams, const mc_c
  * of 4; the launch may use fewer: *n_waves, host, gets the number), in which
  * wavefront w also stores, for its connection-walk steps first_step ..
  * first_step + n_steps - 1, the index into the library's copy of beta that
- * each of its 64 lanes loads on that step (lanes with no ray, or in an empty
- * run of voxels, load the zero word after the last voxel, index nx*ny*nz):
+ * each of its 64 lanes asks for on that step (lanes with no ray, or in an
+ * empty run of voxels, ask for index nx*ny*nz, which the walk's buffer
+ * answers with zero and no memory access):
  * indices (device, max_waves * n_steps * 64 uint32) at
  * [(w * n_steps + step) * 64 + lane], left untouched where a wavefront took
  * fewer steps; wave_steps (device, max_waves uint32) gets each wavefront's
  * number of steps.  For measuring the walk's gathers against a replay of the
  * same addresses without the walk.  Waits for the stream when stats is
- * non-NULL. */
+ * non-NULL.  MC_ERR_INVALID_ARG for grids whose walks take plain loads
+ * (see MC_PLAIN_WALK_LOADS above). */
 int mc_capture_gathers(const mc_grid* grid, const float* beta, int n_cams, const mc_camera* cams,
                        const mc_params* params, double* images, uint32_t first_step, uint32_t n_steps,
                        uint32_t max_waves, uint32_t* indices, uint32_t* wave_steps, uint32_t* n_waves,

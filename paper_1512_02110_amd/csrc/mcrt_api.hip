@@ -3,6 +3,7 @@
 // contract of every entry point.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -130,6 +131,13 @@ struct Scratch {
 };
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// MC_PLAIN_WALK_LOADS=1: connection walks use plain loads whatever the grid's
+// size (the path of grids too large for a buffer, testable on small ones)
+bool plain_walk_loads() {
+    const char* v = std::getenv("MC_PLAIN_WALK_LOADS");
+    return v && v[0] == '1';
+}
 
 // An air + aerosol mixture: device fields of the reference channel and the
 // channel's aerosol cross-section ratio (Eq. channelBeta).
@@ -1377,6 +1385,11 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
     A.n_vox = n_vox;
     A.msh = msh;
     A.mask_words = (int)mask_words;
+    // the walks' buffer spans the voxels in the walk's precision: its byte
+    // range stays below 2^31; larger grids (and MC_PLAIN_WALK_LOADS=1) take
+    // plain loads
+    A.walk_buf = (uint64_t)n_vox * (A.walk32 ? sizeof(float) : sizeof(Real)) < ((uint64_t)1 << 31) &&
+                 !plain_walk_loads();
     {
         const bool lds_fits =
             ((mask_words + 1) & ~(int64_t)1) * 4 + n_vox * (int64_t)sizeof(double) <= GRAD_LDS_BYTES;
@@ -1653,7 +1666,8 @@ int run(int mode, const mc_grid* grid, const void* beta, int n_cams, const mc_ca
                 A.capture_steps = cap->steps;
                 A.cap_first = cap->first;
                 A.cap_steps = cap->n_steps;
-                if (grid_blocks < 1) {
+                // (the capture kernel walks through the buffer only)
+                if (grid_blocks < 1 || !A.walk_buf) {
                     rc = MC_ERR_INVALID_ARG;
                     goto done;
                 }

@@ -106,6 +106,7 @@ struct KArgs {
     int walk32;
     const float* beta_w32;
     DevGrid<float> G32;
+    int walk_buf;               // connection walks fetch through a buffer over the voxels
     const DevCam<Real>* cams;
     int n_cams;
     Real wsx, wsy, wsz;     // sun propagation direction

@@ -273,12 +273,28 @@ __device__ __forceinline__ Real beta_at(const KArgs<Real>& A, const uint32_t* ma
     return A.beta[k];
 }
 
+// Structured buffer loads (element index times the descriptor's stride): an
+// index at or past the descriptor's record count returns zero and makes no
+// memory access.
+__device__ float buf_load_f32(__amdgpu_buffer_rsrc_t rsrc, int index, int offset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.ptr.buffer.load.f32");
+__device__ double buf_load_f64(__amdgpu_buffer_rsrc_t rsrc, int index, int offset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.ptr.buffer.load.f64");
+
 // What the walk of a connection ray reads: the extinction it walks (the
 // library's copy of beta followed by zeros and, for a mixture, the air
 // column), the grid, both in the walk's precision W, and the occupancy
 // bitmask's run shift.  W is the transport precision, except in mixed
 // precision (photon state in FP64), where the connection rays walk a float
 // copy of beta on the grid in float.
+//
+// The render's and the tape's walks fetch through `rs`, a buffer over the
+// n_vox voxels only: a lane whose ray has ended or which is in an empty run
+// asks for index n_vox and gets zero without a memory access (with a plain
+// load every such lane reads the shared zero word, about a quarter of the
+// vector-memory accesses of the render).  The kernels whose walks read an air
+// column (AIRZ) use plain loads; the host also launches those, with the air
+// column at the zero word, for grids too large for a buffer.
 template <typename W>
 struct WalkCtx {
     const W* beta;
@@ -286,6 +302,7 @@ struct WalkCtx {
     uint32_t n_vox;
     int msh;
     uint32_t air_base, air_step;
+    __amdgpu_buffer_rsrc_t rs;
     // where a voxel of an empty run in layer iz reads its extinction
     __device__ __forceinline__ uint32_t empty(int iz) const { return air_base + (uint32_t)iz * air_step; }
     __device__ __forceinline__ bool occ(const uint32_t* mask, int k) const {
@@ -296,6 +313,17 @@ struct WalkCtx {
     // the loaded register can stay in flight across a step without a select
     __device__ __forceinline__ W load(const uint32_t* mask, int k, int iz) const {
         return beta[occ(mask, k) ? (uint32_t)k : empty(iz)];
+    }
+    // the extinction at index i <= n_vox: through the buffer (BUF) or a plain load
+    template <bool BUF>
+    __device__ __forceinline__ W fetch(uint32_t i) const {
+        if constexpr (!BUF) {
+            return beta[i];
+        } else if constexpr (sizeof(W) == 4) {
+            return buf_load_f32(rs, (int)i, 0, 0, 0);
+        } else {
+            return buf_load_f64(rs, (int)i, 0, 0, 0);
+        }
     }
 };
 
@@ -319,6 +347,9 @@ __device__ __forceinline__ WalkCtx<typename WalkPrec<Real, W32>::type> walk_ctx(
         C.G = A.G;
     }
     C.n_vox = (uint32_t)A.n_vox;
+    // stride sizeof(W), n_vox records; the last dword sets the 32-bit data
+    // format that untyped buffer loads of CDNA expect
+    C.rs = __builtin_amdgcn_make_buffer_rsrc((void*)C.beta, (short)sizeof(C.beta[0]), (int)C.n_vox, 0x00020000);
     C.msh = A.msh;
     C.air_base = A.air_base;
     C.air_step = A.air_step;
@@ -662,8 +693,8 @@ struct Job {
     Real f0x, f0y, f0z, vx, vy, vz;
 };
 
-// Step n (n mod 3 = PH) of a walk without a second phase; returns true when
-// the ray is done.  The whole wavefront steps together (no branch around
+// Step n (n mod 3 = PH) of a walk without a second phase; returns the
+// wavefront's mask of the lanes whose ray ends at this step.  The whole wavefront steps together (no branch around
 // the step, so that the compiler can count the fetches in flight and wait
 // for the oldest only): a lane whose ray is done keeps stepping with its end
 // clipped to where it stopped, i.e. with zero lengths and fetches of the
@@ -673,17 +704,21 @@ struct Job {
 // (the bit-field extract reads the low 5 bits of its offset).
 //
 // AIRZ: the empty runs read the air column by layer (a mixture whose air
-// depends on the height only), so the walk tracks its layer.
+// depends on the height only), so the walk tracks its layer, and fetches
+// with plain loads (the air column lies past the walk's buffer); otherwise
+// the fetches go through the buffer.
 template <typename Real, int PH, bool AIRZ>
-__device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t* mask, uint32_t msh5, Job<Real>& J,
-                                          uint32_t& ld) {
+__device__ __forceinline__ unsigned long long job_step3(const WalkCtx<Real>& C, const uint32_t* mask, uint32_t msh5,
+                                                        Job<Real>& J, uint32_t& ld) {
     Real& bo = PH == 0 ? J.b1 : (PH == 1 ? J.b2 : J.b0);  // slot n - 2, i.e. n + 1
     Real& Lo = PH == 0 ? J.L1 : (PH == 1 ? J.L2 : J.L0);
     Real& Ln = PH == 0 ? J.L0 : (PH == 1 ? J.L1 : J.L2);  // slot n
     ConnWalk<Real>& W = J.W;
-    const bool cx = (W.tx <= W.ty) && (W.tx <= W.tz);
-    const bool cy = !cx && (W.ty <= W.tz);
+    // the axis that crosses first (x, then y on ties): the minimum is one of
+    // the three values exactly
     const Real tn = fmin(W.tx, fmin(W.ty, W.tz));
+    const bool cx = W.tx == tn;
+    const bool cy = !cx && W.ty == tn;
     const bool last = tn >= J.r;
     const Real tend = last ? J.r : tn;
     J.tau += (double)bo * (double)Lo;
@@ -698,14 +733,17 @@ __device__ __forceinline__ bool job_step3(const WalkCtx<Real>& C, const uint32_t
     W.tx = W.rx * W.gx;
     W.ty = W.ry * W.gy;
     W.tz = W.rz * W.gz;
-    const bool done = last || (uint32_t)W.k >= C.n_vox;
+    const bool past = (uint32_t)W.k >= C.n_vox;
+    const bool done = last || past;
     J.r = done ? tend : J.r;
     // branch free: voxel 0 is a valid index to test when the ray is done
     const uint32_t kk = done ? 0u : (uint32_t)W.k;
     const bool occ = __builtin_amdgcn_ubfe(mask[kk >> msh5], kk >> C.msh, 1u) != 0u;
     ld = AIRZ ? (done ? C.n_vox : (occ ? kk : C.empty(W.iz))) : ((done || !occ) ? C.n_vox : kk);
-    bo = C.beta[ld];
-    return done;
+    bo = C.template fetch<!AIRZ>(ld);
+    // (a ballot of each test is that compare's own lane mask; one of their
+    // OR would go through a vector register)
+    return __builtin_amdgcn_ballot_w64(last) | __builtin_amdgcn_ballot_w64(past);
 }
 
 template <typename Real>
@@ -917,9 +955,11 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C,
                 }
             }
         } else {
-            // voxel steps are counted per wavefront: the busy lanes of each step
+            // voxel steps are counted per wavefront: the busy lanes of each
+            // step.  The busy and finished lanes are kept as wavefront masks
+            // (scalar registers), updated from each step's mask of ended rays
             const uint32_t msh5 = (uint32_t)C.msh + 5u;
-            bool b = busy, f = fin;  // (local copies stay lane masks)
+            unsigned long long bm = __ballot(busy), fm = __ballot(fin);
             auto capture = [&](uint32_t ld) {
                 if constexpr (CAP) {
                     const uint32_t j = wstep - A.cap_first;
@@ -929,26 +969,26 @@ __device__ __forceinline__ void drain(const KArgs<Real>& A, const WalkCtx<W>& C,
             };
             for (;;) {
                 uint32_t ld0, ld1, ld2;
-                const uint32_t n0 = (uint32_t)__popcll(__ballot(b));
+                const uint32_t n0 = (uint32_t)__popcll(bm);
                 if (n0 <= keep) break;
-                const bool d0 = job_step3<W, 0, AIRZ>(C, mask, msh5, J, ld0);
+                const unsigned long long m0 = job_step3<W, 0, AIRZ>(C, mask, msh5, J, ld0);
                 capture(ld0);
-                f = f || (b && d0);
-                b = b && !d0;
-                const uint32_t n1 = (uint32_t)__popcll(__ballot(b));
-                const bool d1 = job_step3<W, 1, AIRZ>(C, mask, msh5, J, ld1);
+                fm |= bm & m0;
+                bm &= ~m0;
+                const uint32_t n1 = (uint32_t)__popcll(bm);
+                const unsigned long long m1 = job_step3<W, 1, AIRZ>(C, mask, msh5, J, ld1);
                 capture(ld1);
-                f = f || (b && d1);
-                b = b && !d1;
-                const uint32_t n2 = (uint32_t)__popcll(__ballot(b));
-                const bool d2 = job_step3<W, 2, AIRZ>(C, mask, msh5, J, ld2);
+                fm |= bm & m1;
+                bm &= ~m1;
+                const uint32_t n2 = (uint32_t)__popcll(bm);
+                const unsigned long long m2 = job_step3<W, 2, AIRZ>(C, mask, msh5, J, ld2);
                 capture(ld2);
-                f = f || (b && d2);
-                b = b && !d2;
+                fm |= bm & m2;
+                bm &= ~m2;
                 vconn_w += n0 + n1 + n2;
             }
-            busy = b;
-            fin = f;
+            busy = ((bm >> __lane_id()) & 1ull) != 0ull;
+            fin = ((fm >> __lane_id()) & 1ull) != 0ull;
         }
     }
 }
@@ -2177,14 +2217,26 @@ hipError_t launch_mix_path(const KArgs<Real>& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The connection walks read beta with plain loads (the AIRZ kernels) when
+// empty runs read an air column, or when the voxels exceed the range of the
+// walks' buffer (then air_step = 0: the air column is the zero word).
+template <typename Real>
+static bool plain_walk(const KArgs<Real>& a) {
+    return a.air_step != 0 || !a.walk_buf;
+}
+
 template <typename Real>
 hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid, hipStream_t s) {
+    const bool plain = plain_walk(a);
     if constexpr (sizeof(Real) == 8) {
+        if (mode == MODE_RENDER && a.walk32 && plain)
+            return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, true, true>(a, grid, s)
+                                      : launch_r<Real, MODE_RENDER, TALLY_K32, true, true>(a, grid, s);
         if (mode == MODE_RENDER && a.walk32)
             return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, false, true>(a, grid, s)
                                       : launch_r<Real, MODE_RENDER, TALLY_K32, false, true>(a, grid, s);
     }
-    if (mode == MODE_RENDER && a.air_step) {
+    if (mode == MODE_RENDER && plain) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RENDER, TALLY_F64, true>(a, grid, s)
                                   : launch_r<Real, MODE_RENDER, TALLY_K32, true>(a, grid, s);
     }
@@ -2197,8 +2249,12 @@ hipError_t launch_transport(const KArgs<Real>& a, int mode, int tally, int grid,
                                   : launch_r<Real, MODE_GRAD, TALLY_K32>(a, grid, s);
     }
     if (mode == MODE_TAPE)
-        return a.air_step ? launch_r<Real, MODE_TAPE, TALLY_F64, true>(a, grid, s)
-                          : launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
+        return plain ? launch_r<Real, MODE_TAPE, TALLY_F64, true>(a, grid, s)
+                     : launch_r<Real, MODE_TAPE, TALLY_F64>(a, grid, s);
+    if (mode == MODE_RTAPE && plain) {
+        return tally == TALLY_F64 ? launch_r<Real, MODE_RTAPE, TALLY_F64, true>(a, grid, s)
+                                  : launch_r<Real, MODE_RTAPE, TALLY_K32, true>(a, grid, s);
+    }
     if (mode == MODE_RTAPE) {
         return tally == TALLY_F64 ? launch_r<Real, MODE_RTAPE, TALLY_F64>(a, grid, s)
                                   : launch_r<Real, MODE_RTAPE, TALLY_K32>(a, grid, s);
@@ -2224,12 +2280,16 @@ static hipError_t occ_r(const KArgs<Real>& a, int* b) {
 
 template <typename Real>
 hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b) {
+    const bool plain = plain_walk(a);
     if constexpr (sizeof(Real) == 8) {
+        if (mode == MODE_RENDER && a.walk32 && plain)
+            return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, true, true>(a, b)
+                                      : occ_r<Real, MODE_RENDER, TALLY_K32, true, true>(a, b);
         if (mode == MODE_RENDER && a.walk32)
             return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, false, true>(a, b)
                                       : occ_r<Real, MODE_RENDER, TALLY_K32, false, true>(a, b);
     }
-    if (mode == MODE_RENDER && a.air_step)
+    if (mode == MODE_RENDER && plain)
         return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64, true>(a, b)
                                   : occ_r<Real, MODE_RENDER, TALLY_K32, true>(a, b);
     if (mode == MODE_RENDER) return tally == TALLY_F64 ? occ_r<Real, MODE_RENDER, TALLY_F64>(a, b)
@@ -2237,7 +2297,10 @@ hipError_t transport_occupancy(const KArgs<Real>& a, int mode, int tally, int* b
     if (mode == MODE_GRAD) return tally == TALLY_F64 ? occ_r<Real, MODE_GRAD, TALLY_F64>(a, b)
                                                      : occ_r<Real, MODE_GRAD, TALLY_K32>(a, b);
     if (mode == MODE_TAPE)
-        return a.air_step ? occ_r<Real, MODE_TAPE, TALLY_F64, true>(a, b) : occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
+        return plain ? occ_r<Real, MODE_TAPE, TALLY_F64, true>(a, b) : occ_r<Real, MODE_TAPE, TALLY_F64>(a, b);
+    if (mode == MODE_RTAPE && plain)
+        return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64, true>(a, b)
+                                  : occ_r<Real, MODE_RTAPE, TALLY_K32, true>(a, b);
     if (mode == MODE_RTAPE) return tally == TALLY_F64 ? occ_r<Real, MODE_RTAPE, TALLY_F64>(a, b)
                                                       : occ_r<Real, MODE_RTAPE, TALLY_K32>(a, b);
     if (mode == MODE_VOXEL) return occ_r<Real, MODE_VOXEL, TALLY_F64>(a, b);

@@ -119,17 +119,26 @@ __global__ void k_gather_write(const float* __restrict__ data, uint32_t n, uint3
     if (acc == 1234.5f) sink[tid] = acc;
 }
 
+// A structured buffer load (element index times the descriptor's stride):
+// an index at or past the record count returns zero with no memory access.
+__device__ float buf_load_f32(__amdgpu_buffer_rsrc_t rsrc, int index, int offset, int soffset, int aux) __asm(
+    "llvm.amdgcn.struct.ptr.buffer.load.f32");
+
 // Replay of captured gather addresses (the walk's own address stream):
 // wavefront w loads, lane by lane, the NS indices that captured wavefront w
 // of the render loaded on NS consecutive walk steps (idx[(w NS + j) 64 +
-// lane], clamped into data) and gathers data at them, `reps` times over.
-// No walk arithmetic, and no load depends on another: the loads issue as
-// fast as the vector-memory pipeline takes them, so the rate bounds what the
-// walk can reach on the same addresses with the same wavefronts per CU.
+// lane], clamped into data) and gathers data at them, `reps` times over, the
+// way the render's walk loads them: through a buffer over the n_vox voxels,
+// so that the indices past them (rays that have ended, empty runs) return
+// zero without a memory access.  No walk arithmetic, and no load depends on
+// another: the loads issue as fast as the vector-memory pipeline takes them,
+// so the rate bounds what the walk can reach on the same addresses with the
+// same wavefronts per CU.
 template <int NS>
 __global__ void __launch_bounds__(256, 4)
-    k_gather_replay(const float* __restrict__ data, uint32_t n, const uint32_t* __restrict__ idx, uint32_t reps,
-                    float* sink) {
+    k_gather_replay(const float* __restrict__ data, uint32_t n, uint32_t n_vox, const uint32_t* __restrict__ idx,
+                    uint32_t reps, float* sink) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)data, (short)4, (int)n_vox, 0x00020000);
     const size_t w = (size_t)blockIdx.x * 4 + threadIdx.x / 64;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t r[NS];
@@ -143,7 +152,7 @@ __global__ void __launch_bounds__(256, 4)
         asm volatile("" : "+s"(z));
         float v[NS];
 #pragma unroll
-        for (int j = 0; j < NS; ++j) v[j] = data[r[j] + z];
+        for (int j = 0; j < NS; ++j) v[j] = buf_load_f32(rs, (int)(r[j] + z), 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < NS; ++j) acc += v[j];
     }
@@ -242,15 +251,17 @@ int mc_micro_gather_write(const float* data, uint32_t n, uint32_t blocks, uint32
 }
 
 // Replay of n_waves captured wavefronts of n_steps (32 or 48) walk steps
-// each: blocks of 4 wavefronts; indices are clamped into [0, n).
-int mc_micro_gather_replay(const float* data, uint32_t n, const uint32_t* idx, uint32_t n_waves, uint32_t n_steps,
-                           uint32_t reps, float* sink, void* stream) {
-    if (!data || n == 0 || !idx || !sink || n_waves < 4 || n_waves % 4 != 0) return (int)hipErrorInvalidValue;
+// each: blocks of 4 wavefronts; indices are clamped into [0, n), and those
+// at or past n_vox (<= n) read zero without an access.
+int mc_micro_gather_replay(const float* data, uint32_t n, uint32_t n_vox, const uint32_t* idx, uint32_t n_waves,
+                           uint32_t n_steps, uint32_t reps, float* sink, void* stream) {
+    if (!data || n == 0 || n_vox > n || n_vox > 0x7fffffffu || !idx || !sink || n_waves < 4 || n_waves % 4 != 0)
+        return (int)hipErrorInvalidValue;
     hipStream_t s = (hipStream_t)stream;
     if (n_steps == 32)
-        hipLaunchKernelGGL(k_gather_replay<32>, dim3(n_waves / 4), dim3(256), 0, s, data, n, idx, reps, sink);
+        hipLaunchKernelGGL(k_gather_replay<32>, dim3(n_waves / 4), dim3(256), 0, s, data, n, n_vox, idx, reps, sink);
     else if (n_steps == 48)
-        hipLaunchKernelGGL(k_gather_replay<48>, dim3(n_waves / 4), dim3(256), 0, s, data, n, idx, reps, sink);
+        hipLaunchKernelGGL(k_gather_replay<48>, dim3(n_waves / 4), dim3(256), 0, s, data, n, n_vox, idx, reps, sink);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

@@ -26,8 +26,8 @@ def _lib():
     L.mc_micro_valu.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_int, C.c_void_p]
     L.mc_micro_gather_write.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                         C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
-    L.mc_micro_gather_replay.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32,
-                                         C.c_void_p, C.c_void_p]
+    L.mc_micro_gather_replay.argtypes = [C.c_void_p, C.c_uint32, C.c_uint32, C.c_void_p, C.c_uint32, C.c_uint32,
+                                         C.c_uint32, C.c_void_p, C.c_void_p]
     for f in (L.mc_micro_gather, L.mc_micro_atomic, L.mc_micro_copy, L.mc_micro_valu, L.mc_micro_gather_write,
               L.mc_micro_gather_replay):
         f.restype = C.c_int
@@ -42,8 +42,9 @@ def gather_ceiling(s, n_photons, first_step=2000, n_steps=48, reps=20, seed=1000
     walk arithmetic, `reps` times over (the rate the vector-memory pipeline
     sustains on this address stream and working set).  The render's own rate
     comes from a plain render of the same photons: loads issued by its walks
-    (64 per wavefront step, the idle lanes' loads of the zero word included)
-    plus its free-flight loads, per second of kernel time."""
+    (64 per wavefront step, counting the lanes that read zero without an
+    access: rays that have ended, empty runs) plus its free-flight loads, per
+    second of kernel time."""
     import torch
     from paper_1512_02110_amd import mcrt as M
     L = _lib()
@@ -64,7 +65,8 @@ def gather_ceiling(s, n_photons, first_step=2000, n_steps=48, reps=20, seed=1000
     sink = torch.zeros(nf * 64, dtype=torch.float32, device=dev)
 
     def run():
-        rc = L.mc_micro_gather_replay(C.c_void_p(data.data_ptr()), data.numel(), C.c_void_p(sel.data_ptr()), nf,
+        rc = L.mc_micro_gather_replay(C.c_void_p(data.data_ptr()), data.numel(), beta.numel(),
+                                      C.c_void_p(sel.data_ptr()), nf,
                                       n_steps, reps, C.c_void_p(sink.data_ptr()), st_)
         assert rc == 0, rc
     ms = _time(torch, run)

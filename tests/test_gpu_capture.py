@@ -1,8 +1,9 @@
 """The gather capture (a diagnostic of the FP32 render): the render it runs
 is the plain render (same counters, same images up to the order of the FP64
-tally atomics), and every captured load is either the zero word after the
-last voxel or a voxel whose extinction is not zero; the wavefronts' steps
-account for every connection-ray voxel visit."""
+tally atomics), and every captured index is either n_vox (a lane with no
+ray or in an empty run, which the walk's buffer answers with zero and no
+memory access) or a voxel whose extinction is not zero; the wavefronts'
+steps account for every connection-ray voxel visit."""
 import numpy as np
 import pytest
 
