@@ -738,11 +738,13 @@ def main():
                 "kernel": "k_render<float, MODE_RENDER, TALLY_F64>",
                 "kernel_ms_avg": round(sum(k_ms) / len(k_ms), 3),
                 "algorithmic_bytes_per_launch": gbytes / len(recs),
-                "binding_unit": "the vector-memory gather pipeline (address and data units busy, "
-                                "profiles/k_render_fwd_c2_counters.md)",
+                "binding_unit": "VALU issue (95% of one wave64 instruction per CU cycle, with the gather "
+                                "pipeline's address and data units 88% / 98% busy; on the 128^3 and "
+                                "256x256x128 grids the gathers bind: profiles/k_render_fwd_c2_counters.md, "
+                                "profiles/k_render_fwd_c4_c5_counters.md)",
                 "gather_ceiling": {
                     "what": "loads/s of the render's own connection-walk loads (captured per wavefront and lane) "
-                            "replayed with no walk arithmetic, same wavefronts per CU",
+                            "replayed through the same buffer with no walk arithmetic, same wavefronts per CU",
                     "ceiling_gloads_per_s": round(ceil["replay_gloads_per_s"], 1),
                     "render_issued_gloads_per_s": round(ceil["render_issued_gloads_per_s"], 1),
                     "frac_issued": round(ceil["frac_issued_of_replay"], 4),
