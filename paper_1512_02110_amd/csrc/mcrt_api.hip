@@ -1926,6 +1926,9 @@ int mc_capture_gathers(const mc_grid* grid, const float* beta, int n_cams, const
     if (params->transport != MC_FP32 || params->tally != MC_TALLY_F64) return MC_ERR_INVALID_ARG;
     if (!images || !indices || !wave_steps || !n_waves || n_steps < 1 || max_waves < (uint32_t)(BLOCK / 64))
         return MC_ERR_INVALID_ARG;
+    // the capture kernel walks through the buffer: not for grids that take plain loads
+    if ((int64_t)grid->nx * grid->ny * grid->nz * (int64_t)sizeof(float) >= ((int64_t)1 << 31) || plain_walk_loads())
+        return MC_ERR_INVALID_ARG;
     if ((rc = precheck_device()) != MC_OK) return rc;
     if (!is_device_ptr(beta) || !is_device_ptr(images) || !is_device_ptr(indices) || !is_device_ptr(wave_steps))
         return MC_ERR_INVALID_ARG;

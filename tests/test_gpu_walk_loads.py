@@ -79,3 +79,19 @@ def test_kept_and_replayed_gradients_plain_loads_match_buffer(M, monkeypatch, tr
     _close(k1, k2, 1e-10)
     _close(r1, r2, 1e-10)
     _close(k1, r1, 1e-10)
+
+
+def test_capture_refuses_plain_load_walks(M, monkeypatch):
+    """The gather capture runs the buffer walk only: with plain loads forced
+    it returns MC_ERR_INVALID_ARG, as an argument error, before enqueueing
+    anything."""
+    s = scenes.config2(n_photons=10_000)
+    print("case gather capture with plain walk loads forced: rejected", flush=True)
+    b = M.beta_tensor(s, "fp32")
+    monkeypatch.setenv("MC_PLAIN_WALK_LOADS", "1")
+    with pytest.raises(M.McError) as e:
+        M.mc_capture_gathers(s, b, 0, 8, 64)
+    assert e.value.code == M.MC_ERR_INVALID_ARG
+    monkeypatch.delenv("MC_PLAIN_WALK_LOADS")
+    idx, steps, nw, st = M.mc_capture_gathers(s, b, 0, 8, 64)
+    assert st["photons"] == s.n_photons and nw > 0
